@@ -1,0 +1,214 @@
+/*
+ * vgsim.h -- C ABI of the MI355X (gfx950) voxel-graph diffusion-transformation
+ * library (method of Klai, Monga, Jouini, Pot, arXiv:2406.04177).
+ *
+ * The library simulates five carbon pools on the graph of 6-connected pore
+ * voxels of a binary 3D image: per voxel a transformation step (Sec. II.C,
+ * eq. (3), with the clamps of Appendix A, Algorithm 1) and Fick diffusion
+ * between face-neighbours, explicit (Sec. II.B.3a, Scheme 1) or implicit with
+ * Jacobi-preconditioned conjugate gradients (Sec. II.B.3b, Scheme 2; Sec. III).
+ * It also provides the discrete adjoint of the explicit time loop.
+ *
+ * Conventions (every entry point)
+ *   - Returns VG_OK (0) or a negative VG_E* code; vg_last_error() gives text.
+ *     Nothing throws or exits across the ABI.
+ *   - Pointers named *_d are device pointers owned by the caller; the library
+ *     never allocates, frees or keeps device memory beyond what the caller
+ *     binds.  Host pointers (*_h and descriptor arrays) are read during the
+ *     call only.
+ *   - `stream` is a hipStream_t passed as void* (NULL = legacy default
+ *     stream).  Device work is enqueued asynchronously on it; calls that return
+ *     a host value (vg_count_pores, vg_mass_totals, vg_solve_implicit_step)
+ *     synchronise that stream before returning.
+ *   - A vg_sim handle is not thread-safe; do not use one handle from two host
+ *     threads or two streams at once.
+ *   - Pools are numbered in the paper's order: 0 MB, 1 DOM, 2 SOM, 3 FOM
+ *     (called P4 here), 4 CO2.  Fields are structure-of-arrays: pool s of
+ *     voxel i is at fields[s * n + i].
+ *   - Geometry: masks are uint8 [nz][ny][nx], nonzero = pore (the paper tags
+ *     pore voxels with 0, Sec. II.A).  The linear index of (x, y, z) is
+ *     x + nx * (y + ny * z).
+ */
+#ifndef VGSIM_H
+#define VGSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define VG_OK          0
+#define VG_EINVAL     -1   /* bad argument: null pointer, size, range, shape  */
+#define VG_EUNSTABLE  -2   /* explicit dt above the positivity bound         */
+#define VG_ENOCONV    -3   /* CG stopped at max_iter above rtol              */
+#define VG_ENONFINITE -4   /* a mass total is NaN or infinite                */
+#define VG_EHIP       -5   /* HIP runtime error (text in vg_last_error)      */
+#define VG_ESTATE     -6   /* call out of sequence (e.g. no state bound)     */
+
+/* ---- enumerations ------------------------------------------------------ */
+#define VG_F32 0           /* fields stored and stepped in float32           */
+#define VG_F64 1           /* fields stored and stepped in float64           */
+
+#define VG_PERIODIC_X 1u   /* wrap-around neighbours (tests); default no-flux */
+#define VG_PERIODIC_Y 2u
+#define VG_PERIODIC_Z 4u
+
+#define VG_ORDER_TD 0      /* paper order: transformation, then diffusion    */
+#define VG_ORDER_DT 1      /* diffusion, then transformation                 */
+
+#define VG_FORCE 1u        /* vg_step_explicit: skip the dt stability check  */
+
+#define VG_NPOOL 5
+#define VG_NREG 8          /* region conductance factors: volume octants     */
+#define VG_NGRAD 20        /* gradient vector length, layout below           */
+
+/* Model parameters, SI units.  a_s = D[s] * dt / h^2 is the dimensionless
+ * diffusion number of pool s (voxel units give S_ij = d_ij = 1, Sec. II.B.2).
+ * mort_to_p4 = 0 routes a fraction beta of dead biomass to DOM and 1 - beta to
+ * SOM (Sec. II.C); 1 routes all of it to pool 3. */
+typedef struct vg_params {
+    double D[VG_NPOOL];
+    double h;
+    double v_dom, k_dom, rho, mu, beta, v_som, v_p4;
+    int32_t mort_to_p4;
+    int32_t step_order;   /* VG_ORDER_TD or VG_ORDER_DT */
+} vg_params;
+
+/* ---- errors ------------------------------------------------------------ */
+const char *vg_strerror(int code);
+/* Text of the last error raised on the calling thread ("" if none). */
+const char *vg_last_error(void);
+int vg_version(void);
+
+/* ---- graph construction (Sec. II.A, Fig. 2; Sec. III) -------------------
+ * The pore voxels are enumerated in raster order (x fastest) or, with
+ * brick = b > 0, brick by brick (bricks of b^3 voxels in raster order of
+ * bricks, raster order inside a brick).  The enumeration is held in a "rank
+ * index": one 32-bit pore bitmap word per 32 positions of the enumeration plus
+ * the number of pore voxels before that word.  */
+
+/* Bytes of the rank index for this shape and brick size. */
+int vg_rank_bytes(int nx, int ny, int nz, int brick, size_t *bytes);
+
+/* Builds the rank index of mask_d into rank_d (vg_rank_bytes bytes) and
+ * returns the number of pore voxels in *n_out (host).  Synchronises stream. */
+int vg_count_pores(const uint8_t *mask_d, int nx, int ny, int nz, int brick, void *rank_d,
+                   int64_t *n_out, void *stream);
+
+/* Fills the compacted pore-voxel list and neighbour table of one volume.
+ *   vox_d[i]            linear index of compact voxel i (i < n)
+ *   nbr_d[k * ld + i]   index_base + compact index of the neighbour in slot
+ *                       k = (-x, +x, -y, +y, -z, +z), or -1 when that voxel
+ *                       is solid or outside the box (no-flux faces), unless
+ *                       the axis is in `periodic`.
+ * n must be the count from vg_count_pores; ld >= n is the row stride of the
+ * table (the total voxel count when several volumes share one table). */
+int vg_build_graph(const void *rank_d, int nx, int ny, int nz, int brick, unsigned periodic,
+                   int32_t index_base, int64_t n, int64_t ld, int32_t *vox_d, int32_t *nbr_d,
+                   void *stream);
+
+/* idx_d[q] = index_base + compact index of linear voxel lin_d[q], or -1 if
+ * that voxel is solid or out of range. */
+int vg_lookup(const void *rank_d, int nx, int ny, int nz, int brick, const int64_t *lin_d,
+              int64_t count, int32_t index_base, int32_t *idx_d, void *stream);
+
+/* Region code of every voxel for the region conductance factors: bits 0-2
+ * the octant 4[z >= nz/2] + 2[y >= ny/2] + [x >= nx/2] of the voxel, bit 3+k
+ * set when the neighbour position in slot k lies in another octant.  The
+ * edge weight is w_ij = (c[octant(i)] + c[octant(j)]) / 2 (a generalisation
+ * of the unit conductance S_ij / d_ij = 1 of Sec. II.B.2). */
+int vg_region_codes(const int32_t *vox_d, int64_t n, int nx, int ny, int nz, unsigned periodic,
+                    uint16_t *codes_d, void *stream);
+
+/* ---- simulation handle ------------------------------------------------- */
+typedef struct vg_sim vg_sim;
+
+typedef struct vg_desc {
+    int64_t n;               /* pore voxels over all volumes                 */
+    int32_t nseg;            /* volumes (segments of the compact list)       */
+    int32_t precision;       /* VG_F32 or VG_F64                             */
+    const int64_t *seg_off;  /* host [nseg + 1], seg_off[0] = 0, [nseg] = n  */
+    const int32_t *nbr_d;    /* device [6][n] neighbour table                */
+    const uint16_t *rcode_d; /* device [n] region codes or NULL (weights 1)  */
+    int32_t mobile_all;      /* 0: only DOM may diffuse; 1: any pool may     */
+    int32_t features;        /* bit 0: implicit CG, bit 1: adjoint           */
+} vg_desc;
+
+#define VG_FEAT_CG  1
+#define VG_FEAT_ADJ 2
+
+/* Creates a handle (host memory only) and sets default parameters. */
+int vg_create(const vg_desc *desc, vg_sim **out);
+int vg_destroy(vg_sim *h);
+/* Sets the model parameters (validated: h > 0, K_DOM > 0, rates >= 0,
+ * 0 <= beta <= 1, D >= 0; only D[1] may be nonzero unless mobile_all). */
+int vg_set_params(vg_sim *h, const vg_params *p);
+/* Region conductance factors c[VG_NREG] (> 0); ignored without region codes. */
+int vg_set_regions(vg_sim *h, const double *c);
+
+/* Device memory the caller binds with vg_init_state:
+ *   fields  [5][n] elements of the field type (float or double)
+ *   alt     alt_elems elements of the field type (ping-pong of mobile pools)
+ *   work    workspace_bytes bytes (reduction partials, CG vectors, adjoint
+ *           ping-pong and gradient partials, as enabled by `features`). */
+int vg_alt_elems(const vg_sim *h, int64_t *elems);
+int vg_workspace_bytes(const vg_sim *h, size_t *bytes);
+
+/* Binds the caller's buffers (fields already hold the initial masses) and
+ * uploads the small per-handle tables into the workspace. */
+int vg_init_state(vg_sim *h, void *fields_d, void *alt_d, void *work_d, size_t work_bytes,
+                  void *stream);
+
+/* Advances nsteps time steps of the explicit method (Scheme 1 plus the
+ * transformation, in params.step_order).  If log_every > 0, the totals of the
+ * state after every log_every-th step go to totals_log_d[r][g][0..5]
+ * (r = 0 .. nsteps / log_every - 1; pools 0-4 then total carbon, FP64).
+ * Returns VG_EUNSTABLE, without stepping, when
+ * dt * max_s D_s * 6 * max_r c_r / h^2 > 1, unless flags has VG_FORCE.
+ * On return the bound fields hold the new state. */
+int vg_step_explicit(vg_sim *h, int64_t nsteps, double dt, int64_t log_every,
+                     double *totals_log_d, unsigned flags, void *stream);
+
+/* One implicit step (Scheme 2): the transformation, then for each pool with
+ * D_s > 0 the system (I + a_s L_w) y = x_s solved by Jacobi-preconditioned CG
+ * in FP64 (start y = x_s; stop at ||x_s - B y||_2 <= rtol ||x_s||_2).
+ * iters_h[5] / relres_h[5] (host, may be NULL) receive the iterations and
+ * final relative residual per pool.  Returns VG_ENOCONV if a pool stopped at
+ * max_iter (the state still takes the last iterate).  Synchronises stream. */
+int vg_solve_implicit_step(vg_sim *h, double dt, double rtol, int max_iter, int *iters_h,
+                           double *relres_h, void *stream);
+
+/* Totals of the bound state: out_h[g][0..5] (host), FP64, fixed summation
+ * order.  Returns VG_ENONFINITE if any total is not finite.  Synchronises. */
+int vg_mass_totals(vg_sim *h, double *out_h, void *stream);
+
+/* ---- discrete adjoint of the explicit loop (paper order only) -----------
+ * vg_record advances nsteps steps from the bound state x^k0 and writes what
+ * the reverse sweep needs to states_d ([nsteps][5][n], field type):
+ * states[0] = x^k0 and states[j] = T(x^(k0+j-1)) for j >= 1 (the state
+ * after the transformation half of step k0+j-1).  The bound fields are left
+ * at x^k0 (the call only reads them).
+ *
+ * vg_adjoint runs the reverse sweep over those nsteps steps.
+ *   lambda_d [5][n] (field type): in dL/dx^(k0+nsteps), out dL/dx^k0.
+ *   seeds_d  [nsteps][nseg][5] FP64: dL/dTotal_{g,s} at steps k0..k0+nsteps-1
+ *            (added to lambda after each reverse step; the caller seeds step
+ *            k0+nsteps itself, e.g. with vg_seed_lambda).
+ *   grad_d   [VG_NGRAD] FP64, accumulated (+=):
+ *            [0..4] dL/dD_s, [5] v_DOM, [6] K_DOM, [7] rho, [8] mu, [9] beta,
+ *            [10] v_SOM, [11] v_P4, [12..19] dL/dc_r (zero without regions).
+ * dt must equal the one used for the forward steps. */
+int vg_record(vg_sim *h, int64_t nsteps, double dt, void *states_d, void *stream);
+int vg_adjoint(vg_sim *h, int64_t nsteps, double dt, const void *states_d, const double *seeds_d,
+               void *lambda_d, double *grad_d, void *stream);
+/* lambda_d[s][i] = (zero ? 0 : lambda_d[s][i]) + seed_d[g(i)][s] (seed_d
+ * [nseg][5] FP64 on the device). */
+int vg_seed_lambda(vg_sim *h, const double *seed_d, void *lambda_d, int zero, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VGSIM_H */

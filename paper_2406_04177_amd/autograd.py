@@ -1,0 +1,93 @@
+"""Gradients of losses on mass-total curves through the explicit time loop.
+
+``simulate_totals(sim, theta, x0, nsteps, dt, checkpoint_every)`` returns the
+per-volume pool totals after every step ([nsteps+1, nseg, 5], FP64) as a
+differentiable function of
+
+    theta = [D_0..D_4, v_DOM, K_DOM, rho, mu, beta, v_SOM, v_P4, c_0..c_7]
+
+(diffusion coefficients, kinetic rates, region conductance factors; 20
+values) and of the initial fields ``x0``.  The backward pass is the library's
+hand-written discrete adjoint (``vg_adjoint``) with checkpointed recomputation:
+the forward keeps the state at the start of every ``checkpoint_every`` steps;
+the backward re-records each segment (``vg_record``) and sweeps it in reverse.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import torch
+
+from .inputs import ModelParams
+
+NTHETA = 20
+THETA_NAMES = ("D_MB", "D_DOM", "D_SOM", "D_P4", "D_CO2", "v_dom", "k_dom", "rho", "mu", "beta",
+               "v_som", "v_p4") + tuple("c%d" % r for r in range(8))
+
+
+def theta_of(params: ModelParams, c=None) -> torch.Tensor:
+    c = [1.0] * 8 if c is None else list(c)
+    return torch.tensor(list(params.D) + [params.v_dom, params.k_dom, params.rho, params.mu, params.beta,
+                                          params.v_som, params.v_p4] + c, dtype=torch.float64)
+
+
+def params_of(theta, base: ModelParams) -> tuple:
+    t = [float(v) for v in theta.detach().cpu().tolist()]
+    p = dataclasses.replace(base, D=tuple(t[0:5]), v_dom=t[5], k_dom=t[6], rho=t[7], mu=t[8], beta=t[9],
+                            v_som=t[10], v_p4=t[11])
+    return p, t[12:20]
+
+
+class _TotalsFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, theta, x0, sim, nsteps, dt, K):
+        p, c = params_of(theta, sim.params)
+        sim.set_params(p)
+        sim.set_regions(c)
+        sim.set_fields(x0)
+        nseg = sim.graph.nseg
+        dev = sim.fields.device
+        tot = torch.empty((nsteps + 1, nseg, 6), dtype=torch.float64, device=dev)
+        tot[0] = torch.from_numpy(sim.totals()).to(dev)
+        ckpts = []
+        k0 = 0
+        while k0 < nsteps:
+            k = min(K, nsteps - k0)
+            ckpts.append((k0, k, sim.fields.clone()))
+            sim.step(k, dt, log_every=1, totals_out=tot[k0 + 1:k0 + 1 + k])
+            k0 += k
+        ctx.sim, ctx.dt, ctx.ckpts, ctx.nsteps = sim, dt, ckpts, nsteps
+        ctx.theta_device = theta.device
+        ctx.x0_dtype = x0.dtype
+        return tot[:, :, :5].clone()
+
+    @staticmethod
+    def backward(ctx, gout):
+        sim, dt = ctx.sim, ctx.dt
+        dev = sim.fields.device
+        n = sim.graph.n
+        seeds = gout.detach().to(device=dev, dtype=torch.float64).contiguous()
+        lam = torch.zeros((5, n), dtype=sim.dtype, device=dev)
+        sim.seed_lambda(seeds[ctx.nsteps], lam, zero=True)
+        grad = torch.zeros(NTHETA, dtype=torch.float64, device=dev)
+        kmax = max(k for _, k, _ in ctx.ckpts) if ctx.ckpts else 0
+        states = torch.empty((max(kmax, 1), 5, n), dtype=sim.dtype, device=dev)
+        for k0, k, ck in reversed(ctx.ckpts):
+            sim.set_fields(ck)
+            sim.record(k, dt, states)
+            sim.adjoint(k, dt, states, seeds[k0:k0 + k], lam, grad)
+        return (grad.to(ctx.theta_device), lam.to(ctx.x0_dtype), None, None, None, None)
+
+
+def simulate_totals(sim, theta: torch.Tensor, x0: torch.Tensor, nsteps: int, dt: float,
+                    checkpoint_every: int = 100) -> torch.Tensor:
+    """Differentiable [nsteps+1, nseg, 5] totals; see the module docstring."""
+    if nsteps < 1 or checkpoint_every < 1:
+        raise ValueError("need nsteps >= 1 and checkpoint_every >= 1")
+    return _TotalsFn.apply(theta, x0, sim, int(nsteps), float(dt), int(checkpoint_every))
+
+
+def co2_mse(totals: torch.Tensor, target: torch.Tensor) -> torch.Tensor:
+    """Mean over (step, volume) of (CO2 total - target)^2."""
+    return ((totals[:, :, 4] - target) ** 2).mean()

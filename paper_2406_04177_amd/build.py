@@ -1,0 +1,49 @@
+"""Builds libvgsim.so (the HIP kernels and the C ABI) in-tree for gfx950.
+
+    python -m paper_2406_04177_amd.build        # or: python paper_2406_04177_amd/build.py
+
+hipcc cross-compiles without a GPU.  Flags:
+  --offload-arch=gfx950            MI355X (CDNA4) code object only
+  -ffp-contract=off                no fused multiply-add: every operation rounds
+                                   as written, so the FP64 path reproduces a
+                                   plain IEEE implementation bit for bit
+  -target-feature -packed-fp32-ops no packed FP32 instructions
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libvgsim.so")
+SOURCES = ["vg_graph.hip", "vg_step.hip", "vg_cg.hip", "vg_adjoint.hip", "vg_api.cpp"]
+HEADERS = ["vg_internal.h"]
+
+
+def hipcc() -> str:
+    for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", "hipcc"):
+        if cand and (os.path.isabs(cand) and os.path.exists(cand) or not os.path.isabs(cand)):
+            return cand
+    return "hipcc"
+
+
+def build(verbose: bool = False) -> str:
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = [hipcc(), "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+           "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-Wno-unused-command-line-argument",
+           "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp]
+    cmd += [os.path.join(CSRC, s) for s in SOURCES]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))
+    sys.exit(0)

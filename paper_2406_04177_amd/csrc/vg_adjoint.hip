@@ -1,0 +1,391 @@
+// Discrete adjoint of the explicit time loop in the paper's order
+// (x^(k+1) = D(T(x^k)): transformation of Appendix A Algorithm 1, then
+// Scheme 1 diffusion).  Reverse-mode derivative of exactly the arithmetic of
+// the forward kernels, for a loss on the per-volume pool totals.
+//
+// Forward recording stores, per step of a checkpoint segment, the state the
+// reverse pass needs: x^k0 for the first step and z^(k-1) = T(x^(k-1)) for the
+// others (the fused forward pass produces z; x^k = D(z^(k-1)) is recomputed
+// in the adjoint kernel with the forward's own arithmetic, so the stored
+// bytes per step equal one field set).
+//
+// One reverse step is one fused pass per voxel:
+//   x   = D(z)_i (or the stored x) and u = T(x) locally,
+//   ubar = Q_w lambda (Q_w symmetric, so its transpose is the same gather),
+//   dL/da_s += u_s,i * sum_j w_ij (lambda_j - lambda_i),
+//   dL/dc_r += a_s u_s,i (lambda_j - lambda_i) (1/2 to each endpoint region),
+//   lambda^k = J_T(x)^T ubar + seed,
+// with FP64 per-thread accumulators reduced per block in a fixed order.
+#include "vg_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace vg {
+namespace {
+
+constexpr int kG = VG_NGRAD;
+
+template <typename R>
+__device__ __forceinline__ void transform_fwd(const Coef<R> &C, R &m1, R &m2, R &m3, R &m4, R &m5) {
+    R uptake = C.v_dom * m2 / (C.k_dom + m2) * m1 * C.dt;
+    if (uptake > m2) uptake = m2;
+    R resp = C.rho * m1 * C.dt;
+    R morta = C.mu * m1 * C.dt;
+    if (resp + morta > m1) {
+        if (morta > m1) {
+            morta = m1;
+            resp = R(0);
+        } else {
+            resp = m1 - morta;
+        }
+    }
+    R turn_p4 = C.v_p4 * m4 * C.dt;
+    if (turn_p4 > m4) turn_p4 = m4;
+    R turn_som = C.v_som * m3 * C.dt;
+    if (turn_som > m3) turn_som = m3;
+    const R n1 = m1 + (uptake - morta - resp);
+    R n2, n3, n4;
+    if (C.route == 0) {
+        n2 = m2 + (C.beta * morta - uptake + turn_p4 + turn_som);
+        n3 = m3 + (C.omb * morta - turn_som);
+        n4 = m4 - turn_p4;
+    } else {
+        n2 = m2 + (R(0) - uptake + turn_p4 + turn_som);
+        n3 = m3 + (R(0) - turn_som);
+        n4 = m4 + (morta - turn_p4);
+    }
+    m1 = n1; m2 = n2; m3 = n3; m4 = n4; m5 = m5 + resp;
+}
+
+// Reverse of the transformation at pre-step masses x (branches re-taken from
+// x).  In: ybar = adjoint of T's outputs.  Out: adjoint of its inputs.  The
+// rate derivatives accumulate into g[0..6] = v_DOM, K_DOM, rho, mu, beta,
+// v_SOM, v_P4 (FP64).
+template <typename R>
+__device__ __forceinline__ void transform_rev(const Coef<R> &C, const R (&x)[VG_NPOOL], R (&bar)[VG_NPOOL],
+                                              double *g) {
+    const R m1 = x[0], m2 = x[1], m3 = x[2], m4 = x[3];
+    const R dt = C.dt;
+    const R den = C.k_dom + m2;
+    const R up_raw = C.v_dom * m2 / den * m1 * dt;
+    const bool up_clamp = up_raw > m2;
+    const R resp0 = C.rho * m1 * dt, morta0 = C.mu * m1 * dt;
+    int rm = 0;   // 0 free, 1 all biomass dies, 2 respiration takes the rest
+    R morta = morta0;
+    if (resp0 + morta0 > m1) {
+        if (morta0 > m1) { rm = 1; morta = m1; }
+        else rm = 2;
+    }
+    const bool p4_clamp = C.v_p4 * m4 * dt > m4;
+    const bool som_clamp = C.v_som * m3 * dt > m3;
+
+    const R y1 = bar[0], y2 = bar[1], y3 = bar[2], y4 = bar[3], y5 = bar[4];
+    R b1 = y1, b2 = y2, b3 = y3, b4 = y4;
+    const R b5 = y5;
+    const R upb = y1 - y2;
+    R mortb;
+    if (C.route == 0) {
+        mortb = -y1 + C.beta * y2 + C.omb * y3;
+        g[4] += (double)morta * (double)(y2 - y3);
+    } else {
+        mortb = -y1 + y4;
+    }
+    const R respb = -y1 + y5;
+    const R p4b = y2 - y4;
+    const R somb = y2 - y3;
+    if (up_clamp) {
+        b2 += upb;
+    } else {
+        const R gm = m2 / den;
+        b1 += upb * C.v_dom * gm * dt;
+        b2 += upb * C.v_dom * m1 * dt * C.k_dom / (den * den);
+        g[0] += (double)upb * (double)(gm * m1 * dt);
+        g[1] -= (double)upb * (double)(C.v_dom * m1 * dt * m2 / (den * den));
+    }
+    if (rm == 0) {
+        b1 += respb * C.rho * dt + mortb * C.mu * dt;
+        g[2] += (double)respb * (double)(m1 * dt);
+        g[3] += (double)mortb * (double)(m1 * dt);
+    } else if (rm == 1) {
+        b1 += mortb;
+    } else {
+        const R mt = mortb - respb;
+        b1 += respb + mt * C.mu * dt;
+        g[3] += (double)mt * (double)(m1 * dt);
+    }
+    if (som_clamp) b3 += somb;
+    else { b3 += somb * C.v_som * dt; g[5] += (double)somb * (double)(m3 * dt); }
+    if (p4_clamp) b4 += p4b;
+    else { b4 += p4b * C.v_p4 * dt; g[6] += (double)p4b * (double)(m4 * dt); }
+    bar[0] = b1; bar[1] = b2; bar[2] = b3; bar[3] = b4; bar[4] = b5;
+}
+
+template <typename R>
+struct AdjBufs {
+    const int32_t *nbr;
+    const uint16_t *rcode;
+    const R *st;       // stored state of this step, pool s at st + s*n
+    const R *lin;      // lambda^(k+1)
+    R *lout;           // lambda^k
+    const double *seed;   // [nseg][5] for this step
+    int64_t n, ntiles;
+};
+
+template <int MOB>
+__device__ __forceinline__ constexpr bool mobile(int s) {
+    return MOB == 2 || (MOB == 1 && s == 1);
+}
+
+template <typename R, int MOB, bool REG, bool FROM_X>
+__global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces pc, double *__restrict__ part) {
+    __shared__ double lds[kWaves * kG];
+    __shared__ R cl[VG_NREG];
+    if (threadIdx.x < VG_NREG) cl[threadIdx.x] = C.c[threadIdx.x];
+    __syncthreads();
+    double g[kG];
+#pragma unroll
+    for (int q = 0; q < kG; q++) g[q] = 0.0;
+    const int64_t n = A.n;
+
+    for (int64_t t = xcd_tile(blockIdx.x, gridDim.x); t < A.ntiles; t += gridDim.x) {
+        const int64_t i = t * kTile + threadIdx.x;
+        if (i >= n) continue;
+        int32_t j[6];
+#pragma unroll
+        for (int k = 0; k < 6; k++) j[k] = A.nbr[(int64_t)k * n + i];
+        R w[6];
+        uint32_t code = 0, own = 0;
+        if (REG) {
+            code = A.rcode[i];
+            own = code & 7u;
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                const uint32_t other = own ^ (((code >> (3 + k)) & 1u) << (k >> 1));
+                w[k] = R(0.5) * (cl[own] + cl[other]);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 6; k++) w[k] = R(1);
+        }
+        // forward state x^k of this step
+        R x[VG_NPOOL];
+#pragma unroll
+        for (int s = 0; s < VG_NPOOL; s++) x[s] = A.st[(int64_t)s * n + i];
+        if (!FROM_X) {
+#pragma unroll
+            for (int s = 0; s < VG_NPOOL; s++) {
+                if (!mobile<MOB>(s)) continue;
+                const R xi = x[s];
+                R d[6];
+#pragma unroll
+                for (int k = 0; k < 6; k++) {
+                    R tt = R(0);
+                    if (j[k] >= 0) {
+                        const R diff = A.st[(int64_t)s * n + j[k]] - xi;
+                        tt = REG ? w[k] * diff : diff;
+                    }
+                    d[k] = tt;
+                }
+                x[s] = xi + C.a[s] * (((d[0] + d[1]) + (d[2] + d[3])) + (d[4] + d[5]));
+            }
+        }
+        R u[VG_NPOOL] = {x[0], x[1], x[2], x[3], x[4]};
+        transform_fwd(C, u[0], u[1], u[2], u[3], u[4]);
+
+        // adjoint of the diffusion half: ubar = Q_w lambda; parameter terms
+        R bar[VG_NPOOL];
+        double own_c = 0.0, cross_c[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < VG_NPOOL; s++) {
+            const R li = A.lin[(int64_t)s * n + i];
+            R sum = R(0);
+            double creg_own = 0.0, creg_x[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                if (j[k] < 0) continue;
+                const R dl = A.lin[(int64_t)s * n + j[k]] - li;
+                sum += w[k] * dl;
+                if (REG && mobile<MOB>(s)) {
+                    const double tk = (double)dl;
+                    if ((code >> (3 + k)) & 1u) {
+                        creg_own += 0.5 * tk;
+                        creg_x[k >> 1] += 0.5 * tk;
+                    } else {
+                        creg_own += tk;
+                    }
+                }
+            }
+            bar[s] = mobile<MOB>(s) ? li + C.a[s] * sum : li;
+            g[s] += (double)u[s] * (double)sum;   // dL/da_s
+            if (REG && mobile<MOB>(s)) {
+                const double f = (double)C.a[s] * (double)u[s];
+                own_c += f * creg_own;
+                cross_c[0] += f * creg_x[0];
+                cross_c[1] += f * creg_x[1];
+                cross_c[2] += f * creg_x[2];
+            }
+        }
+        if (REG) {
+#pragma unroll
+            for (int r = 0; r < VG_NREG; r++) {
+                double v = 0.0;
+                if ((int)own == r) v += own_c;
+                if ((int)(own ^ 1u) == r) v += cross_c[0];
+                if ((int)(own ^ 2u) == r) v += cross_c[1];
+                if ((int)(own ^ 4u) == r) v += cross_c[2];
+                g[12 + r] += v;
+            }
+        }
+        // adjoint of the transformation half
+        transform_rev(C, x, bar, &g[5]);
+        // seeds of this step's totals
+        int32_t p = pc.piece_first[t];
+        while (p + 1 < pc.piece_first[t + 1] && i >= pc.piece_lo[p + 1]) p++;
+        const double *sd = A.seed + (int64_t)pc.piece_seg[p] * VG_NPOOL;
+#pragma unroll
+        for (int s = 0; s < VG_NPOOL; s++) A.lout[(int64_t)s * n + i] = (R)((double)bar[s] + sd[s]);
+    }
+    block_sum<kG>(g, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < kG; q++) part[(int64_t)blockIdx.x * kG + q] += g[q];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(double *__restrict__ p, int64_t cnt, double v) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < cnt) p[i] = v;
+}
+
+// grad[q] += sum over blocks (fixed order) of part[b][q]; dL/da_s -> dL/dD_s.
+__global__ __launch_bounds__(kBlock) void k_adj_finalize(const double *__restrict__ part, int nblocks,
+                                                         double scale_d, double *__restrict__ grad) {
+    __shared__ double lds[kWaves * kG];
+    double v[kG];
+#pragma unroll
+    for (int q = 0; q < kG; q++) v[q] = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kBlock) {
+#pragma unroll
+        for (int q = 0; q < kG; q++) v[q] += part[(int64_t)b * kG + q];
+    }
+    block_sum<kG>(v, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < kG; q++) grad[q] += q < VG_NPOOL ? v[q] * scale_d : v[q];
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_seed(R *__restrict__ lam, const double *__restrict__ seed, int zero,
+                                                 Pieces pc, int64_t n) {
+    const int64_t t = blockIdx.x;
+    const int64_t i = t * kTile + threadIdx.x;
+    if (i >= n) return;
+    int32_t p = pc.piece_first[t];
+    while (p + 1 < pc.piece_first[t + 1] && i >= pc.piece_lo[p + 1]) p++;
+    const double *sd = seed + (int64_t)pc.piece_seg[p] * VG_NPOOL;
+#pragma unroll
+    for (int s = 0; s < VG_NPOOL; s++) {
+        const int64_t e = (int64_t)s * n + i;
+        lam[e] = (R)((zero ? 0.0 : (double)lam[e]) + sd[s]);
+    }
+}
+
+template <typename R, int MOB, bool REG>
+int launch_adj_step(vg_sim *h, bool from_x, const AdjBufs<R> &A, const Coef<R> &C, hipStream_t s) {
+    Pieces pc{h->piece_first, h->piece_lo, h->piece_seg, h->npieces};
+    if (from_x) hipLaunchKernelGGL((k_adj<R, MOB, REG, true>), dim3(h->adj_blocks), dim3(kBlock), 0, s, A, C, pc,
+                                   h->adj_part);
+    else hipLaunchKernelGGL((k_adj<R, MOB, REG, false>), dim3(h->adj_blocks), dim3(kBlock), 0, s, A, C, pc,
+                            h->adj_part);
+    return launch_status("k_adj");
+}
+
+template <typename R>
+int adjoint_sweep(vg_sim *h, int64_t nsteps, double dt, const void *states, const double *seeds, void *lambda,
+                  double *grad, hipStream_t s) {
+    const Coef<R> C = make_coef<R>(h, dt);
+    const int64_t n = h->n;
+    const int64_t cnt = (int64_t)h->adj_blocks * kG;
+    int rc;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((cnt + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, h->adj_part, cnt,
+                       0.0);
+    if ((rc = launch_status("k_fill"))) return rc;
+    R *bufs[2] = {(R *)lambda, (R *)h->lam_alt};
+    int cur = 0;
+    const bool reg = h->rcode != nullptr;
+    for (int64_t jstep = nsteps - 1; jstep >= 0; jstep--) {
+        AdjBufs<R> A;
+        A.nbr = h->nbr;
+        A.rcode = h->rcode;
+        A.st = (const R *)states + jstep * VG_NPOOL * n;
+        A.lin = bufs[cur];
+        A.lout = bufs[cur ^ 1];
+        A.seed = seeds + jstep * (int64_t)h->nseg * VG_NPOOL;
+        A.n = n;
+        A.ntiles = h->ntiles;
+        const bool fx = jstep == 0;
+        if (h->mobile_all) rc = reg ? launch_adj_step<R, 2, true>(h, fx, A, C, s) : launch_adj_step<R, 2, false>(h, fx, A, C, s);
+        else rc = reg ? launch_adj_step<R, 1, true>(h, fx, A, C, s) : launch_adj_step<R, 1, false>(h, fx, A, C, s);
+        if (rc) return rc;
+        cur ^= 1;
+    }
+    if (cur) {
+        if ((rc = hip_status(hipMemcpyAsync(lambda, h->lam_alt, sizeof(R) * VG_NPOOL * (size_t)n,
+                                            hipMemcpyDeviceToDevice, s), "lambda copy"))) return rc;
+    }
+    const double scale_d = dt / (h->params.h * h->params.h);
+    hipLaunchKernelGGL(k_adj_finalize, dim3(1), dim3(kBlock), 0, s, h->adj_part, h->adj_blocks, scale_d, grad);
+    return launch_status("k_adj_finalize");
+}
+
+template <typename R>
+int record(vg_sim *h, int64_t nsteps, double dt, void *states, hipStream_t s) {
+    const int64_t n = h->n;
+    R *st = (R *)states;
+    int rc;
+    // states[0] = x^k0 (the bound fields)
+    if ((rc = hip_status(hipMemcpyAsync(st, h->fields, sizeof(R) * VG_NPOOL * (size_t)n, hipMemcpyDeviceToDevice, s),
+                         "record copy"))) return rc;
+    for (int64_t jstep = 1; jstep < nsteps; jstep++) {
+        const void *src[VG_NPOOL];
+        void *dst[VG_NPOOL];
+        for (int p = 0; p < VG_NPOOL; p++) {
+            src[p] = st + ((jstep - 1) * VG_NPOOL + p) * n;
+            dst[p] = st + (jstep * VG_NPOOL + p) * n;
+        }
+        // states[1] = T(x^k0); states[j] = T(D(states[j-1])) afterwards
+        rc = launch_pass_bufs(h, jstep == 1 ? MODE_T : MODE_DT, TOT_NONE, dt, src, dst, s);
+        if (rc) return rc;
+    }
+    return VG_OK;
+}
+
+}  // namespace
+
+int launch_record(vg_sim *h, int64_t nsteps, double dt, void *states, hipStream_t s) {
+    if (h->n == 0 || nsteps == 0) return VG_OK;
+    if (h->prec == VG_F64) return record<double>(h, nsteps, dt, states, s);
+    return record<float>(h, nsteps, dt, states, s);
+}
+
+int launch_adjoint(vg_sim *h, int64_t nsteps, double dt, const void *states, const double *seeds, void *lambda,
+                   double *grad, hipStream_t s) {
+    if (h->n == 0 || nsteps == 0) return VG_OK;
+    if (h->prec == VG_F64) return adjoint_sweep<double>(h, nsteps, dt, states, seeds, lambda, grad, s);
+    return adjoint_sweep<float>(h, nsteps, dt, states, seeds, lambda, grad, s);
+}
+
+int launch_seed(vg_sim *h, const double *seed, void *lambda, int zero, hipStream_t s) {
+    if (h->n == 0) return VG_OK;
+    Pieces pc{h->piece_first, h->piece_lo, h->piece_seg, h->npieces};
+    if (h->prec == VG_F64)
+        hipLaunchKernelGGL((k_seed<double>), dim3((unsigned)h->ntiles), dim3(kBlock), 0, s, (double *)lambda, seed,
+                           zero, pc, h->n);
+    else
+        hipLaunchKernelGGL((k_seed<float>), dim3((unsigned)h->ntiles), dim3(kBlock), 0, s, (float *)lambda, seed,
+                           zero, pc, h->n);
+    return launch_status("k_seed");
+}
+
+}  // namespace vg

@@ -1,0 +1,386 @@
+// C-ABI of libvgsim: handle, argument validation, workspace layout and the
+// orchestration of the kernels of vg_step.hip, vg_cg.hip and vg_adjoint.hip.
+// Owns no device memory: every device buffer is bound by the caller.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "vg_internal.h"
+
+namespace vg {
+
+static thread_local char g_err[512];
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+int hip_status(hipError_t e, const char *what) {
+    if (e == hipSuccess) return VG_OK;
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return VG_EHIP;
+}
+
+int launch_status(const char *what) { return hip_status(hipGetLastError(), what); }
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Workspace layout; with base == nullptr it only measures.
+size_t layout(vg_sim *h, char *base) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off += align_up(bytes ? bytes : 1);
+        return p;
+    };
+    h->piece_first = (int32_t *)take(sizeof(int32_t) * (size_t)(h->ntiles + 1));
+    h->piece_lo = (int64_t *)take(sizeof(int64_t) * (size_t)(h->npieces + 1));
+    h->piece_seg = (int32_t *)take(sizeof(int32_t) * (size_t)h->npieces);
+    h->seg_first = (int32_t *)take(sizeof(int32_t) * (size_t)(h->nseg + 1));
+    h->part = (double *)take(sizeof(double) * VG_NPOOL * (size_t)h->npieces);
+    h->tot_tmp = (double *)take(sizeof(double) * 6 * (size_t)h->nseg);
+    const size_t nd = sizeof(double) * (size_t)h->n;
+    if (h->features & VG_FEAT_CG) {
+        h->cg_y = (double *)take(nd);
+        h->cg_r = (double *)take(nd);
+        h->cg_z = (double *)take(nd);
+        h->cg_q = (double *)take(nd);
+        h->cg_m = (double *)take(nd);
+        h->cg_p[0] = (double *)take(nd);
+        h->cg_p[1] = (double *)take(nd);
+        h->cg_part = (double *)take(sizeof(double) * 4 * (size_t)h->cg_blocks);
+        h->cg_scal = (double *)take(sizeof(double) * 8);
+    }
+    if (h->features & VG_FEAT_ADJ) {
+        h->lam_alt = take(h->elem() * VG_NPOOL * (size_t)h->n);
+        h->adj_part = (double *)take(sizeof(double) * VG_NGRAD * (size_t)h->adj_blocks);
+    }
+    return off;
+}
+
+// Pieces: the intersections of the reduction tiles with the segments.
+void make_pieces(vg_sim *h) {
+    const int64_t n = h->n;
+    h->ntiles = (n + kTile - 1) / kTile;
+    h->piece_first_h.assign((size_t)h->ntiles + 1, 0);
+    h->piece_lo_h.clear();
+    h->piece_seg_h.clear();
+    int g = 0;
+    while (g < h->nseg && h->seg_off[g + 1] <= 0) g++;
+    for (int64_t t = 0; t < h->ntiles; t++) {
+        h->piece_first_h[t] = (int32_t)h->piece_seg_h.size();
+        int64_t lo = t * kTile;
+        const int64_t hi = lo + kTile < n ? lo + kTile : n;
+        while (lo < hi) {
+            while (h->seg_off[g + 1] <= lo) g++;
+            h->piece_lo_h.push_back(lo);
+            h->piece_seg_h.push_back(g);
+            lo = h->seg_off[g + 1] < hi ? h->seg_off[g + 1] : hi;
+        }
+    }
+    h->piece_first_h[h->ntiles] = (int32_t)h->piece_seg_h.size();
+    h->npieces = (int32_t)h->piece_seg_h.size();
+    h->piece_lo_h.push_back(n);
+    h->seg_first_h.assign((size_t)h->nseg + 1, h->npieces);
+    for (int gg = h->nseg - 1; gg >= 0; gg--) h->seg_first_h[gg] = h->seg_first_h[gg + 1];
+    for (int p = h->npieces - 1; p >= 0; p--) h->seg_first_h[h->piece_seg_h[p]] = p;
+    // empty segments take the start of the next non-empty one
+    for (int gg = h->nseg - 1; gg >= 0; gg--)
+        if (h->seg_off[gg] == h->seg_off[gg + 1]) h->seg_first_h[gg] = h->seg_first_h[gg + 1];
+    const int64_t cap = 2048;
+    h->cg_blocks = (int)(h->ntiles < cap ? (h->ntiles > 0 ? h->ntiles : 1) : cap);
+    h->adj_blocks = h->cg_blocks;
+}
+
+int check_params(const vg_sim *h, const vg_params *p) {
+    if (!(p->h > 0) || !std::isfinite(p->h)) { set_error("h must be positive"); return VG_EINVAL; }
+    if (!(p->k_dom > 0)) { set_error("K_DOM must be positive"); return VG_EINVAL; }
+    const double r[6] = {p->v_dom, p->rho, p->mu, p->v_som, p->v_p4, p->beta};
+    for (double v : r)
+        if (!(v >= 0) || !std::isfinite(v)) { set_error("rates must be finite and >= 0"); return VG_EINVAL; }
+    if (p->beta > 1) { set_error("beta must lie in [0, 1]"); return VG_EINVAL; }
+    for (int s = 0; s < VG_NPOOL; s++) {
+        if (!(p->D[s] >= 0) || !std::isfinite(p->D[s])) { set_error("D must be finite and >= 0"); return VG_EINVAL; }
+        if (!h->mobile_all && s != 1 && p->D[s] != 0) {
+            set_error("pool %d diffuses but the handle was created with mobile_all = 0", s);
+            return VG_EINVAL;
+        }
+    }
+    if (p->step_order != VG_ORDER_TD && p->step_order != VG_ORDER_DT) {
+        set_error("step_order must be VG_ORDER_TD or VG_ORDER_DT");
+        return VG_EINVAL;
+    }
+    return VG_OK;
+}
+
+double max_c(const vg_sim *h) {
+    double m = 1.0;
+    if (h->rcode) {
+        m = h->c[0];
+        for (int r = 1; r < VG_NREG; r++) m = h->c[r] > m ? h->c[r] : m;
+    }
+    return m;
+}
+
+int need_bound(const vg_sim *h) {
+    if (!h) { set_error("handle is NULL"); return VG_EINVAL; }
+    if (!h->bound) { set_error("no state bound (call vg_init_state)"); return VG_ESTATE; }
+    return VG_OK;
+}
+
+}  // namespace
+}  // namespace vg
+
+using namespace vg;
+
+extern "C" const char *vg_strerror(int code) {
+    switch (code) {
+        case VG_OK: return "ok";
+        case VG_EINVAL: return "invalid argument";
+        case VG_EUNSTABLE: return "explicit time step above the stability bound";
+        case VG_ENOCONV: return "conjugate gradient did not converge";
+        case VG_ENONFINITE: return "non-finite mass total";
+        case VG_EHIP: return "HIP runtime error";
+        case VG_ESTATE: return "call out of sequence";
+        default: return "unknown error";
+    }
+}
+
+extern "C" const char *vg_last_error(void) { return g_err; }
+
+extern "C" int vg_version(void) { return 100; }
+
+extern "C" int vg_create(const vg_desc *d, vg_sim **out) {
+    if (!d || !out) { set_error("null pointer argument"); return VG_EINVAL; }
+    *out = nullptr;
+    if (d->n < 0 || d->n > INT32_MAX || d->nseg < 1 || !d->seg_off || (d->n > 0 && !d->nbr_d)) {
+        set_error("bad graph descriptor (n, nseg, seg_off, nbr)");
+        return VG_EINVAL;
+    }
+    if (d->precision != VG_F32 && d->precision != VG_F64) { set_error("precision must be VG_F32 or VG_F64"); return VG_EINVAL; }
+    if (d->seg_off[0] != 0 || d->seg_off[d->nseg] != d->n) { set_error("seg_off must run from 0 to n"); return VG_EINVAL; }
+    for (int g = 0; g < d->nseg; g++)
+        if (d->seg_off[g + 1] < d->seg_off[g]) { set_error("seg_off must be non-decreasing"); return VG_EINVAL; }
+    if (d->features & ~(VG_FEAT_CG | VG_FEAT_ADJ)) { set_error("unknown feature bits"); return VG_EINVAL; }
+    vg_sim *h = new (std::nothrow) vg_sim();
+    if (!h) { set_error("out of host memory"); return VG_EINVAL; }
+    h->n = d->n;
+    h->nseg = d->nseg;
+    h->prec = d->precision;
+    h->mobile_all = d->mobile_all ? 1 : 0;
+    h->features = d->features;
+    h->seg_off.assign(d->seg_off, d->seg_off + d->nseg + 1);
+    h->nbr = d->nbr_d;
+    h->rcode = d->rcode_d;
+    vg_params p{};
+    p.D[1] = 1e-9;
+    p.h = 24e-6;
+    p.v_dom = 1e-4; p.k_dom = 0.5; p.rho = 2e-6; p.mu = 5e-7; p.beta = 0.55; p.v_som = 1e-7; p.v_p4 = 1e-7;
+    p.mort_to_p4 = 0;
+    p.step_order = VG_ORDER_TD;
+    h->params = p;
+    make_pieces(h);
+    *out = h;
+    return VG_OK;
+}
+
+extern "C" int vg_destroy(vg_sim *h) {
+    delete h;
+    return VG_OK;
+}
+
+extern "C" int vg_set_params(vg_sim *h, const vg_params *p) {
+    if (!h || !p) { set_error("null pointer argument"); return VG_EINVAL; }
+    int rc = check_params(h, p);
+    if (rc) return rc;
+    h->params = *p;
+    return VG_OK;
+}
+
+extern "C" int vg_set_regions(vg_sim *h, const double *c) {
+    if (!h || !c) { set_error("null pointer argument"); return VG_EINVAL; }
+    for (int r = 0; r < VG_NREG; r++)
+        if (!(c[r] > 0) || !std::isfinite(c[r])) { set_error("region factors must be finite and > 0"); return VG_EINVAL; }
+    for (int r = 0; r < VG_NREG; r++) h->c[r] = c[r];
+    return VG_OK;
+}
+
+extern "C" int vg_alt_elems(const vg_sim *h, int64_t *elems) {
+    if (!h || !elems) { set_error("null pointer argument"); return VG_EINVAL; }
+    *elems = (h->mobile_all ? VG_NPOOL : 1) * h->n;
+    return VG_OK;
+}
+
+extern "C" int vg_workspace_bytes(const vg_sim *h, size_t *bytes) {
+    if (!h || !bytes) { set_error("null pointer argument"); return VG_EINVAL; }
+    vg_sim tmp;
+    tmp.n = h->n; tmp.nseg = h->nseg; tmp.prec = h->prec; tmp.features = h->features;
+    tmp.ntiles = h->ntiles; tmp.npieces = h->npieces; tmp.cg_blocks = h->cg_blocks; tmp.adj_blocks = h->adj_blocks;
+    *bytes = layout(&tmp, nullptr);
+    return VG_OK;
+}
+
+extern "C" int vg_init_state(vg_sim *h, void *fields_d, void *alt_d, void *work_d, size_t work_bytes, void *stream) {
+    if (!h) { set_error("handle is NULL"); return VG_EINVAL; }
+    if (h->n > 0 && (!fields_d || !alt_d || !work_d)) { set_error("null buffer"); return VG_EINVAL; }
+    size_t need = 0;
+    vg_workspace_bytes(h, &need);
+    if (work_bytes < need) {
+        set_error("workspace too small: %zu < %zu bytes", work_bytes, need);
+        return VG_EINVAL;
+    }
+    h->fields = (char *)fields_d;
+    h->alt = (char *)alt_d;
+    h->work = (char *)work_d;
+    layout(h, h->work);
+    h->cur = 0;
+    hipStream_t s = (hipStream_t)stream;
+    int rc;
+    if ((rc = hip_status(hipMemcpyAsync(h->piece_first, h->piece_first_h.data(), sizeof(int32_t) * h->piece_first_h.size(),
+                                        hipMemcpyHostToDevice, s), "upload tiles"))) return rc;
+    if ((rc = hip_status(hipMemcpyAsync(h->piece_lo, h->piece_lo_h.data(), sizeof(int64_t) * h->piece_lo_h.size(),
+                                        hipMemcpyHostToDevice, s), "upload pieces"))) return rc;
+    if (h->npieces > 0 &&
+        (rc = hip_status(hipMemcpyAsync(h->piece_seg, h->piece_seg_h.data(), sizeof(int32_t) * h->piece_seg_h.size(),
+                                        hipMemcpyHostToDevice, s), "upload piece segments"))) return rc;
+    if ((rc = hip_status(hipMemcpyAsync(h->seg_first, h->seg_first_h.data(), sizeof(int32_t) * h->seg_first_h.size(),
+                                        hipMemcpyHostToDevice, s), "upload segments"))) return rc;
+    // the host tables must outlive the asynchronous copies
+    if ((rc = hip_status(hipStreamSynchronize(s), "synchronise"))) return rc;
+    h->bound = true;
+    return VG_OK;
+}
+
+extern "C" int vg_step_explicit(vg_sim *h, int64_t nsteps, double dt, int64_t log_every, double *totals_log_d,
+                                unsigned flags, void *stream) {
+    int rc;
+    if (!h) { set_error("handle is NULL"); return VG_EINVAL; }
+    if (nsteps < 0 || !(dt > 0) || !std::isfinite(dt) || log_every < 0) {
+        set_error("need nsteps >= 0, dt > 0, log_every >= 0");
+        return VG_EINVAL;
+    }
+    const int64_t nlog = log_every > 0 ? nsteps / log_every : 0;
+    if (nlog > 0 && !totals_log_d) { set_error("totals_log_d is NULL"); return VG_EINVAL; }
+    if (flags & ~VG_FORCE) { set_error("unknown flags"); return VG_EINVAL; }
+    if (!(flags & VG_FORCE)) {
+        double dmax = 0;
+        for (int s = 0; s < VG_NPOOL; s++) dmax = h->params.D[s] > dmax ? h->params.D[s] : dmax;
+        const double worst = dmax * dt / (h->params.h * h->params.h) * 6.0 * max_c(h);
+        if (worst > 1.0) {
+            set_error("dt = %g gives max_s a_s * sum_j w_ij = %g > 1 (negative masses possible)", dt, worst);
+            return VG_EUNSTABLE;
+        }
+    }
+    if ((rc = need_bound(h))) return rc;
+    if (nsteps == 0 || h->n == 0) return VG_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t row = (size_t)h->nseg * 6;
+    auto logged = [&](int64_t j) { return log_every > 0 && j % log_every == 0; };
+    auto finalize = [&](int64_t j) -> int {
+        return launch_totals_finalize(h, totals_log_d + (size_t)(j / log_every - 1) * row, s);
+    };
+    if (h->params.step_order == VG_ORDER_TD) {
+        if ((rc = launch_pass(h, MODE_T, TOT_NONE, dt, s))) return rc;
+        for (int64_t j = 1; j < nsteps; j++) {
+            const bool lg = logged(j);
+            if ((rc = launch_pass(h, MODE_DT, lg ? TOT_MID : TOT_NONE, dt, s))) return rc;
+            if (lg && (rc = finalize(j))) return rc;
+        }
+        const bool lg = logged(nsteps);
+        if ((rc = launch_pass(h, MODE_D, lg ? TOT_OUT : TOT_NONE, dt, s))) return rc;
+        if (lg && (rc = finalize(nsteps))) return rc;
+    } else {
+        for (int64_t j = 1; j <= nsteps; j++) {
+            const bool lg = logged(j);
+            if ((rc = launch_pass(h, MODE_DT, lg ? TOT_OUT : TOT_NONE, dt, s))) return rc;
+            if (lg && (rc = finalize(j))) return rc;
+        }
+    }
+    return restore_canonical(h, s);
+}
+
+extern "C" int vg_mass_totals(vg_sim *h, double *out_h, void *stream) {
+    int rc = need_bound(h);
+    if (rc) return rc;
+    if (!out_h) { set_error("out_h is NULL"); return VG_EINVAL; }
+    hipStream_t s = (hipStream_t)stream;
+    if (h->n == 0) {
+        for (int i = 0; i < h->nseg * 6; i++) out_h[i] = 0.0;
+        return VG_OK;
+    }
+    if ((rc = launch_pass(h, MODE_NONE, TOT_IN, 1.0, s))) return rc;
+    if ((rc = launch_totals_finalize(h, h->tot_tmp, s))) return rc;
+    if ((rc = hip_status(hipMemcpyAsync(out_h, h->tot_tmp, sizeof(double) * 6 * (size_t)h->nseg, hipMemcpyDeviceToHost, s),
+                         "copy totals"))) return rc;
+    if ((rc = hip_status(hipStreamSynchronize(s), "synchronise"))) return rc;
+    for (int i = 0; i < h->nseg * 6; i++)
+        if (!std::isfinite(out_h[i])) { set_error("total %d of segment %d is not finite", i % 6, i / 6); return VG_ENONFINITE; }
+    return VG_OK;
+}
+
+extern "C" int vg_solve_implicit_step(vg_sim *h, double dt, double rtol, int max_iter, int *iters_h, double *relres_h,
+                                      void *stream) {
+    int rc = need_bound(h);
+    if (rc) return rc;
+    if (!(h->features & VG_FEAT_CG)) { set_error("handle created without VG_FEAT_CG"); return VG_ESTATE; }
+    if (!(dt > 0) || !std::isfinite(dt) || !(rtol > 0) || max_iter < 0) {
+        set_error("need dt > 0, rtol > 0, max_iter >= 0");
+        return VG_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = launch_pass(h, MODE_T, TOT_NONE, dt, s))) return rc;
+    int status = VG_OK;
+    for (int p = 0; p < VG_NPOOL; p++) {
+        int it = 0;
+        double rr = 0.0;
+        if (h->params.D[p] > 0) {
+            const double a = h->params.D[p] * dt / (h->params.h * h->params.h);
+            rc = run_cg(h, p, a, rtol, max_iter, &it, &rr, s);
+            if (rc == VG_ENOCONV) status = VG_ENOCONV;
+            else if (rc) return rc;
+        }
+        if (iters_h) iters_h[p] = it;
+        if (relres_h) relres_h[p] = rr;
+    }
+    if (status == VG_ENOCONV) set_error("CG reached max_iter = %d above rtol = %g", max_iter, rtol);
+    if ((rc = hip_status(hipStreamSynchronize(s), "synchronise"))) return rc;
+    return status;
+}
+
+extern "C" int vg_record(vg_sim *h, int64_t nsteps, double dt, void *states_d, void *stream) {
+    int rc = need_bound(h);
+    if (rc) return rc;
+    if (!(h->features & VG_FEAT_ADJ)) { set_error("handle created without VG_FEAT_ADJ"); return VG_ESTATE; }
+    if (h->params.step_order != VG_ORDER_TD) { set_error("the adjoint supports the paper order only"); return VG_EINVAL; }
+    if (nsteps < 0 || !(dt > 0) || (nsteps > 0 && h->n > 0 && !states_d)) { set_error("bad record arguments"); return VG_EINVAL; }
+    return launch_record(h, nsteps, dt, states_d, (hipStream_t)stream);
+}
+
+extern "C" int vg_adjoint(vg_sim *h, int64_t nsteps, double dt, const void *states_d, const double *seeds_d,
+                          void *lambda_d, double *grad_d, void *stream) {
+    int rc = need_bound(h);
+    if (rc) return rc;
+    if (!(h->features & VG_FEAT_ADJ)) { set_error("handle created without VG_FEAT_ADJ"); return VG_ESTATE; }
+    if (h->params.step_order != VG_ORDER_TD) { set_error("the adjoint supports the paper order only"); return VG_EINVAL; }
+    if (nsteps < 0 || !(dt > 0)) { set_error("need nsteps >= 0 and dt > 0"); return VG_EINVAL; }
+    if (nsteps > 0 && h->n > 0 && (!states_d || !seeds_d || !lambda_d || !grad_d)) {
+        set_error("null pointer argument");
+        return VG_EINVAL;
+    }
+    return launch_adjoint(h, nsteps, dt, states_d, seeds_d, lambda_d, grad_d, (hipStream_t)stream);
+}
+
+extern "C" int vg_seed_lambda(vg_sim *h, const double *seed_d, void *lambda_d, int zero, void *stream) {
+    int rc = need_bound(h);
+    if (rc) return rc;
+    if (h->n > 0 && (!seed_d || !lambda_d)) { set_error("null pointer argument"); return VG_EINVAL; }
+    return launch_seed(h, seed_d, lambda_d, zero, (hipStream_t)stream);
+}

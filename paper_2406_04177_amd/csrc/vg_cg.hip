@@ -1,0 +1,250 @@
+// Implicit diffusion (Sec. II.B.3b, Scheme 2): per diffusing pool, solve
+// (I + a L_w) y = x with the conjugate gradient method preconditioned by the
+// inverse diagonal of the system matrix (Sec. III).  Matrix-free: the
+// Laplacian is applied as a gather over the neighbour table.  Vectors,
+// dot products and scalars are FP64 whatever the field type.
+//
+// Per iteration two streaming kernels (p/q update with the SpMV and p.q
+// partials; x/r/z update with r.z and r.r partials), each followed by a
+// one-block kernel that reduces the per-block partials in a fixed order and
+// updates the scalars on the device.  The host reads the scalars only every
+// few iterations; kernels launched after convergence return at once.
+#include "vg_internal.h"
+
+namespace vg {
+namespace {
+
+enum { S_RZ = 0, S_RR, S_BB, S_ALPHA, S_BETA, S_DONE, S_ITER, S_RTOL2, S_NSCAL = 8 };
+
+__device__ __forceinline__ double weight(const uint16_t *rcode, const double *cl, int64_t i, int k,
+                                         bool reg) {
+    if (!reg) return 1.0;
+    const uint32_t code = rcode[i];
+    const uint32_t own = code & 7u;
+    const uint32_t other = own ^ (((code >> (3 + k)) & 1u) << (k >> 1));
+    return 0.5 * (cl[own] + cl[other]);
+}
+
+struct CgArgs {
+    const int32_t *nbr;
+    const uint16_t *rcode;
+    int64_t n;
+    int64_t ntiles;
+    double a;
+    double c[VG_NREG];
+};
+
+template <typename R, bool REG>
+__global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs A, const R *__restrict__ field,
+                                                    double *__restrict__ y, double *__restrict__ r,
+                                                    double *__restrict__ z, double *__restrict__ p,
+                                                    double *__restrict__ m, double *__restrict__ part) {
+    __shared__ double lds[kWaves * 3];
+    __shared__ double cl[VG_NREG];
+    if (threadIdx.x < VG_NREG) cl[threadIdx.x] = A.c[threadIdx.x];
+    __syncthreads();
+    double acc[3] = {0.0, 0.0, 0.0};   // r.z, r.r, b.b
+    for (int64_t t = xcd_tile(blockIdx.x, gridDim.x); t < A.ntiles; t += gridDim.x) {
+        const int64_t i = t * kTile + threadIdx.x;
+        if (i >= A.n) continue;
+        const double b = (double)field[i];
+        double s = 0.0, deg = 0.0;
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            const int32_t j = A.nbr[(int64_t)k * A.n + i];
+            if (j < 0) continue;
+            const double w = weight(A.rcode, cl, i, k, REG);
+            deg += w;
+            s += w * (b - (double)field[j]);
+        }
+        const double mi = 1.0 / (1.0 + A.a * deg);
+        const double ri = b - (b + A.a * s);
+        const double zi = mi * ri;
+        y[i] = b;
+        r[i] = ri;
+        z[i] = zi;
+        p[i] = zi;
+        m[i] = mi;
+        acc[0] += ri * zi;
+        acc[1] += ri * ri;
+        acc[2] += b * b;
+    }
+    block_sum<3>(acc, lds);
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 3; q++) part[(int64_t)blockIdx.x * 4 + q] = acc[q];
+    }
+}
+
+// q = B p' with p' = z + beta p (the new search direction, also written out)
+template <bool REG>
+__global__ __launch_bounds__(kBlock) void k_cg_spmv(CgArgs A, const double *__restrict__ z,
+                                                    const double *__restrict__ pold, double *__restrict__ pnew,
+                                                    double *__restrict__ q, const double *__restrict__ scal,
+                                                    double *__restrict__ part) {
+    if (scal[S_DONE] != 0.0) return;
+    __shared__ double lds[kWaves];
+    __shared__ double cl[VG_NREG];
+    if (threadIdx.x < VG_NREG) cl[threadIdx.x] = A.c[threadIdx.x];
+    __syncthreads();
+    const double beta = scal[S_BETA];
+    double acc[1] = {0.0};
+    for (int64_t t = xcd_tile(blockIdx.x, gridDim.x); t < A.ntiles; t += gridDim.x) {
+        const int64_t i = t * kTile + threadIdx.x;
+        if (i >= A.n) continue;
+        const double pi = z[i] + beta * pold[i];
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            const int32_t j = A.nbr[(int64_t)k * A.n + i];
+            if (j < 0) continue;
+            const double pj = z[j] + beta * pold[j];
+            s += weight(A.rcode, cl, i, k, REG) * (pi - pj);
+        }
+        const double qi = pi + A.a * s;
+        pnew[i] = pi;
+        q[i] = qi;
+        acc[0] += pi * qi;
+    }
+    block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * 4] = acc[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, int64_t ntiles, const double *__restrict__ p,
+                                                      const double *__restrict__ q, const double *__restrict__ m,
+                                                      double *__restrict__ y, double *__restrict__ r,
+                                                      double *__restrict__ z, const double *__restrict__ scal,
+                                                      double *__restrict__ part) {
+    if (scal[S_DONE] != 0.0) return;
+    __shared__ double lds[kWaves * 2];
+    const double alpha = scal[S_ALPHA];
+    double acc[2] = {0.0, 0.0};
+    for (int64_t t = xcd_tile(blockIdx.x, gridDim.x); t < ntiles; t += gridDim.x) {
+        const int64_t i = t * kTile + threadIdx.x;
+        if (i >= n) continue;
+        y[i] += alpha * p[i];
+        const double ri = r[i] - alpha * q[i];
+        const double zi = m[i] * ri;
+        r[i] = ri;
+        z[i] = zi;
+        acc[0] += ri * zi;
+        acc[1] += ri * ri;
+    }
+    block_sum<2>(acc, lds);
+    if (threadIdx.x == 0) {
+        part[(int64_t)blockIdx.x * 4] = acc[0];
+        part[(int64_t)blockIdx.x * 4 + 1] = acc[1];
+    }
+}
+
+// stage 0: after init; 1: alpha after spmv; 2: beta/convergence after update
+__global__ __launch_bounds__(kBlock) void k_cg_scalars(const double *__restrict__ part, int nblocks, int stage,
+                                                       double *__restrict__ scal) {
+    if (stage != 0 && scal[S_DONE] != 0.0) return;
+    __shared__ double lds[kWaves * 3];
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblocks; b += kBlock) {
+        v[0] += part[(int64_t)b * 4];
+        v[1] += part[(int64_t)b * 4 + 1];
+        v[2] += part[(int64_t)b * 4 + 2];
+    }
+    block_sum<3>(v, lds);
+    if (threadIdx.x != 0) return;
+    if (stage == 0) {
+        scal[S_RZ] = v[0];
+        scal[S_RR] = v[1];
+        scal[S_BB] = v[2];
+        scal[S_BETA] = 0.0;
+        scal[S_ITER] = 0.0;
+        scal[S_DONE] = (v[1] <= scal[S_RTOL2] * v[2]) ? 1.0 : 0.0;
+    } else if (stage == 1) {
+        scal[S_ALPHA] = scal[S_RZ] / v[0];
+    } else {
+        scal[S_BETA] = v[0] / scal[S_RZ];
+        scal[S_RZ] = v[0];
+        scal[S_RR] = v[1];
+        scal[S_ITER] = scal[S_ITER] + 1.0;
+        if (v[1] <= scal[S_RTOL2] * scal[S_BB]) scal[S_DONE] = 1.0;
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_cg_writeback(int64_t n, const double *__restrict__ y,
+                                                         R *__restrict__ field) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) field[i] = (R)y[i];
+}
+
+template <typename R>
+int cg_solve(vg_sim *h, int pool, double a, double rtol, int max_iter, int *iters, double *relres,
+             hipStream_t s) {
+    CgArgs A;
+    A.nbr = h->nbr;
+    A.rcode = h->rcode;
+    A.n = h->n;
+    A.ntiles = h->ntiles;
+    A.a = a;
+    for (int k = 0; k < VG_NREG; k++) A.c[k] = h->c[k];
+    const bool reg = h->rcode != nullptr;
+    const int G = h->cg_blocks;
+    R *field = (R *)h->fields + (int64_t)pool * h->n;
+    int rc;
+    // squared tolerance (compared with squared norms; rtol^2 is exact enough)
+    double host_scal[S_NSCAL] = {0, 0, 0, 0, 0, 0, 0, rtol * rtol};
+    if ((rc = hip_status(hipMemcpyAsync(h->cg_scal, host_scal, sizeof(host_scal), hipMemcpyHostToDevice, s),
+                         "cg scalars"))) return rc;
+    if (reg) hipLaunchKernelGGL((k_cg_init<R, true>), dim3(G), dim3(kBlock), 0, s, A, field, h->cg_y, h->cg_r,
+                                h->cg_z, h->cg_p[0], h->cg_m, h->cg_part);
+    else hipLaunchKernelGGL((k_cg_init<R, false>), dim3(G), dim3(kBlock), 0, s, A, field, h->cg_y, h->cg_r,
+                            h->cg_z, h->cg_p[0], h->cg_m, h->cg_part);
+    if ((rc = launch_status("k_cg_init"))) return rc;
+    hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kBlock), 0, s, h->cg_part, G, 0, h->cg_scal);
+    if ((rc = launch_status("k_cg_scalars"))) return rc;
+
+    int launched = 0, cur = 0;
+    const int chunk = 8;
+    double back[S_NSCAL];
+    for (;;) {
+        if ((rc = hip_status(hipMemcpyAsync(back, h->cg_scal, sizeof(back), hipMemcpyDeviceToHost, s),
+                             "cg scalars back"))) return rc;
+        if ((rc = hip_status(hipStreamSynchronize(s), "cg sync"))) return rc;
+        if (back[S_DONE] != 0.0 || launched >= max_iter) break;
+        const int todo = (max_iter - launched) < chunk ? (max_iter - launched) : chunk;
+        for (int it = 0; it < todo; it++) {
+            if (reg) hipLaunchKernelGGL((k_cg_spmv<true>), dim3(G), dim3(kBlock), 0, s, A, h->cg_z, h->cg_p[cur],
+                                        h->cg_p[cur ^ 1], h->cg_q, h->cg_scal, h->cg_part);
+            else hipLaunchKernelGGL((k_cg_spmv<false>), dim3(G), dim3(kBlock), 0, s, A, h->cg_z, h->cg_p[cur],
+                                    h->cg_p[cur ^ 1], h->cg_q, h->cg_scal, h->cg_part);
+            if ((rc = launch_status("k_cg_spmv"))) return rc;
+            hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kBlock), 0, s, h->cg_part, G, 1, h->cg_scal);
+            if ((rc = launch_status("k_cg_scalars"))) return rc;
+            hipLaunchKernelGGL(k_cg_update, dim3(G), dim3(kBlock), 0, s, h->n, h->ntiles, h->cg_p[cur ^ 1],
+                               h->cg_q, h->cg_m, h->cg_y, h->cg_r, h->cg_z, h->cg_scal, h->cg_part);
+            if ((rc = launch_status("k_cg_update"))) return rc;
+            hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kBlock), 0, s, h->cg_part, G, 2, h->cg_scal);
+            if ((rc = launch_status("k_cg_scalars"))) return rc;
+            cur ^= 1;   // p ping-pong; after convergence the kernels return early
+        }
+        launched += todo;
+    }
+    hipLaunchKernelGGL((k_cg_writeback<R>), dim3((unsigned)((h->n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       h->n, h->cg_y, field);
+    if ((rc = launch_status("k_cg_writeback"))) return rc;
+    if (iters) *iters = (int)back[S_ITER];
+    if (relres) *relres = back[S_BB] > 0.0 ? __builtin_sqrt(back[S_RR] / back[S_BB]) : 0.0;
+    return back[S_DONE] != 0.0 ? VG_OK : VG_ENOCONV;
+}
+
+}  // namespace
+
+int run_cg(vg_sim *h, int pool, double a, double rtol, int max_iter, int *iters, double *relres,
+           hipStream_t s) {
+    if (h->n == 0) {
+        if (iters) *iters = 0;
+        if (relres) *relres = 0.0;
+        return VG_OK;
+    }
+    if (h->prec == VG_F64) return cg_solve<double>(h, pool, a, rtol, max_iter, iters, relres, s);
+    return cg_solve<float>(h, pool, a, rtol, max_iter, iters, relres, s);
+}
+
+}  // namespace vg

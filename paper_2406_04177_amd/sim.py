@@ -1,0 +1,150 @@
+"""Simulation state on the GPU: explicit and implicit time steps, mass totals,
+forward recording and the adjoint sweep (thin wrapper over the C ABI).
+
+Pools are numbered in the paper's order (Sec. II.A): 0 MB, 1 DOM, 2 SOM,
+3 FOM (called P4), 4 CO2.  Fields are a ``[5, n]`` tensor of the field type;
+torch allocates every buffer and supplies the stream, the library's kernels do
+all the arithmetic.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from .graph import Graph
+from .inputs import ModelParams
+
+_DTYPES = {"f32": torch.float32, "f64": torch.float64}
+
+
+def to_vg_params(p: ModelParams, step_order: int = _lib.VG_ORDER_TD) -> _lib.VgParams:
+    vp = _lib.VgParams()
+    for s in range(5):
+        vp.D[s] = float(p.D[s])
+    vp.h, vp.v_dom, vp.k_dom, vp.rho, vp.mu = float(p.h), float(p.v_dom), float(p.k_dom), float(p.rho), float(p.mu)
+    vp.beta, vp.v_som, vp.v_p4 = float(p.beta), float(p.v_som), float(p.v_p4)
+    vp.mort_to_p4 = 1 if p.mort_to_p4 else 0
+    vp.step_order = int(step_order)
+    return vp
+
+
+class Simulation:
+    """Binds a graph, parameters and GPU buffers to a library handle."""
+
+    def __init__(self, graph: Graph, params: ModelParams, precision: str = "f32",
+                 implicit: bool = True, adjoint: bool = False, mobile_all=None,
+                 step_order: int = _lib.VG_ORDER_TD, regions=None, stream=None):
+        self.L = _lib.load()
+        self.graph = graph
+        self.precision = precision
+        self.dtype = _DTYPES[precision]
+        self.step_order = step_order
+        self.stream = stream
+        if mobile_all is None:
+            mobile_all = any(float(d) != 0.0 for s, d in enumerate(params.D) if s != 1)
+        features = (_lib.VG_FEAT_CG if implicit else 0) | (_lib.VG_FEAT_ADJ if adjoint else 0)
+        self._seg = np.ascontiguousarray(graph.seg_off, np.int64)
+        use_regions = regions is not None or graph.rcode is not None
+        if use_regions and graph.rcode is None:
+            graph.make_region_codes(stream)
+        desc = _lib.VgDesc()
+        desc.n = graph.n
+        desc.nseg = graph.nseg
+        desc.precision = _lib.VG_F64 if precision == "f64" else _lib.VG_F32
+        desc.seg_off = self._seg.ctypes.data
+        desc.nbr_d = graph.nbr.data_ptr() if graph.n else None
+        desc.rcode_d = graph.rcode.data_ptr() if (use_regions and graph.n) else None
+        desc.mobile_all = 1 if mobile_all else 0
+        desc.features = features
+        h = ctypes.c_void_p()
+        _lib.check(self.L.vg_create(ctypes.byref(desc), ctypes.byref(h)), "vg_create")
+        self.h = h
+        self.set_params(params)
+        if regions is not None:
+            self.set_regions(regions)
+        dev = graph.vox.device
+        alt = ctypes.c_int64(0)
+        _lib.check(self.L.vg_alt_elems(h, ctypes.byref(alt)), "vg_alt_elems")
+        wsb = ctypes.c_size_t(0)
+        _lib.check(self.L.vg_workspace_bytes(h, ctypes.byref(wsb)), "vg_workspace_bytes")
+        self.fields = torch.zeros((5, graph.n), dtype=self.dtype, device=dev)
+        self.alt = torch.empty(max(alt.value, 1), dtype=self.dtype, device=dev)
+        self.work = torch.empty(wsb.value, dtype=torch.uint8, device=dev)
+        _lib.check(self.L.vg_init_state(h, self.fields.data_ptr(), self.alt.data_ptr(), self.work.data_ptr(),
+                                        wsb.value, self._sp()), "vg_init_state")
+
+    # ------------------------------------------------------------------ setup
+    def _sp(self):
+        return _lib.stream_ptr(self.stream)
+
+    def set_params(self, params: ModelParams):
+        self.params = params
+        vp = to_vg_params(params, self.step_order)
+        _lib.check(self.L.vg_set_params(self.h, ctypes.byref(vp)), "vg_set_params")
+
+    def set_regions(self, c):
+        arr = (ctypes.c_double * 8)(*[float(v) for v in c])
+        _lib.check(self.L.vg_set_regions(self.h, arr), "vg_set_regions")
+        self.regions = list(map(float, c))
+
+    def set_fields(self, x: torch.Tensor):
+        """Copy a [5, n] tensor into the bound fields."""
+        self.fields.copy_(x.to(device=self.fields.device, dtype=self.dtype))
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            self.L.vg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ stepping
+    def step(self, nsteps: int, dt: float, log_every: int = 0, force: bool = False,
+             totals_out: torch.Tensor = None):
+        """Advance ``nsteps`` explicit steps.  Returns the FP64 totals log
+        [nsteps // log_every, nseg, 6] (cuda) when ``log_every > 0``."""
+        nlog = nsteps // log_every if log_every > 0 else 0
+        log = totals_out
+        if nlog and log is None:
+            log = torch.empty((nlog, self.graph.nseg, 6), dtype=torch.float64, device=self.fields.device)
+        _lib.check(self.L.vg_step_explicit(self.h, int(nsteps), float(dt), int(log_every),
+                                           log.data_ptr() if nlog else None,
+                                           _lib.VG_FORCE if force else 0, self._sp()), "vg_step_explicit")
+        return log if nlog else None
+
+    def implicit_step(self, dt: float, rtol: float = 1e-10, max_iter: int = 1000, check: bool = True):
+        """One implicit step (transformation + Scheme 2 by PCG).  Returns
+        (iterations[5], relative residuals[5], status)."""
+        it = (ctypes.c_int * 5)()
+        rr = (ctypes.c_double * 5)()
+        rc = self.L.vg_solve_implicit_step(self.h, float(dt), float(rtol), int(max_iter), it, rr, self._sp())
+        if check:
+            _lib.check(rc, "vg_solve_implicit_step")
+        return list(it), list(rr), rc
+
+    def totals(self) -> np.ndarray:
+        """[nseg, 6] FP64 totals (pools 0-4, total carbon) of the current state."""
+        out = np.zeros((self.graph.nseg, 6), np.float64)
+        _lib.check(self.L.vg_mass_totals(self.h, out.ctypes.data_as(ctypes.c_void_p), self._sp()),
+                   "vg_mass_totals")
+        return out
+
+    # ------------------------------------------------------------------ adjoint
+    def record(self, nsteps: int, dt: float, states: torch.Tensor):
+        _lib.check(self.L.vg_record(self.h, int(nsteps), float(dt), states.data_ptr(), self._sp()), "vg_record")
+
+    def adjoint(self, nsteps: int, dt: float, states: torch.Tensor, seeds: torch.Tensor, lam: torch.Tensor,
+                grad: torch.Tensor):
+        _lib.check(self.L.vg_adjoint(self.h, int(nsteps), float(dt), states.data_ptr(), seeds.data_ptr(),
+                                     lam.data_ptr(), grad.data_ptr(), self._sp()), "vg_adjoint")
+
+    def seed_lambda(self, seed: torch.Tensor, lam: torch.Tensor, zero: bool):
+        _lib.check(self.L.vg_seed_lambda(self.h, seed.data_ptr(), lam.data_ptr(), 1 if zero else 0, self._sp()),
+                   "vg_seed_lambda")

@@ -1,0 +1,140 @@
+"""The C ABI loads, exports every entry point that include/vgsim.h declares,
+and its host-side validation rejects bad arguments (no GPU needed: none of
+these calls reaches the device)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2406_04177_amd import _lib
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "vgsim.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(vg_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_binding_exports():
+    assert declared_functions() == sorted(_lib.EXPORTS)
+
+
+def test_every_declared_symbol_is_exported():
+    L = _lib.load()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert L.vg_version() >= 100
+
+
+def test_error_strings():
+    L = _lib.load()
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert len(L.vg_strerror(code)) > 0
+
+
+def test_rank_bytes_validation():
+    L = _lib.load()
+    n = ctypes.c_size_t(0)
+    assert L.vg_rank_bytes(48, 48, 48, 0, ctypes.byref(n)) == 0
+    assert n.value >= 48 ** 3 // 32 * 8
+    assert L.vg_rank_bytes(0, 4, 4, 0, ctypes.byref(n)) == _lib.VG_EINVAL
+    assert L.vg_rank_bytes(4, 4, 4, -1, ctypes.byref(n)) == _lib.VG_EINVAL
+    assert L.vg_rank_bytes(2048, 2048, 1024, 0, ctypes.byref(n)) == _lib.VG_EINVAL   # > 2^31 voxels
+    assert b"2^31" in L.vg_last_error()
+    assert L.vg_count_pores(None, 4, 4, 4, 0, None, None, None) == _lib.VG_EINVAL
+
+
+def make_handle(n=1000, nseg=1, mobile_all=0, features=3):
+    L = _lib.load()
+    seg = np.linspace(0, n, nseg + 1).astype(np.int64)
+    desc = _lib.VgDesc()
+    desc.n, desc.nseg, desc.precision = n, nseg, _lib.VG_F32
+    desc.seg_off = seg.ctypes.data
+    desc.nbr_d = 0x1000          # never dereferenced by host-side calls
+    desc.rcode_d = None
+    desc.mobile_all, desc.features = mobile_all, features
+    h = ctypes.c_void_p()
+    rc = L.vg_create(ctypes.byref(desc), ctypes.byref(h))
+    return rc, h, seg
+
+
+def test_create_validates_descriptor():
+    L = _lib.load()
+    rc, h, seg = make_handle()
+    assert rc == 0 and h.value
+    L.vg_destroy(h)
+    desc = _lib.VgDesc()
+    seg = np.array([0, 5, 3], np.int64)
+    desc.n, desc.nseg, desc.precision, desc.seg_off, desc.nbr_d = 3, 2, 0, seg.ctypes.data, 0x1000
+    assert L.vg_create(ctypes.byref(desc), ctypes.byref(ctypes.c_void_p())) == _lib.VG_EINVAL
+    desc.precision = 7
+    assert L.vg_create(ctypes.byref(desc), ctypes.byref(ctypes.c_void_p())) == _lib.VG_EINVAL
+
+
+def test_params_validation():
+    from paper_2406_04177_amd.inputs import ModelParams
+    from paper_2406_04177_amd.sim import to_vg_params
+    L = _lib.load()
+    rc, h, _ = make_handle()
+    ok = to_vg_params(ModelParams())
+    assert L.vg_set_params(h, ctypes.byref(ok)) == 0
+    for bad in (ModelParams(k_dom=0.0), ModelParams(rho=-1.0), ModelParams(beta=1.5), ModelParams(h=0.0),
+                ModelParams(D=(1e-9, 1e-9, 0, 0, 0)), ModelParams(mu=float("nan"))):
+        assert L.vg_set_params(h, ctypes.byref(to_vg_params(bad))) == _lib.VG_EINVAL
+    # another pool may diffuse when the handle allows it
+    rc, h2, _ = make_handle(mobile_all=1)
+    assert L.vg_set_params(h2, ctypes.byref(to_vg_params(ModelParams(D=(1e-9, 1e-9, 0, 0, 0))))) == 0
+    c_bad = (ctypes.c_double * 8)(1, 1, 1, 0, 1, 1, 1, 1)
+    assert L.vg_set_regions(h, c_bad) == _lib.VG_EINVAL
+    L.vg_destroy(h)
+    L.vg_destroy(h2)
+
+
+def test_explicit_stability_bound_is_checked_before_any_device_work():
+    """Sec. IV.C: beyond dt = h^2 / (6 D) the explicit scheme gives negative
+    masses; the library refuses such a step unless forced."""
+    from paper_2406_04177_amd.inputs import ModelParams, explicit_dt
+    from paper_2406_04177_amd.sim import to_vg_params
+    L = _lib.load()
+    rc, h, _ = make_handle()
+    p = ModelParams()
+    L.vg_set_params(h, ctypes.byref(to_vg_params(p)))
+    bound = explicit_dt(p, factor=1.0)
+    assert L.vg_step_explicit(h, 10, bound * 1.01, 0, None, 0, None) == _lib.VG_EUNSTABLE
+    # below the bound (or forced) the call gets as far as the state check
+    assert L.vg_step_explicit(h, 10, bound * 0.99, 0, None, 0, None) == _lib.VG_ESTATE
+    assert L.vg_step_explicit(h, 10, bound * 1.01, 0, None, _lib.VG_FORCE, None) == _lib.VG_ESTATE
+    assert L.vg_step_explicit(h, -1, bound, 0, None, 0, None) == _lib.VG_EINVAL
+    assert L.vg_step_explicit(h, 10, 0.0, 0, None, 0, None) == _lib.VG_EINVAL
+    assert L.vg_step_explicit(h, 10, bound * 0.5, 1, None, 0, None) == _lib.VG_EINVAL  # log without buffer
+    L.vg_destroy(h)
+
+
+def test_calls_out_of_sequence():
+    L = _lib.load()
+    rc, h, _ = make_handle(features=0)
+    out = np.zeros(6)
+    assert L.vg_mass_totals(h, out.ctypes.data, None) == _lib.VG_ESTATE
+    assert L.vg_solve_implicit_step(h, 1.0, 1e-10, 10, None, None, None) == _lib.VG_ESTATE
+    assert L.vg_record(h, 1, 1.0, None, None) == _lib.VG_ESTATE
+    ws = ctypes.c_size_t(0)
+    assert L.vg_workspace_bytes(h, ctypes.byref(ws)) == 0 and ws.value > 0
+    assert L.vg_init_state(h, 0x1000, 0x1000, 0x1000, 0, None) == _lib.VG_EINVAL   # workspace too small
+    L.vg_destroy(h)
+
+
+def test_workspace_grows_with_features():
+    L = _lib.load()
+    sizes = []
+    for feat in (0, 1, 2, 3):
+        rc, h, _ = make_handle(n=100000, features=feat)
+        ws = ctypes.c_size_t(0)
+        L.vg_workspace_bytes(h, ctypes.byref(ws))
+        sizes.append(ws.value)
+        L.vg_destroy(h)
+    assert sizes[0] < sizes[1] < sizes[3] and sizes[0] < sizes[2] < sizes[3]
+    assert sizes[1] >= 7 * 8 * 100000          # seven FP64 CG vectors

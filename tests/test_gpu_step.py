@@ -1,0 +1,182 @@
+"""Explicit time stepping on the GPU vs the FP64 oracle.
+
+FP64 fields: bit-identical to the oracle (same operations in the same order,
+no fused multiply-add on either side), totals within 1e-13 relative.
+FP32 fields: within 1e-5 relative per pool for runs of up to a few hundred
+steps; longer runs are held to a bound derived from FP32 rounding (see
+test_fp32_long_run_error_bound).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as orc
+from paper_2406_04177_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+F64, F32 = "f64", "f32"
+
+
+def setup(shape=(48, 48, 48), seed=0, init="spots", params=None, masks=None, regions=None, brick=0,
+          periodic=0):
+    from paper_2406_04177_amd.graph import Graph
+    if masks is None:
+        masks = [inputs.synthetic_volume(shape, seed=seed)]
+    if init == "spots":
+        specs = [inputs.init_spots(m, seed) for m in masks]
+    elif init == "uniform":
+        specs = [inputs.init_uniform(m, seed, frac_dom=0.02) for m in masks]
+    else:
+        specs = [inputs.init_random_all(m, seed) for m in masks]
+    g = Graph.from_masks(masks, brick=brick, periodic=periodic, regions=regions is not None)
+    og = orc.build_batch(masks, brick=brick, periodic=periodic)
+    return g, og, specs
+
+
+def run_gpu(g, specs, params, dt, steps, precision, log_every=0, order=0, regions=None, mobile_all=None):
+    from paper_2406_04177_amd.sim import Simulation
+    sim = Simulation(g, params, precision=precision, step_order=order, regions=regions, mobile_all=mobile_all)
+    sim.set_fields(g.fields_from_specs(specs, torch.float64))
+    log = sim.step(steps, dt, log_every=log_every)
+    torch.cuda.synchronize()
+    return sim, (log.cpu().numpy() if log is not None else None)
+
+
+def run_oracle(og, specs, params, dt, steps, order=0, regions=None):
+    x0 = orc.fields_from_spec(og, specs)
+    w = None
+    if regions is not None:
+        w = orc.edge_weights(og, orc.octant_regions(og), regions)
+    return orc.run(params, dt, og, x0, steps, order=order, w=w)
+
+
+def rel_err_per_pool(got, ref):
+    return [float(np.abs(got[s] - ref[s]).max() / max(np.abs(ref[s]).max(), 1e-300)) for s in range(5)]
+
+
+def test_fp64_48cube_2000_steps_bitwise():
+    """The 48^3 workload: DOM = 1 in 50 voxels, MB = 0.5 in 100, 2000 steps."""
+    p = inputs.ModelParams()
+    dt = inputs.explicit_dt(p)
+    g, og, specs = setup()
+    print("n =", g.n, flush=True)
+    sim, log = run_gpu(g, specs, p, dt, 2000, F64, log_every=100)
+    ref, tot = run_oracle(og, specs, p, dt, 2000)
+    got = sim.fields.cpu().numpy()
+    np.testing.assert_array_equal(got, ref)
+    np.testing.assert_allclose(log, tot[100::100], rtol=1e-13, atol=1e-300)
+
+
+@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("steps", [1, 2, 7, 64])
+def test_fp64_bitwise_orders_and_lengths(order, steps):
+    p = inputs.ModelParams(mu=3e-4, rho=1e-4, v_som=2e-4, v_p4=3e-4)
+    dt = inputs.explicit_dt(p)
+    g, og, specs = setup(shape=(20, 22, 24), init="dense")
+    sim, log = run_gpu(g, specs, p, dt, steps, F64, log_every=1, order=order)
+    ref, tot = run_oracle(og, specs, p, dt, steps, order=order)
+    np.testing.assert_array_equal(sim.fields.cpu().numpy(), ref)
+    np.testing.assert_allclose(log, tot[1:], rtol=1e-13, atol=1e-300)
+
+
+def test_fp64_clamps_all_pools_mobile_and_regions_bitwise():
+    """Large rates make every clamp of Algorithm 1 fire; all pools diffuse with
+    region conductance factors."""
+    p = inputs.ModelParams(D=(3e-10, 1e-9, 2e-10, 5e-10, 1e-10), v_dom=3.0, k_dom=0.05, rho=2.0, mu=1.5,
+                           v_som=4.0, v_p4=6.0)
+    c = [0.6, 0.9, 1.0, 0.7, 0.8, 0.95, 0.65, 0.85]
+    dt = inputs.explicit_dt(p, factor=0.9)
+    g, og, specs = setup(shape=(18, 20, 22), init="dense", regions=c)
+    sim, log = run_gpu(g, specs, p, dt, 30, F64, log_every=3, regions=c)
+    ref, tot = run_oracle(og, specs, p, dt, 30, regions=c)
+    np.testing.assert_array_equal(sim.fields.cpu().numpy(), ref)
+    np.testing.assert_allclose(log, tot[3::3], rtol=1e-13, atol=1e-300)
+
+
+def test_fp64_mortality_to_p4_bitwise():
+    p = inputs.ModelParams(mu=1e-3, rho=1e-4, mort_to_p4=True)
+    dt = inputs.explicit_dt(p)
+    g, og, specs = setup(shape=(16, 16, 16), init="dense")
+    sim, _ = run_gpu(g, specs, p, dt, 20, F64)
+    ref, _ = run_oracle(og, specs, p, dt, 20)
+    np.testing.assert_array_equal(sim.fields.cpu().numpy(), ref)
+
+
+def test_batch_segments_totals():
+    masks = [inputs.synthetic_volume((24, 20, 16), porosity=por, seed=b)
+             for b, por in enumerate((0.12, 0.25, 0.18))]
+    masks.insert(2, np.zeros((24, 20, 16), np.uint8))
+    p = inputs.ModelParams(mu=1e-4, rho=1e-4)
+    dt = inputs.explicit_dt(p, factor=0.8)
+    g, og, specs = setup(masks=masks, init="dense")
+    sim, log = run_gpu(g, specs, p, dt, 40, F64, log_every=1)
+    ref, tot = run_oracle(og, specs, p, dt, 40)
+    np.testing.assert_array_equal(sim.fields.cpu().numpy(), ref)
+    np.testing.assert_allclose(log, tot[1:], rtol=1e-13, atol=1e-300)
+    assert np.all(log[:, 2, :] == 0)          # the empty volume
+    np.testing.assert_allclose(sim.totals(), tot[-1], rtol=1e-13, atol=1e-300)
+
+
+def test_brick_order_equals_raster_after_unpermuting():
+    p = inputs.ModelParams(mu=1e-4, rho=1e-4)
+    dt = inputs.explicit_dt(p)
+    mask = inputs.synthetic_volume((32, 40, 24), seed=4)
+    specs = [inputs.init_random_all(mask, 4)]
+    from paper_2406_04177_amd.graph import Graph
+    gr = Graph.from_masks(mask)
+    gb = Graph.from_masks(mask, brick=8)
+    a, _ = run_gpu(gr, specs, p, dt, 25, F64)
+    b, _ = run_gpu(gb, specs, p, dt, 25, F64)
+    vr, vb = gr.vox.cpu().numpy(), gb.vox.cpu().numpy()
+    perm = np.searchsorted(vr, vb)
+    np.testing.assert_array_equal(b.fields.cpu().numpy(), a.fields.cpu().numpy()[:, perm])
+
+
+@pytest.mark.parametrize("steps", [10, 200])
+def test_fp32_within_1e5(steps):
+    p = inputs.ModelParams()
+    dt = inputs.explicit_dt(p)
+    g, og, specs = setup(init="uniform")
+    sim, log = run_gpu(g, specs, p, dt, steps, F32, log_every=steps)
+    ref, tot = run_oracle(og, specs, p, dt, steps)
+    errs = rel_err_per_pool(sim.fields.cpu().numpy().astype(np.float64), ref)
+    print("fp32 per-pool rel err after", steps, "steps:", errs, flush=True)
+    assert max(errs) <= 1e-5, errs
+    np.testing.assert_allclose(log[-1, :, :5], tot[-1, :, :5], rtol=1e-5)
+
+
+def test_fp32_long_run_error_bound():
+    """Over k steps each pool is rounded to FP32 once per step, so its error
+    grows at most like c * k * 2^-24 relative (c ~ 2 for the few rounded
+    operations per update); checked for 2000 steps with c = 4."""
+    p = inputs.ModelParams()
+    dt = inputs.explicit_dt(p)
+    steps = 2000
+    g, og, specs = setup(init="uniform")
+    sim, log = run_gpu(g, specs, p, dt, steps, F32)
+    ref, _ = run_oracle(og, specs, p, dt, steps)
+    errs = rel_err_per_pool(sim.fields.cpu().numpy().astype(np.float64), ref)
+    print("fp32 per-pool rel err after", steps, "steps:", errs, flush=True)
+    assert max(errs) <= 4 * steps * 2.0 ** -24, errs
+
+
+def test_zero_steps_and_totals_of_initial_state():
+    p = inputs.ModelParams()
+    g, og, specs = setup(shape=(12, 12, 12), init="dense")
+    sim, _ = run_gpu(g, specs, p, inputs.explicit_dt(p), 0, F64)
+    x0 = orc.fields_from_spec(og, specs)
+    np.testing.assert_array_equal(sim.fields.cpu().numpy(), x0)
+    np.testing.assert_allclose(sim.totals(), orc.totals(og, x0), rtol=1e-14, atol=1e-300)
+
+
+def test_unstable_dt_is_refused_and_state_kept():
+    from paper_2406_04177_amd import _lib
+    p = inputs.ModelParams()
+    g, og, specs = setup(shape=(12, 12, 12), init="dense")
+    sim, _ = run_gpu(g, specs, p, inputs.explicit_dt(p), 0, F64)
+    before = sim.fields.clone()
+    with pytest.raises(_lib.VgError) as e:
+        sim.step(5, inputs.explicit_dt(p, factor=1.2))
+    assert e.value.code == _lib.VG_EUNSTABLE
+    assert torch.equal(before, sim.fields)
