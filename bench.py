@@ -35,6 +35,9 @@ METRIC = "pore-voxel species updates/s + HBM GB/s (% peak); adjoint/forward time
 # read the 6-slot int32 neighbour table)
 BYTES_FUSED_F32 = 5 * 4 + 5 * 4 + 6 * 4
 BYTES_FUSED_F64 = 5 * 8 + 5 * 8 + 6 * 4
+# rank-index kernel: the pools, plus the tile's pore-bitmap words (8 B per 32
+# enumeration positions, i.e. 8 / (32 * porosity) ~ 1.5 B per pore voxel at 17 %)
+BYTES_RANK_F32 = 5 * 4 + 5 * 4 + 8.0 / (32 * 0.17)
 
 
 def log(msg):
@@ -76,6 +79,8 @@ def main(argv=None):
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--quick", action="store_true", help="headline only (no extra rows, no CPU baseline)")
     ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--kernel", choices=("auto", "table", "rank"), default="auto",
+                    help="neighbour source of the explicit-step kernel")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
@@ -105,6 +110,8 @@ def main(argv=None):
     log("n = %d pore voxels; graph build %.2f ms (incl. mask upload and host sync)" % (n, ms_graph))
 
     sim = Simulation(g, params, precision="f32", implicit=False, adjoint=False)
+    kernel = {"auto": 0, "table": 1, "rank": 2}[args.kernel]
+    sim.set_kernel(kernel)
     x0 = g.fields_from_specs(spec, torch.float32)
     sim.set_fields(x0)
     sim.step(args.warmup, dt, log_every=100)
@@ -113,7 +120,9 @@ def main(argv=None):
     ms, _ = timed(lambda: sim.step(K, dt, log_every=100, totals_out=tot_log if K >= 100 else None))
     ms_step = ms / K
     vps = n * K / (ms / 1e3)
-    achieved = BYTES_FUSED_F32 * n / (ms_step / 1e3) / 1e9
+    rank_used = kernel == 2 or (kernel == 0 and g.nseg == 1)
+    bpv = BYTES_RANK_F32 if rank_used else BYTES_FUSED_F32
+    achieved = bpv * n / (ms_step / 1e3) / 1e9
     log("explicit FP32: %.4f ms/step, %.3e voxel-steps/s, %.0f GB/s algorithmic" % (ms_step, vps, achieved))
     out = {
         "metric": METRIC,
@@ -127,14 +136,25 @@ def main(argv=None):
                    "voxel_steps_per_s": vps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_step<float, DT, DOM-only> (fused transformation + diffusion)",
-                     "bytes_per_voxel": BYTES_FUSED_F32},
+                     "kernel": "%s<float, DT, DOM-only> (fused transformation + diffusion)"
+                               % ("k_step_rank" if rank_used else "k_step"),
+                     "bytes_per_voxel": bpv},
     }
     del tot_log
 
     if not args.quick:
         rows = {}
         rows["a1_graph_build_ms"] = ms_graph
+        # the other neighbour source on the same state, for comparison
+        other = 1 if kernel != 1 else 2
+        sim.set_kernel(other)
+        sim.step(20, dt)
+        mso, _ = timed(lambda: sim.step(K // 2, dt, log_every=100))
+        rows["fp32_step_%s_kernel" % ("table" if other == 1 else "rank")] = {
+            "ms_per_step": mso / (K // 2), "bytes_per_voxel": BYTES_FUSED_F32 if other == 1 else BYTES_RANK_F32,
+            "achieved_GBs": (BYTES_FUSED_F32 if other == 1 else BYTES_RANK_F32) * n / (mso / (K // 2) / 1e3) / 1e9}
+        log("explicit FP32, %s kernel: %.4f ms/step" % ("table" if other == 1 else "rank", mso / (K // 2)))
+        sim.set_kernel(kernel)
         # plain FP64 step on the same input
         sim64 = Simulation(g, params, precision="f64", implicit=True, adjoint=False)
         sim64.set_fields(x0.double())

@@ -135,6 +135,14 @@ typedef struct vg_desc {
     const uint16_t *rcode_d; /* device [n] region codes or NULL (weights 1)  */
     int32_t mobile_all;      /* 0: only DOM may diffuse; 1: any pool may     */
     int32_t features;        /* bit 0: implicit CG, bit 1: adjoint           */
+    /* Optional, single volume (nseg == 1) only: the rank index built by
+     * vg_count_pores for the same mask, shape, brick and periodic flags as
+     * nbr_d.  With it the explicit step finds neighbours from the pore bitmap
+     * (about 41 B per voxel and step instead of 64 B); NULL = table only. */
+    const void *rank_d;
+    int32_t nx, ny, nz;      /* volume shape of rank_d                       */
+    int32_t brick;           /* enumeration of rank_d (0 raster)             */
+    uint32_t periodic;       /* VG_PERIODIC_* flags the table was built with */
 } vg_desc;
 
 #define VG_FEAT_CG  1
@@ -143,6 +151,13 @@ typedef struct vg_desc {
 /* Creates a handle (host memory only) and sets default parameters. */
 int vg_create(const vg_desc *desc, vg_sim **out);
 int vg_destroy(vg_sim *h);
+/* Neighbour source of the explicit-step kernels: VG_KERNEL_AUTO (rank index
+ * when the descriptor has one, else the table), VG_KERNEL_TABLE or
+ * VG_KERNEL_RANK (VG_EINVAL without a rank index).  Results are identical. */
+#define VG_KERNEL_AUTO  0
+#define VG_KERNEL_TABLE 1
+#define VG_KERNEL_RANK  2
+int vg_set_kernel(vg_sim *h, int variant);
 /* Sets the model parameters (validated: h > 0, K_DOM > 0, rates >= 0,
  * 0 <= beta <= 1, D >= 0; only D[1] may be nonzero unless mobile_all). */
 int vg_set_params(vg_sim *h, const vg_params *p);

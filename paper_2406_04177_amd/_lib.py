@@ -12,7 +12,7 @@ import os
 import threading
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libvgsim.so")
+LIB_PATH = os.environ.get("VGSIM_LIB") or os.path.join(_HERE, "libvgsim.so")
 
 VG_OK, VG_EINVAL, VG_EUNSTABLE, VG_ENOCONV, VG_ENONFINITE, VG_EHIP, VG_ESTATE = 0, -1, -2, -3, -4, -5, -6
 VG_F32, VG_F64 = 0, 1
@@ -20,10 +20,11 @@ VG_ORDER_TD, VG_ORDER_DT = 0, 1
 VG_FORCE = 1
 VG_FEAT_CG, VG_FEAT_ADJ = 1, 2
 VG_NPOOL, VG_NREG, VG_NGRAD = 5, 8, 20
+VG_KERNEL_AUTO, VG_KERNEL_TABLE, VG_KERNEL_RANK = 0, 1, 2
 
 EXPORTS = ("vg_strerror", "vg_last_error", "vg_version", "vg_rank_bytes", "vg_count_pores",
            "vg_build_graph", "vg_lookup", "vg_region_codes", "vg_create", "vg_destroy",
-           "vg_set_params", "vg_set_regions", "vg_alt_elems", "vg_workspace_bytes", "vg_init_state",
+           "vg_set_kernel", "vg_set_params", "vg_set_regions", "vg_alt_elems", "vg_workspace_bytes", "vg_init_state",
            "vg_step_explicit", "vg_solve_implicit_step", "vg_mass_totals", "vg_record", "vg_adjoint",
            "vg_seed_lambda")
 
@@ -44,7 +45,9 @@ class VgParams(ctypes.Structure):
 class VgDesc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nseg", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("seg_off", ctypes.c_void_p), ("nbr_d", ctypes.c_void_p), ("rcode_d", ctypes.c_void_p),
-                ("mobile_all", ctypes.c_int32), ("features", ctypes.c_int32)]
+                ("mobile_all", ctypes.c_int32), ("features", ctypes.c_int32),
+                ("rank_d", ctypes.c_void_p), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("brick", ctypes.c_int32), ("periodic", ctypes.c_uint32)]
 
 
 _lock = threading.Lock()
@@ -74,6 +77,7 @@ def load():
             "vg_region_codes": (I, [P, I64, I, I, I, U, P, P]),
             "vg_create": (I, [ctypes.POINTER(VgDesc), ctypes.POINTER(P)]),
             "vg_destroy": (I, [P]),
+            "vg_set_kernel": (I, [P, I]),
             "vg_set_params": (I, [P, ctypes.POINTER(VgParams)]),
             "vg_set_regions": (I, [P, ctypes.POINTER(D)]),
             "vg_alt_elems": (I, [P, ctypes.POINTER(I64)]),

@@ -147,8 +147,9 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces 
     for (int q = 0; q < kG; q++) g[q] = 0.0;
     const int64_t n = A.n;
 
-    for (int64_t t = xcd_tile(blockIdx.x, gridDim.x); t < A.ntiles; t += gridDim.x) {
-        const int64_t i = t * kTile + threadIdx.x;
+    for (int64_t t = xcd_tile(blockIdx.x, gridDim.x); t < A.ntiles; t += gridDim.x)
+    for (int v = 0; v < kVPT; v++) {
+        const int64_t i = t * kTile + v * kBlock + threadIdx.x;
         if (i >= n) continue;
         int32_t j[6];
 #pragma unroll
@@ -176,15 +177,14 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces 
             for (int s = 0; s < VG_NPOOL; s++) {
                 if (!mobile<MOB>(s)) continue;
                 const R xi = x[s];
+                R v[6];
+#pragma unroll
+                for (int k = 0; k < 6; k++) v[k] = A.st[(int64_t)s * n + (j[k] >= 0 ? (int64_t)j[k] : i)];
                 R d[6];
 #pragma unroll
                 for (int k = 0; k < 6; k++) {
-                    R tt = R(0);
-                    if (j[k] >= 0) {
-                        const R diff = A.st[(int64_t)s * n + j[k]] - xi;
-                        tt = REG ? w[k] * diff : diff;
-                    }
-                    d[k] = tt;
+                    const R diff = v[k] - xi;
+                    d[k] = j[k] >= 0 ? (REG ? w[k] * diff : diff) : R(0);
                 }
                 x[s] = xi + C.a[s] * (((d[0] + d[1]) + (d[2] + d[3])) + (d[4] + d[5]));
             }
@@ -198,12 +198,15 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces 
 #pragma unroll
         for (int s = 0; s < VG_NPOOL; s++) {
             const R li = A.lin[(int64_t)s * n + i];
+            R lj[6];
+#pragma unroll
+            for (int k = 0; k < 6; k++) lj[k] = A.lin[(int64_t)s * n + (j[k] >= 0 ? (int64_t)j[k] : i)];
             R sum = R(0);
             double creg_own = 0.0, creg_x[3] = {0.0, 0.0, 0.0};
 #pragma unroll
             for (int k = 0; k < 6; k++) {
                 if (j[k] < 0) continue;
-                const R dl = A.lin[(int64_t)s * n + j[k]] - li;
+                const R dl = lj[k] - li;
                 sum += w[k] * dl;
                 if (REG && mobile<MOB>(s)) {
                     const double tk = (double)dl;
@@ -279,15 +282,17 @@ template <typename R>
 __global__ __launch_bounds__(kBlock) void k_seed(R *__restrict__ lam, const double *__restrict__ seed, int zero,
                                                  Pieces pc, int64_t n) {
     const int64_t t = blockIdx.x;
-    const int64_t i = t * kTile + threadIdx.x;
-    if (i >= n) return;
-    int32_t p = pc.piece_first[t];
-    while (p + 1 < pc.piece_first[t + 1] && i >= pc.piece_lo[p + 1]) p++;
-    const double *sd = seed + (int64_t)pc.piece_seg[p] * VG_NPOOL;
+    for (int v = 0; v < kVPT; v++) {
+        const int64_t i = t * kTile + v * kBlock + threadIdx.x;
+        if (i >= n) return;
+        int32_t p = pc.piece_first[t];
+        while (p + 1 < pc.piece_first[t + 1] && i >= pc.piece_lo[p + 1]) p++;
+        const double *sd = seed + (int64_t)pc.piece_seg[p] * VG_NPOOL;
 #pragma unroll
-    for (int s = 0; s < VG_NPOOL; s++) {
-        const int64_t e = (int64_t)s * n + i;
-        lam[e] = (R)((zero ? 0.0 : (double)lam[e]) + sd[s]);
+        for (int s = 0; s < VG_NPOOL; s++) {
+            const int64_t e = (int64_t)s * n + i;
+            lam[e] = (R)((zero ? 0.0 : (double)lam[e]) + sd[s]);
+        }
     }
 }
 

@@ -47,6 +47,10 @@ size_t layout(vg_sim *h, char *base) {
     h->seg_first = (int32_t *)take(sizeof(int32_t) * (size_t)(h->nseg + 1));
     h->part = (double *)take(sizeof(double) * VG_NPOOL * (size_t)h->npieces);
     h->tot_tmp = (double *)take(sizeof(double) * 6 * (size_t)h->nseg);
+    h->chunk_first = (int32_t *)take(sizeof(int32_t) * (size_t)(h->nchunks + 1));
+    h->seg_chunk = (int32_t *)take(sizeof(int32_t) * (size_t)(h->nseg + 1));
+    h->chunk_part = (double *)take(sizeof(double) * VG_NPOOL * (size_t)h->nchunks);
+    h->tile_word = (int32_t *)take(sizeof(int32_t) * (size_t)(h->ntiles > 0 ? h->ntiles : 1));
     const size_t nd = sizeof(double) * (size_t)h->n;
     if (h->features & VG_FEAT_CG) {
         h->cg_y = (double *)take(nd);
@@ -95,6 +99,16 @@ void make_pieces(vg_sim *h) {
     // empty segments take the start of the next non-empty one
     for (int gg = h->nseg - 1; gg >= 0; gg--)
         if (h->seg_off[gg] == h->seg_off[gg + 1]) h->seg_first_h[gg] = h->seg_first_h[gg + 1];
+    // totals chunks: runs of up to kChunk pieces inside one segment
+    h->chunk_first_h.clear();
+    h->seg_chunk_h.assign((size_t)h->nseg + 1, 0);
+    for (int gg = 0; gg < h->nseg; gg++) {
+        h->seg_chunk_h[gg] = (int32_t)h->chunk_first_h.size();
+        for (int32_t p = h->seg_first_h[gg]; p < h->seg_first_h[gg + 1]; p += kChunk) h->chunk_first_h.push_back(p);
+    }
+    h->nchunks = (int32_t)h->chunk_first_h.size();
+    h->seg_chunk_h[h->nseg] = h->nchunks;
+    h->chunk_first_h.push_back(h->npieces);
     const int64_t cap = 2048;
     h->cg_blocks = (int)(h->ntiles < cap ? (h->ntiles > 0 ? h->ntiles : 1) : cap);
     h->adj_blocks = h->cg_blocks;
@@ -180,6 +194,18 @@ extern "C" int vg_create(const vg_desc *d, vg_sim **out) {
     h->seg_off.assign(d->seg_off, d->seg_off + d->nseg + 1);
     h->nbr = d->nbr_d;
     h->rcode = d->rcode_d;
+    if (d->rank_d) {
+        Geom g;
+        int rc = make_geom(d->nx, d->ny, d->nz, d->brick, &g);
+        if (rc) { delete h; return rc; }
+        if (d->nseg != 1 || g.npos >= ((int64_t)1 << 31) || d->periodic > 7u) {
+            set_error("a rank index needs a single volume of fewer than 2^31 positions");
+            delete h;
+            return VG_EINVAL;
+        }
+        h->rank = d->rank_d;
+        h->nx = d->nx; h->ny = d->ny; h->nz = d->nz; h->brick = d->brick; h->periodic = d->periodic;
+    }
     vg_params p{};
     p.D[1] = 1e-9;
     p.h = 24e-6;
@@ -194,6 +220,16 @@ extern "C" int vg_create(const vg_desc *d, vg_sim **out) {
 
 extern "C" int vg_destroy(vg_sim *h) {
     delete h;
+    return VG_OK;
+}
+
+extern "C" int vg_set_kernel(vg_sim *h, int variant) {
+    if (!h) { set_error("handle is NULL"); return VG_EINVAL; }
+    if (variant < VG_KERNEL_AUTO || variant > VG_KERNEL_RANK || (variant == VG_KERNEL_RANK && !h->rank)) {
+        set_error("kernel variant %d not available", variant);
+        return VG_EINVAL;
+    }
+    h->kernel = variant;
     return VG_OK;
 }
 
@@ -224,6 +260,7 @@ extern "C" int vg_workspace_bytes(const vg_sim *h, size_t *bytes) {
     vg_sim tmp;
     tmp.n = h->n; tmp.nseg = h->nseg; tmp.prec = h->prec; tmp.features = h->features;
     tmp.ntiles = h->ntiles; tmp.npieces = h->npieces; tmp.cg_blocks = h->cg_blocks; tmp.adj_blocks = h->adj_blocks;
+    tmp.nchunks = h->nchunks;
     *bytes = layout(&tmp, nullptr);
     return VG_OK;
 }
@@ -253,6 +290,11 @@ extern "C" int vg_init_state(vg_sim *h, void *fields_d, void *alt_d, void *work_
                                         hipMemcpyHostToDevice, s), "upload piece segments"))) return rc;
     if ((rc = hip_status(hipMemcpyAsync(h->seg_first, h->seg_first_h.data(), sizeof(int32_t) * h->seg_first_h.size(),
                                         hipMemcpyHostToDevice, s), "upload segments"))) return rc;
+    if ((rc = hip_status(hipMemcpyAsync(h->chunk_first, h->chunk_first_h.data(), sizeof(int32_t) * h->chunk_first_h.size(),
+                                        hipMemcpyHostToDevice, s), "upload chunks"))) return rc;
+    if ((rc = hip_status(hipMemcpyAsync(h->seg_chunk, h->seg_chunk_h.data(), sizeof(int32_t) * h->seg_chunk_h.size(),
+                                        hipMemcpyHostToDevice, s), "upload segment chunks"))) return rc;
+    if ((rc = launch_tile_words(h, s))) return rc;
     // the host tables must outlive the asynchronous copies
     if ((rc = hip_status(hipStreamSynchronize(s), "synchronise"))) return rc;
     h->bound = true;

@@ -44,18 +44,24 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs A, const R *__restric
     if (threadIdx.x < VG_NREG) cl[threadIdx.x] = A.c[threadIdx.x];
     __syncthreads();
     double acc[3] = {0.0, 0.0, 0.0};   // r.z, r.r, b.b
-    for (int64_t t = xcd_tile(blockIdx.x, gridDim.x); t < A.ntiles; t += gridDim.x) {
-        const int64_t i = t * kTile + threadIdx.x;
+    for (int64_t t = xcd_tile(blockIdx.x, gridDim.x); t < A.ntiles; t += gridDim.x)
+    for (int v = 0; v < kVPT; v++) {
+        const int64_t i = t * kTile + v * kBlock + threadIdx.x;
         if (i >= A.n) continue;
         const double b = (double)field[i];
+        int32_t j[6];
+        double fj[6];
+#pragma unroll
+        for (int k = 0; k < 6; k++) j[k] = A.nbr[(int64_t)k * A.n + i];
+#pragma unroll
+        for (int k = 0; k < 6; k++) fj[k] = (double)field[j[k] >= 0 ? (int64_t)j[k] : i];
         double s = 0.0, deg = 0.0;
 #pragma unroll
         for (int k = 0; k < 6; k++) {
-            const int32_t j = A.nbr[(int64_t)k * A.n + i];
-            if (j < 0) continue;
+            if (j[k] < 0) continue;
             const double w = weight(A.rcode, cl, i, k, REG);
             deg += w;
-            s += w * (b - (double)field[j]);
+            s += w * (b - fj[k]);
         }
         const double mi = 1.0 / (1.0 + A.a * deg);
         const double ri = b - (b + A.a * s);
@@ -88,17 +94,26 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(CgArgs A, const double *__re
     __syncthreads();
     const double beta = scal[S_BETA];
     double acc[1] = {0.0};
-    for (int64_t t = xcd_tile(blockIdx.x, gridDim.x); t < A.ntiles; t += gridDim.x) {
-        const int64_t i = t * kTile + threadIdx.x;
+    for (int64_t t = xcd_tile(blockIdx.x, gridDim.x); t < A.ntiles; t += gridDim.x)
+    for (int v = 0; v < kVPT; v++) {
+        const int64_t i = t * kTile + v * kBlock + threadIdx.x;
         if (i >= A.n) continue;
         const double pi = z[i] + beta * pold[i];
+        int32_t j[6];
+        double zj[6], pj[6];
+#pragma unroll
+        for (int k = 0; k < 6; k++) j[k] = A.nbr[(int64_t)k * A.n + i];
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            const int64_t jj = j[k] >= 0 ? (int64_t)j[k] : i;
+            zj[k] = z[jj];
+            pj[k] = pold[jj];
+        }
         double s = 0.0;
 #pragma unroll
         for (int k = 0; k < 6; k++) {
-            const int32_t j = A.nbr[(int64_t)k * A.n + i];
-            if (j < 0) continue;
-            const double pj = z[j] + beta * pold[j];
-            s += weight(A.rcode, cl, i, k, REG) * (pi - pj);
+            if (j[k] < 0) continue;
+            s += weight(A.rcode, cl, i, k, REG) * (pi - (zj[k] + beta * pj[k]));
         }
         const double qi = pi + A.a * s;
         pnew[i] = pi;
@@ -118,8 +133,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, int64_t ntiles,
     __shared__ double lds[kWaves * 2];
     const double alpha = scal[S_ALPHA];
     double acc[2] = {0.0, 0.0};
-    for (int64_t t = xcd_tile(blockIdx.x, gridDim.x); t < ntiles; t += gridDim.x) {
-        const int64_t i = t * kTile + threadIdx.x;
+    for (int64_t t = xcd_tile(blockIdx.x, gridDim.x); t < ntiles; t += gridDim.x)
+    for (int v = 0; v < kVPT; v++) {
+        const int64_t i = t * kTile + v * kBlock + threadIdx.x;
         if (i >= n) continue;
         y[i] += alpha * p[i];
         const double ri = r[i] - alpha * q[i];

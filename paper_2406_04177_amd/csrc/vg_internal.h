@@ -130,7 +130,82 @@ struct Pieces {
     int32_t npieces;
 };
 
-constexpr int kTile = kBlock;   // voxels per step-kernel tile (one per thread)
+#ifndef VG_VPT
+#define VG_VPT 2
+#endif
+constexpr int kVPT = VG_VPT;            // voxels per thread in a tile
+constexpr int kTile = kBlock * kVPT;    // voxels per tile (one tile per block)
+constexpr int kChunk = 256;             // pieces per first-stage totals chunk
+
+// Division by a run-time invariant 32-bit divisor with one multiply-high
+// (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", PLDI 1994, Fig. 4.1).  Exact for every n < 2^32.
+struct FastDiv {
+    uint32_t d = 1, m = 1, s1 = 0, s2 = 0;
+    __host__ void init(uint32_t div) {
+        d = div;
+        uint32_t l = 0;
+        while (l < 32 && (1ull << l) < div) l++;
+        m = (uint32_t)((((1ull << 32) * ((1ull << l) - div)) / div) + 1);
+        s1 = l < 1 ? l : 1;
+        s2 = l > 1 ? l - 1 : 0;
+    }
+    __device__ __forceinline__ uint32_t div(uint32_t n) const {
+        const uint32_t t1 = __umulhi(m, n);
+        return (t1 + ((n - t1) >> s1)) >> s2;
+    }
+};
+
+// Geometry of the enumeration with fast divisions, for the kernels that find
+// neighbours through the rank index instead of the neighbour table.
+struct RGeom {
+    Geom g;
+    FastDiv fnx, fny, fb, fb2, fb3, fnbx, fnby;
+    unsigned periodic;
+    const RankWord *rank;
+    const int32_t *tile_word;   // word holding the first compact index of each tile
+};
+
+__device__ __forceinline__ void rg_xyz(const RGeom &G, uint32_t p, int &x, int &y, int &z) {
+    if (G.g.b <= 0) {
+        const uint32_t q1 = G.fnx.div(p);
+        x = (int)(p - q1 * G.fnx.d);
+        const uint32_t q2 = G.fny.div(q1);
+        y = (int)(q1 - q2 * G.fny.d);
+        z = (int)q2;
+        return;
+    }
+    const uint32_t blin = G.fb3.div(p);
+    const uint32_t loc = p - blin * G.fb3.d;
+    const uint32_t r1 = G.fnbx.div(blin);
+    const int bx = (int)(blin - r1 * G.fnbx.d);
+    const uint32_t r2 = G.fnby.div(r1);
+    const int by = (int)(r1 - r2 * G.fnby.d);
+    const int bz = (int)r2;
+    const uint32_t lz = G.fb2.div(loc);
+    const uint32_t rem = loc - lz * G.fb2.d;
+    const uint32_t ly = G.fb.div(rem);
+    const uint32_t lx = rem - ly * G.fb.d;
+    const int b = G.g.b;
+    x = bx * b + (int)lx;
+    y = by * b + (int)ly;
+    z = bz * b + (int)lz;
+}
+
+__device__ __forceinline__ uint32_t rg_pos(const RGeom &G, int x, int y, int z) {
+    if (G.g.b <= 0) return (uint32_t)x + G.fnx.d * ((uint32_t)y + G.fny.d * (uint32_t)z);
+    const uint32_t b = (uint32_t)G.g.b;
+    const uint32_t bx = G.fb.div((uint32_t)x), by = G.fb.div((uint32_t)y), bz = G.fb.div((uint32_t)z);
+    const uint32_t lx = (uint32_t)x - bx * b, ly = (uint32_t)y - by * b, lz = (uint32_t)z - bz * b;
+    const uint32_t blin = (bz * (uint32_t)G.g.nby + by) * (uint32_t)G.g.nbx + bx;
+    return blin * G.fb3.d + (lz * b + ly) * b + lx;
+}
+
+__device__ __forceinline__ int32_t rank_lookup(const RankWord &wd, uint32_t p) {
+    const uint32_t bit = p & 31u;
+    if (!((wd.bits >> bit) & 1u)) return -1;
+    return (int32_t)(wd.before + (uint32_t)__popc(wd.bits & ((1u << bit) - 1u)));
+}
 
 
 }  // namespace vg
@@ -159,6 +234,16 @@ struct vg_sim {
     // reduction tiles and pieces (host copies and device views)
     int64_t ntiles = 0;
     int32_t npieces = 0;
+    int32_t nchunks = 0;
+    std::vector<int32_t> chunk_first_h, seg_chunk_h;
+    int32_t *chunk_first = nullptr, *seg_chunk = nullptr;
+    double *chunk_part = nullptr;   // [nchunks][5]
+    // rank-index neighbours (single volume)
+    const void *rank = nullptr;
+    int nx = 0, ny = 0, nz = 0, brick = 0;
+    unsigned periodic = 0;
+    int32_t *tile_word = nullptr;   // [ntiles]
+    int kernel = 0;                 // 0 auto, 1 neighbour table, 2 rank index
     std::vector<int32_t> piece_first_h, piece_seg_h, seg_first_h;
     std::vector<int64_t> piece_lo_h;
     int32_t *piece_first = nullptr, *piece_seg = nullptr, *seg_first = nullptr;
@@ -189,6 +274,8 @@ int launch_pass(vg_sim *h, int mode, int tot, double dt, hipStream_t s);
 int launch_pass_bufs(vg_sim *h, int mode, int tot, double dt, const void *const src[VG_NPOOL],
                      void *const dst[VG_NPOOL], hipStream_t s);
 int launch_totals_finalize(vg_sim *h, double *out_rows, hipStream_t s);
+int launch_tile_words(vg_sim *h, hipStream_t s);
+bool use_rank(const vg_sim *h);
 int restore_canonical(vg_sim *h, hipStream_t s);
 // vg_cg.hip
 int run_cg(vg_sim *h, int pool, double a, double rtol, int max_iter, int *iters, double *relres,

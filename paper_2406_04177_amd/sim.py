@@ -36,7 +36,7 @@ class Simulation:
 
     def __init__(self, graph: Graph, params: ModelParams, precision: str = "f32",
                  implicit: bool = True, adjoint: bool = False, mobile_all=None,
-                 step_order: int = _lib.VG_ORDER_TD, regions=None, stream=None):
+                 step_order: int = _lib.VG_ORDER_TD, regions=None, stream=None, rank_neighbours: bool = True):
         self.L = _lib.load()
         self.graph = graph
         self.precision = precision
@@ -59,6 +59,11 @@ class Simulation:
         desc.rcode_d = graph.rcode.data_ptr() if (use_regions and graph.n) else None
         desc.mobile_all = 1 if mobile_all else 0
         desc.features = features
+        if graph.nseg == 1 and graph.n and rank_neighbours:
+            nz, ny, nx = graph.shape
+            desc.rank_d = graph.ranks[0].data_ptr()
+            desc.nx, desc.ny, desc.nz = nx, ny, nz
+            desc.brick, desc.periodic = graph.brick, graph.periodic
         h = ctypes.c_void_p()
         _lib.check(self.L.vg_create(ctypes.byref(desc), ctypes.byref(h)), "vg_create")
         self.h = h
@@ -79,6 +84,10 @@ class Simulation:
     # ------------------------------------------------------------------ setup
     def _sp(self):
         return _lib.stream_ptr(self.stream)
+
+    def set_kernel(self, variant: int):
+        """Neighbour source of the explicit step: _lib.VG_KERNEL_AUTO / TABLE / RANK."""
+        _lib.check(self.L.vg_set_kernel(self.h, int(variant)), "vg_set_kernel")
 
     def set_params(self, params: ModelParams):
         self.params = params

@@ -34,9 +34,15 @@ def setup(shape=(48, 48, 48), seed=0, init="spots", params=None, masks=None, reg
     return g, og, specs
 
 
-def run_gpu(g, specs, params, dt, steps, precision, log_every=0, order=0, regions=None, mobile_all=None):
+TABLE, RANK = 1, 2      # neighbour source of the step kernels (identical results)
+KERNELS = pytest.mark.parametrize("kernel", [TABLE, RANK], ids=["table", "rank"])
+
+
+def run_gpu(g, specs, params, dt, steps, precision, log_every=0, order=0, regions=None, mobile_all=None,
+            kernel=0):
     from paper_2406_04177_amd.sim import Simulation
     sim = Simulation(g, params, precision=precision, step_order=order, regions=regions, mobile_all=mobile_all)
+    sim.set_kernel(kernel)
     sim.set_fields(g.fields_from_specs(specs, torch.float64))
     log = sim.step(steps, dt, log_every=log_every)
     torch.cuda.synchronize()
@@ -55,32 +61,35 @@ def rel_err_per_pool(got, ref):
     return [float(np.abs(got[s] - ref[s]).max() / max(np.abs(ref[s]).max(), 1e-300)) for s in range(5)]
 
 
-def test_fp64_48cube_2000_steps_bitwise():
+@KERNELS
+def test_fp64_48cube_2000_steps_bitwise(kernel):
     """The 48^3 workload: DOM = 1 in 50 voxels, MB = 0.5 in 100, 2000 steps."""
     p = inputs.ModelParams()
     dt = inputs.explicit_dt(p)
     g, og, specs = setup()
     print("n =", g.n, flush=True)
-    sim, log = run_gpu(g, specs, p, dt, 2000, F64, log_every=100)
+    sim, log = run_gpu(g, specs, p, dt, 2000, F64, log_every=100, kernel=kernel)
     ref, tot = run_oracle(og, specs, p, dt, 2000)
     got = sim.fields.cpu().numpy()
     np.testing.assert_array_equal(got, ref)
     np.testing.assert_allclose(log, tot[100::100], rtol=1e-13, atol=1e-300)
 
 
+@KERNELS
 @pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("steps", [1, 2, 7, 64])
-def test_fp64_bitwise_orders_and_lengths(order, steps):
+def test_fp64_bitwise_orders_and_lengths(order, steps, kernel):
     p = inputs.ModelParams(mu=3e-4, rho=1e-4, v_som=2e-4, v_p4=3e-4)
     dt = inputs.explicit_dt(p)
     g, og, specs = setup(shape=(20, 22, 24), init="dense")
-    sim, log = run_gpu(g, specs, p, dt, steps, F64, log_every=1, order=order)
+    sim, log = run_gpu(g, specs, p, dt, steps, F64, log_every=1, order=order, kernel=kernel)
     ref, tot = run_oracle(og, specs, p, dt, steps, order=order)
     np.testing.assert_array_equal(sim.fields.cpu().numpy(), ref)
     np.testing.assert_allclose(log, tot[1:], rtol=1e-13, atol=1e-300)
 
 
-def test_fp64_clamps_all_pools_mobile_and_regions_bitwise():
+@KERNELS
+def test_fp64_clamps_all_pools_mobile_and_regions_bitwise(kernel):
     """Large rates make every clamp of Algorithm 1 fire; all pools diffuse with
     region conductance factors."""
     p = inputs.ModelParams(D=(3e-10, 1e-9, 2e-10, 5e-10, 1e-10), v_dom=3.0, k_dom=0.05, rho=2.0, mu=1.5,
@@ -88,17 +97,18 @@ def test_fp64_clamps_all_pools_mobile_and_regions_bitwise():
     c = [0.6, 0.9, 1.0, 0.7, 0.8, 0.95, 0.65, 0.85]
     dt = inputs.explicit_dt(p, factor=0.9)
     g, og, specs = setup(shape=(18, 20, 22), init="dense", regions=c)
-    sim, log = run_gpu(g, specs, p, dt, 30, F64, log_every=3, regions=c)
+    sim, log = run_gpu(g, specs, p, dt, 30, F64, log_every=3, regions=c, kernel=kernel)
     ref, tot = run_oracle(og, specs, p, dt, 30, regions=c)
     np.testing.assert_array_equal(sim.fields.cpu().numpy(), ref)
     np.testing.assert_allclose(log, tot[3::3], rtol=1e-13, atol=1e-300)
 
 
-def test_fp64_mortality_to_p4_bitwise():
+@KERNELS
+def test_fp64_mortality_to_p4_bitwise(kernel):
     p = inputs.ModelParams(mu=1e-3, rho=1e-4, mort_to_p4=True)
     dt = inputs.explicit_dt(p)
     g, og, specs = setup(shape=(16, 16, 16), init="dense")
-    sim, _ = run_gpu(g, specs, p, dt, 20, F64)
+    sim, _ = run_gpu(g, specs, p, dt, 20, F64, kernel=kernel)
     ref, _ = run_oracle(og, specs, p, dt, 20)
     np.testing.assert_array_equal(sim.fields.cpu().numpy(), ref)
 
@@ -126,19 +136,21 @@ def test_brick_order_equals_raster_after_unpermuting():
     from paper_2406_04177_amd.graph import Graph
     gr = Graph.from_masks(mask)
     gb = Graph.from_masks(mask, brick=8)
-    a, _ = run_gpu(gr, specs, p, dt, 25, F64)
-    b, _ = run_gpu(gb, specs, p, dt, 25, F64)
+    a, _ = run_gpu(gr, specs, p, dt, 25, F64, kernel=TABLE)
     vr, vb = gr.vox.cpu().numpy(), gb.vox.cpu().numpy()
     perm = np.searchsorted(vr, vb)
-    np.testing.assert_array_equal(b.fields.cpu().numpy(), a.fields.cpu().numpy()[:, perm])
+    for kernel in (TABLE, RANK):
+        b, _ = run_gpu(gb, specs, p, dt, 25, F64, kernel=kernel)
+        np.testing.assert_array_equal(b.fields.cpu().numpy(), a.fields.cpu().numpy()[:, perm])
 
 
+@KERNELS
 @pytest.mark.parametrize("steps", [10, 200])
-def test_fp32_within_1e5(steps):
+def test_fp32_within_1e5(steps, kernel):
     p = inputs.ModelParams()
     dt = inputs.explicit_dt(p)
     g, og, specs = setup(init="uniform")
-    sim, log = run_gpu(g, specs, p, dt, steps, F32, log_every=steps)
+    sim, log = run_gpu(g, specs, p, dt, steps, F32, log_every=steps, kernel=kernel)
     ref, tot = run_oracle(og, specs, p, dt, steps)
     errs = rel_err_per_pool(sim.fields.cpu().numpy().astype(np.float64), ref)
     print("fp32 per-pool rel err after", steps, "steps:", errs, flush=True)
@@ -146,7 +158,8 @@ def test_fp32_within_1e5(steps):
     np.testing.assert_allclose(log[-1, :, :5], tot[-1, :, :5], rtol=1e-5)
 
 
-def test_fp32_long_run_error_bound():
+@KERNELS
+def test_fp32_long_run_error_bound(kernel):
     """Over k steps each pool is rounded to FP32 once per step, so its error
     grows at most like c * k * 2^-24 relative (c ~ 2 for the few rounded
     operations per update); checked for 2000 steps with c = 4."""
@@ -154,7 +167,7 @@ def test_fp32_long_run_error_bound():
     dt = inputs.explicit_dt(p)
     steps = 2000
     g, og, specs = setup(init="uniform")
-    sim, log = run_gpu(g, specs, p, dt, steps, F32)
+    sim, log = run_gpu(g, specs, p, dt, steps, F32, kernel=kernel)
     ref, _ = run_oracle(og, specs, p, dt, steps)
     errs = rel_err_per_pool(sim.fields.cpu().numpy().astype(np.float64), ref)
     print("fp32 per-pool rel err after", steps, "steps:", errs, flush=True)
@@ -180,3 +193,39 @@ def test_unstable_dt_is_refused_and_state_kept():
         sim.step(5, inputs.explicit_dt(p, factor=1.2))
     assert e.value.code == _lib.VG_EUNSTABLE
     assert torch.equal(before, sim.fields)
+
+
+@pytest.mark.parametrize("periodic,brick", [(7, 0), (5, 4), (0, 3)])
+def test_rank_kernel_equals_table_kernel_bitwise(periodic, brick):
+    """The two neighbour sources give bit-identical steps, also with periodic
+    axes, ragged bricks and regions."""
+    p = inputs.ModelParams(D=(1e-10, 1e-9, 0, 2e-10, 0), mu=1e-4, rho=1e-4)
+    c = [0.6, 0.9, 1.0, 0.7, 0.8, 0.95, 0.65, 0.85]
+    dt = inputs.explicit_dt(p)
+    mask = inputs.synthetic_volume((21, 26, 19), seed=6)
+    specs = [inputs.init_random_all(mask, 6)]
+    from paper_2406_04177_amd.graph import Graph
+    g = Graph.from_masks(mask, brick=brick, periodic=periodic, regions=True)
+    a, la = run_gpu(g, specs, p, dt, 17, F64, log_every=4, regions=c, kernel=TABLE)
+    b, lb = run_gpu(g, specs, p, dt, 17, F64, log_every=4, regions=c, kernel=RANK)
+    np.testing.assert_array_equal(a.fields.cpu().numpy(), b.fields.cpu().numpy())
+    np.testing.assert_allclose(la, lb, rtol=1e-14)
+    og = orc.build_graph(mask, brick=brick, periodic=periodic)
+    ref, _ = run_oracle(og, specs, p, dt, 17, regions=c)
+    np.testing.assert_array_equal(b.fields.cpu().numpy(), ref)
+
+
+def test_rank_kernel_ragged_tiles():
+    """n not a multiple of the tile, one-voxel and two-voxel volumes."""
+    p = inputs.ModelParams(mu=1e-4, rho=1e-4)
+    dt = inputs.explicit_dt(p)
+    from paper_2406_04177_amd.graph import Graph
+    for shape, por in (((1, 1, 1), 1.0), ((1, 1, 2), 1.0), ((9, 10, 11), 0.7), ((40, 3, 50), 0.5)):
+        rng = np.random.default_rng(sum(shape))
+        mask = (rng.random(shape) < por).astype(np.uint8)
+        specs = [inputs.init_random_all(mask, 1)]
+        g = Graph.from_masks(mask)
+        og = orc.build_graph(mask)
+        sim, _ = run_gpu(g, specs, p, dt, 9, F64, kernel=RANK)
+        ref, _ = run_oracle(og, specs, p, dt, 9)
+        np.testing.assert_array_equal(sim.fields.cpu().numpy(), ref)
