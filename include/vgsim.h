@@ -137,9 +137,12 @@ typedef struct vg_desc {
     int32_t features;        /* bit 0: implicit CG, bit 1: adjoint           */
     /* Optional, single volume (nseg == 1) only: the rank index built by
      * vg_count_pores for the same mask, shape, brick and periodic flags as
-     * nbr_d.  With it the explicit step finds neighbours from the pore bitmap
-     * (about 41 B per voxel and step instead of 64 B); NULL = table only. */
+     * nbr_d, and the compacted list vox_d.  With them (and no periodic axis,
+     * every dimension <= 1024) the explicit step finds neighbours from the
+     * pore bitmap (about 46 B per voxel and step instead of 64 B); the
+     * workspace then holds a 4-byte geometry word per voxel.  NULL = table. */
     const void *rank_d;
+    const int32_t *vox_d;
     int32_t nx, ny, nz;      /* volume shape of rank_d                       */
     int32_t brick;           /* enumeration of rank_d (0 raster)             */
     uint32_t periodic;       /* VG_PERIODIC_* flags the table was built with */
@@ -152,8 +155,8 @@ typedef struct vg_desc {
 int vg_create(const vg_desc *desc, vg_sim **out);
 int vg_destroy(vg_sim *h);
 /* Neighbour source of the explicit-step kernels: VG_KERNEL_AUTO (rank index
- * when the descriptor has one, else the table), VG_KERNEL_TABLE or
- * VG_KERNEL_RANK (VG_EINVAL without a rank index).  Results are identical. */
+ * when the descriptor has a usable one, else the table), VG_KERNEL_TABLE or
+ * VG_KERNEL_RANK (VG_EINVAL without one).  Results are bit-identical. */
 #define VG_KERNEL_AUTO  0
 #define VG_KERNEL_TABLE 1
 #define VG_KERNEL_RANK  2

@@ -46,7 +46,7 @@ class VgDesc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nseg", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("seg_off", ctypes.c_void_p), ("nbr_d", ctypes.c_void_p), ("rcode_d", ctypes.c_void_p),
                 ("mobile_all", ctypes.c_int32), ("features", ctypes.c_int32),
-                ("rank_d", ctypes.c_void_p), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("rank_d", ctypes.c_void_p), ("vox_d", ctypes.c_void_p), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("nz", ctypes.c_int32), ("brick", ctypes.c_int32), ("periodic", ctypes.c_uint32)]
 
 

@@ -50,7 +50,7 @@ size_t layout(vg_sim *h, char *base) {
     h->chunk_first = (int32_t *)take(sizeof(int32_t) * (size_t)(h->nchunks + 1));
     h->seg_chunk = (int32_t *)take(sizeof(int32_t) * (size_t)(h->nseg + 1));
     h->chunk_part = (double *)take(sizeof(double) * VG_NPOOL * (size_t)h->nchunks);
-    h->tile_word = (int32_t *)take(sizeof(int32_t) * (size_t)(h->ntiles > 0 ? h->ntiles : 1));
+    h->geo = h->rank ? (uint32_t *)take(sizeof(uint32_t) * (size_t)h->n) : nullptr;
     const size_t nd = sizeof(double) * (size_t)h->n;
     if (h->features & VG_FEAT_CG) {
         h->cg_y = (double *)take(nd);
@@ -198,12 +198,17 @@ extern "C" int vg_create(const vg_desc *d, vg_sim **out) {
         Geom g;
         int rc = make_geom(d->nx, d->ny, d->nz, d->brick, &g);
         if (rc) { delete h; return rc; }
-        if (d->nseg != 1 || g.npos >= ((int64_t)1 << 31) || d->periodic > 7u) {
-            set_error("a rank index needs a single volume of fewer than 2^31 positions");
+        if (d->nseg != 1 || g.npos >= ((int64_t)1 << 31) || d->periodic > 7u || !d->vox_d) {
+            set_error("a rank index needs a single volume of fewer than 2^31 positions and vox_d");
             delete h;
             return VG_EINVAL;
         }
-        h->rank = d->rank_d;
+        // the rank-index kernel covers volumes without periodic axes and with
+        // every dimension <= 1024 (10-bit coordinates); others use the table
+        if (d->periodic == 0 && d->nx <= 1024 && d->ny <= 1024 && d->nz <= 1024) {
+            h->rank = d->rank_d;
+            h->vox = d->vox_d;
+        }
         h->nx = d->nx; h->ny = d->ny; h->nz = d->nz; h->brick = d->brick; h->periodic = d->periodic;
     }
     vg_params p{};
@@ -261,6 +266,7 @@ extern "C" int vg_workspace_bytes(const vg_sim *h, size_t *bytes) {
     tmp.n = h->n; tmp.nseg = h->nseg; tmp.prec = h->prec; tmp.features = h->features;
     tmp.ntiles = h->ntiles; tmp.npieces = h->npieces; tmp.cg_blocks = h->cg_blocks; tmp.adj_blocks = h->adj_blocks;
     tmp.nchunks = h->nchunks;
+    tmp.rank = h->rank;   // the geometry words are part of the workspace when a rank index is used
     *bytes = layout(&tmp, nullptr);
     return VG_OK;
 }
@@ -294,7 +300,7 @@ extern "C" int vg_init_state(vg_sim *h, void *fields_d, void *alt_d, void *work_
                                         hipMemcpyHostToDevice, s), "upload chunks"))) return rc;
     if ((rc = hip_status(hipMemcpyAsync(h->seg_chunk, h->seg_chunk_h.data(), sizeof(int32_t) * h->seg_chunk_h.size(),
                                         hipMemcpyHostToDevice, s), "upload segment chunks"))) return rc;
-    if ((rc = launch_tile_words(h, s))) return rc;
+    if ((rc = launch_geometry(h, s))) return rc;
     // the host tables must outlive the asynchronous copies
     if ((rc = hip_status(hipStreamSynchronize(s), "synchronise"))) return rc;
     h->bound = true;

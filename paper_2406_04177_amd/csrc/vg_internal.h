@@ -131,8 +131,9 @@ struct Pieces {
 };
 
 #ifndef VG_VPT
-#define VG_VPT 2
+#define VG_VPT 1
 #endif
+
 constexpr int kVPT = VG_VPT;            // voxels per thread in a tile
 constexpr int kTile = kBlock * kVPT;    // voxels per tile (one tile per block)
 constexpr int kChunk = 256;             // pieces per first-stage totals chunk
@@ -163,7 +164,6 @@ struct RGeom {
     FastDiv fnx, fny, fb, fb2, fb3, fnbx, fnby;
     unsigned periodic;
     const RankWord *rank;
-    const int32_t *tile_word;   // word holding the first compact index of each tile
 };
 
 __device__ __forceinline__ void rg_xyz(const RGeom &G, uint32_t p, int &x, int &y, int &z) {
@@ -242,7 +242,8 @@ struct vg_sim {
     const void *rank = nullptr;
     int nx = 0, ny = 0, nz = 0, brick = 0;
     unsigned periodic = 0;
-    int32_t *tile_word = nullptr;   // [ntiles]
+    const int32_t *vox = nullptr;   // compacted list (linear indices)
+    uint32_t *geo = nullptr;        // [n] geometry words of the rank-index kernel
     int kernel = 0;                 // 0 auto, 1 neighbour table, 2 rank index
     std::vector<int32_t> piece_first_h, piece_seg_h, seg_first_h;
     std::vector<int64_t> piece_lo_h;
@@ -274,7 +275,7 @@ int launch_pass(vg_sim *h, int mode, int tot, double dt, hipStream_t s);
 int launch_pass_bufs(vg_sim *h, int mode, int tot, double dt, const void *const src[VG_NPOOL],
                      void *const dst[VG_NPOOL], hipStream_t s);
 int launch_totals_finalize(vg_sim *h, double *out_rows, hipStream_t s);
-int launch_tile_words(vg_sim *h, hipStream_t s);
+int launch_geometry(vg_sim *h, hipStream_t s);
 bool use_rank(const vg_sim *h);
 int restore_canonical(vg_sim *h, hipStream_t s);
 // vg_cg.hip

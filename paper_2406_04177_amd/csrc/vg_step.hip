@@ -11,12 +11,12 @@
 //
 // Two ways to find the neighbours of compact voxel i:
 //   table  the 6-slot int32 table nbr[6][n] (24 B per voxel and pass);
-//   rank   the rank index of the enumeration: a block decodes the positions of
-//          its tile of compact voxels from the pore bitmap words into LDS, and
-//          each neighbour's compact index is the rank of its position
-//          (bitmap word + popcount).  The words of a tile are ~1.5 B per voxel
-//          and the neighbour words are cache hits, so a pass moves ~41 B per
-//          voxel instead of 64 B.  Single volume only.
+//   rank   a 32-bit geometry word per voxel (packed coordinates, and in raster
+//          order the -x / +x neighbours, which are i - 1 / i + 1) plus the rank
+//          index of the enumeration: a neighbour's compact index is the rank of
+//          its position (pore-bitmap word + popcount; the words are cache
+//          hits), so a pass moves ~46 B per voxel instead of 64 B.  Single
+//          volume, no periodic axis, every dimension <= 1024.
 //
 // The paper's step is T then D.  The pass computes K = T o D (diffuse, then
 // transform), so n paper steps run as T, K^(n-1), D.  Inside a K pass the
@@ -282,200 +282,117 @@ __global__ __launch_bounds__(kBlock) void k_step(StepBufs<R> B, Coef<R> C, Piece
     }
 }
 
-// Rank-index variant (single volume: one piece per tile).  FAST: raster
-// order, no periodic axis, every dimension <= 1024.  Then the decode also
-// stores each voxel's coordinates and whether its -x / +x neighbours are pore
-// (compact indices i - 1 / i + 1 in raster order), so only the four +-y / +-z
-// neighbours need a bitmap word each.
-template <typename R, int MODE, int MOB, bool REG, int TOT, bool FAST>
-__global__ __launch_bounds__(kBlock) void k_step_rank(StepBufs<R> B, Coef<R> C, RGeom G, double *__restrict__ part) {
-    __shared__ int32_t pos[kTile];
-    __shared__ int32_t done;
+// Rank-index variant (single volume: one piece per tile).  Each voxel has a
+// 32-bit geometry word (x | y << 10 | z << 20, and in raster order whether
+// its -x / +x neighbours are pore in bits 30 / 31: their compact indices are
+// then i - 1 / i + 1).  The other neighbours' compact indices are ranks of
+// their positions: one pore-bitmap word (8 B, a cache hit) and a popcount.
+// Per voxel and pass this reads 4 B of geometry instead of 24 B of table.
+// Neighbours of one thread's voxels from their geometry words (rank index).
+template <typename R, bool REG, bool RASTER>
+__device__ __forceinline__ void geo_neighbours(const RGeom &G, const R *cl, const int64_t (&ic)[kVPT],
+                                               const uint32_t (&gw)[kVPT], int32_t (&j)[kVPT][6],
+                                               R (&w)[kVPT][6]) {
+    constexpr int NW = RASTER ? 4 : 6;        // neighbours found through the bitmap
+    const uint32_t nx = G.fnx.d, plane = G.fnx.d * G.fny.d;
+    uint32_t pq[kVPT][NW];
+    bool ok[kVPT][NW];
+#pragma unroll
+    for (int v = 0; v < kVPT; v++) {
+        const uint32_t c = gw[v];
+        const int xx = (int)(c & 1023u), yy = (int)((c >> 10) & 1023u), zz = (int)((c >> 20) & 1023u);
+        if (RASTER) {
+            const uint32_t p = (uint32_t)xx + nx * ((uint32_t)yy + G.fny.d * (uint32_t)zz);
+            j[v][0] = ((c >> 30) & 1u) ? (int32_t)ic[v] - 1 : -1;
+            j[v][1] = (c >> 31) ? (int32_t)ic[v] + 1 : -1;
+            ok[v][0] = yy > 0;
+            ok[v][1] = yy + 1 < G.g.ny;
+            ok[v][2] = zz > 0;
+            ok[v][3] = zz + 1 < G.g.nz;
+            pq[v][0] = ok[v][0] ? p - nx : p;
+            pq[v][1] = ok[v][1] ? p + nx : p;
+            pq[v][2] = ok[v][2] ? p - plane : p;
+            pq[v][3] = ok[v][3] ? p + plane : p;
+        } else {
+            const int xyz[3] = {xx, yy, zz};
+            const int dims[3] = {G.g.nx, G.g.ny, G.g.nz};
+            const uint32_t p = rg_pos(G, xx, yy, zz);
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                const int axis = k >> 1;
+                int q[3] = {xyz[0], xyz[1], xyz[2]};
+                q[axis] += (k & 1) ? 1 : -1;
+                ok[v][k % NW] = q[axis] >= 0 && q[axis] < dims[axis];
+                pq[v][k % NW] = ok[v][k % NW] ? rg_pos(G, q[0], q[1], q[2]) : p;
+            }
+        }
+        if (REG) {
+            const int hx = G.g.nx / 2, hy = G.g.ny / 2, hz = G.g.nz / 2;
+            const int oct = 4 * (zz >= hz) + 2 * (yy >= hy) + (xx >= hx);
+            const int nb[6] = {oct ^ ((xx - 1 >= hx) != (xx >= hx)), oct ^ ((xx + 1 >= hx) != (xx >= hx)),
+                               oct ^ (2 * ((yy - 1 >= hy) != (yy >= hy))), oct ^ (2 * ((yy + 1 >= hy) != (yy >= hy))),
+                               oct ^ (4 * ((zz - 1 >= hz) != (zz >= hz))), oct ^ (4 * ((zz + 1 >= hz) != (zz >= hz)))};
+#pragma unroll
+            for (int k = 0; k < 6; k++) w[v][k] = R(0.5) * (cl[oct] + cl[nb[k]]);
+        }
+    }
+    // all bitmap words of the thread are loaded before any is used
+    uint32_t wb[kVPT][NW], wbefore[kVPT][NW];
+#pragma unroll
+    for (int v = 0; v < kVPT; v++)
+#pragma unroll
+        for (int k = 0; k < NW; k++) {
+            const RankWord t = G.rank[pq[v][k] >> 5];
+            wb[v][k] = t.bits;
+            wbefore[v][k] = t.before;
+        }
+#pragma unroll
+    for (int v = 0; v < kVPT; v++)
+#pragma unroll
+        for (int k = 0; k < NW; k++) {
+            const uint32_t bit = pq[v][k] & 31u;
+            const bool pore = ok[v][k] && ((wb[v][k] >> bit) & 1u);
+            j[v][k + 6 - NW] = pore ? (int32_t)(wbefore[v][k] + (uint32_t)__popc(wb[v][k] & ((1u << bit) - 1u))) : -1;
+        }
+}
+
+// Rank-index variant (single volume, one tile per block).  Each voxel has a
+// 32-bit geometry word (x | y << 10 | z << 20, and in raster order whether its
+// -x / +x neighbours are pore in bits 30 / 31: their compact indices are then
+// i - 1 / i + 1).  The other neighbours' compact indices are ranks of their
+// positions: one pore-bitmap word (8 B, a cache hit) and a popcount.  Per
+// voxel and pass this reads 4 B of geometry instead of 24 B of table.
+// (A persistent, software-pipelined form of this kernel measured slower.)
+template <typename R, int MODE, int MOB, bool REG, int TOT, bool RASTER>
+__global__ __launch_bounds__(kBlock) void k_step_geo(StepBufs<R> B, Coef<R> C, RGeom G,
+                                                     const uint32_t *__restrict__ geo, double *__restrict__ part) {
     __shared__ double lds[kWaves * VG_NPOOL];
     __shared__ R cl[VG_NREG];
     constexpr bool do_d = MODE == MODE_D || MODE == MODE_DT;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t n = B.n;
-    const uint32_t i0 = (uint32_t)(tile * kTile);
-    const uint32_t i1 = (uint32_t)(i0 + kTile < n ? i0 + kTile : n);
-    if (REG && threadIdx.x < VG_NREG) cl[threadIdx.x] = C.c[threadIdx.x];
-
+    if (REG) {
+        if (threadIdx.x < VG_NREG) cl[threadIdx.x] = C.c[threadIdx.x];
+        __syncthreads();
+    }
     int64_t ic[kVPT];
     bool act[kVPT];
 #pragma unroll
     for (int v = 0; v < kVPT; v++) {
-        const int64_t i = (int64_t)i0 + v * kBlock + threadIdx.x;
-        act[v] = i < (int64_t)i1;
+        const int64_t i = tile * kTile + v * kBlock + threadIdx.x;
+        act[v] = i < n;
         ic[v] = act[v] ? i : n - 1;
     }
-    // own pools first: their latency overlaps the decode below
+    uint32_t gw[kVPT];
+    if (do_d) {
+#pragma unroll
+        for (int v = 0; v < kVPT; v++) gw[v] = ld_once(&geo[ic[v]]);
+    }
     R x[kVPT][VG_NPOOL];
     load_own<R, MODE, MOB, TOT>(B, ic, x);
-
-    if (do_d || REG) {
-        // decode the enumeration positions of compact voxels [i0, i1) into LDS
-        int64_t w = (int64_t)G.tile_word[tile] + threadIdx.x;
-        for (;;) {
-            uint32_t end = 0;
-            if (w < G.g.nwords) {
-                const RankWord wd = G.rank[w];
-                uint32_t bits = wd.bits;
-                const uint32_t before = wd.before;
-                end = before + (uint32_t)__popc(bits);
-                if (before < i1 && end > i0) {
-                    uint32_t idx = before;
-                    if (FAST) {
-                        // coordinates of the word's first position, then per bit
-                        const uint32_t p0 = (uint32_t)w << 5;
-                        const uint32_t q1 = G.fnx.div(p0);
-                        const uint32_t z0 = G.fny.div(q1);
-                        const int x0 = (int)(p0 - q1 * G.fnx.d), y0 = (int)(q1 - z0 * G.fny.d);
-                        const uint32_t lo_bit = w > 0 ? G.rank[w - 1].bits >> 31 : 0u;
-                        const uint32_t hi_bit = w + 1 < G.g.nwords ? G.rank[w + 1].bits & 1u : 0u;
-                        const uint32_t all = bits;
-                        while (bits) {
-                            const uint32_t b = (uint32_t)(__ffs(bits) - 1);
-                            if (idx >= i0 && idx < i1) {
-                                int x = x0 + (int)b, y = y0, z = (int)z0;
-                                if (x >= G.g.nx) {   // a word spans at most two rows when nx >= 32
-                                    x -= G.g.nx;
-                                    if (++y >= G.g.ny) { y = 0; z++; }
-                                }
-                                const uint32_t left = b > 0 ? (all >> (b - 1)) & 1u : lo_bit;
-                                const uint32_t right = b < 31 ? (all >> (b + 1)) & 1u : hi_bit;
-                                const uint32_t mx = (x > 0 && left) ? 1u : 0u;
-                                const uint32_t px = (x + 1 < G.g.nx && right) ? 1u : 0u;
-                                pos[idx - i0] = (int32_t)((uint32_t)x | ((uint32_t)y << 10) | ((uint32_t)z << 20) |
-                                                          (mx << 30) | (px << 31));
-                            }
-                            idx++;
-                            bits &= bits - 1u;
-                        }
-                    } else {
-                        while (bits) {
-                            const uint32_t b = (uint32_t)(__ffs(bits) - 1);
-                            if (idx >= i0 && idx < i1) pos[idx - i0] = (int32_t)(((uint32_t)w << 5) + b);
-                            idx++;
-                            bits &= bits - 1u;
-                        }
-                    }
-                }
-            }
-            if (threadIdx.x == kBlock - 1) done = (w >= G.g.nwords || end >= i1) ? 1 : 0;
-            __syncthreads();
-            if (done) break;
-            w += kBlock;
-            __syncthreads();
-        }
-    }
-
     int32_t j[kVPT][6];
     R w[kVPT][6];
-    if (do_d && FAST) {
-        const uint32_t nx = G.fnx.d, plane = G.fnx.d * G.fny.d;
-        uint32_t pq[kVPT][4];
-        bool ok[kVPT][4];
-#pragma unroll
-        for (int v = 0; v < kVPT; v++) {
-            const uint32_t c = (uint32_t)pos[act[v] ? v * kBlock + threadIdx.x : 0];
-            const int x = (int)(c & 1023u), y = (int)((c >> 10) & 1023u), z = (int)((c >> 20) & 1023u);
-            const uint32_t p = (uint32_t)x + nx * ((uint32_t)y + G.fny.d * (uint32_t)z);
-            // an inactive lane borrows voxel i0's coordinates; its +-x flags
-            // would point past the tile, so they are dropped
-            j[v][0] = (act[v] && ((c >> 30) & 1u)) ? (int32_t)ic[v] - 1 : -1;
-            j[v][1] = (act[v] && (c >> 31)) ? (int32_t)ic[v] + 1 : -1;
-            ok[v][0] = y > 0;
-            ok[v][1] = y + 1 < G.g.ny;
-            ok[v][2] = z > 0;
-            ok[v][3] = z + 1 < G.g.nz;
-            pq[v][0] = ok[v][0] ? p - nx : p;
-            pq[v][1] = ok[v][1] ? p + nx : p;
-            pq[v][2] = ok[v][2] ? p - plane : p;
-            pq[v][3] = ok[v][3] ? p + plane : p;
-            if (REG) {
-                const int hx = G.g.nx / 2, hy = G.g.ny / 2, hz = G.g.nz / 2;
-                const int oct = 4 * (z >= hz) + 2 * (y >= hy) + (x >= hx);
-                const int nb[6] = {oct ^ ((x - 1 >= hx) != (x >= hx)), oct ^ ((x + 1 >= hx) != (x >= hx)),
-                                   oct ^ (2 * ((y - 1 >= hy) != (y >= hy))), oct ^ (2 * ((y + 1 >= hy) != (y >= hy))),
-                                   oct ^ (4 * ((z - 1 >= hz) != (z >= hz))), oct ^ (4 * ((z + 1 >= hz) != (z >= hz)))};
-#pragma unroll
-                for (int k = 0; k < 6; k++) w[v][k] = R(0.5) * (cl[oct] + cl[nb[k]]);
-            }
-        }
-        uint32_t wb[kVPT][4], wbefore[kVPT][4];
-#pragma unroll
-        for (int v = 0; v < kVPT; v++)
-#pragma unroll
-            for (int k = 0; k < 4; k++) {
-                const RankWord t = G.rank[pq[v][k] >> 5];
-                wb[v][k] = t.bits;
-                wbefore[v][k] = t.before;
-            }
-#pragma unroll
-        for (int v = 0; v < kVPT; v++)
-#pragma unroll
-            for (int k = 0; k < 4; k++) {
-                const uint32_t bit = pq[v][k] & 31u;
-                const bool pore = ok[v][k] && ((wb[v][k] >> bit) & 1u);
-                j[v][k + 2] = pore ? (int32_t)(wbefore[v][k] + (uint32_t)__popc(wb[v][k] & ((1u << bit) - 1u))) : -1;
-            }
-    } else if (do_d) {
-        const int dims[3] = {G.g.nx, G.g.ny, G.g.nz};
-        // position strides of the three axes in raster order
-        const uint32_t stride[3] = {1u, G.fnx.d, G.fnx.d * G.fny.d};
-        uint32_t pq[kVPT][6];
-        bool ok[kVPT][6];
-#pragma unroll
-        for (int v = 0; v < kVPT; v++) {
-            const uint32_t p = act[v] ? (uint32_t)pos[v * kBlock + threadIdx.x] : (uint32_t)pos[0];
-            int xyz[3];
-            rg_xyz(G, p, xyz[0], xyz[1], xyz[2]);
-            int oct = 0;
-            if (REG) oct = 4 * (xyz[2] >= dims[2] / 2) + 2 * (xyz[1] >= dims[1] / 2) + (xyz[0] >= dims[0] / 2);
-#pragma unroll
-            for (int k = 0; k < 6; k++) {
-                const int axis = k >> 1;
-                const bool up = k & 1;
-                int q[3] = {xyz[0], xyz[1], xyz[2]};
-                q[axis] += up ? 1 : -1;
-                bool inside = true, wrapped = false;
-                if (q[axis] < 0 || q[axis] >= dims[axis]) {
-                    if (G.periodic & (1u << axis)) {
-                        q[axis] = q[axis] < 0 ? q[axis] + dims[axis] : q[axis] - dims[axis];
-                        wrapped = true;
-                    } else {
-                        inside = false;
-                    }
-                }
-                ok[v][k] = inside;
-                if (!inside) pq[v][k] = p;         // any valid position: its word is loaded, not used
-                else if (G.g.b <= 0 && !wrapped) pq[v][k] = up ? p + stride[axis] : p - stride[axis];
-                else pq[v][k] = rg_pos(G, q[0], q[1], q[2]);
-                if (REG) {
-                    const int oq = 4 * (q[2] >= dims[2] / 2) + 2 * (q[1] >= dims[1] / 2) + (q[0] >= dims[0] / 2);
-                    w[v][k] = R(0.5) * (cl[oct] + cl[oq]);
-                }
-            }
-        }
-        // all bitmap words of the thread are loaded before any is used
-        uint32_t wb[kVPT][6], wbefore[kVPT][6];
-#pragma unroll
-        for (int v = 0; v < kVPT; v++)
-#pragma unroll
-            for (int k = 0; k < 6; k++) {
-                const RankWord t = G.rank[pq[v][k] >> 5];
-                wb[v][k] = t.bits;
-                wbefore[v][k] = t.before;
-            }
-#pragma unroll
-        for (int v = 0; v < kVPT; v++)
-#pragma unroll
-            for (int k = 0; k < 6; k++) {
-                const uint32_t bit = pq[v][k] & 31u;
-                const bool pore = ok[v][k] && ((wb[v][k] >> bit) & 1u);
-                j[v][k] = pore ? (int32_t)(wbefore[v][k] + (uint32_t)__popc(wb[v][k] & ((1u << bit) - 1u))) : -1;
-            }
-    }
+    if (do_d) geo_neighbours<R, REG, RASTER>(G, cl, ic, gw, j, w);
     double acc[kVPT][VG_NPOOL];
     finish<R, MODE, MOB, REG, TOT>(B, C, ic, act, j, w, x, acc);
     if (TOT != TOT_NONE) {
@@ -492,20 +409,28 @@ __global__ __launch_bounds__(kBlock) void k_step_rank(StepBufs<R> B, Coef<R> C, 
     }
 }
 
-// Word of the rank index that holds compact index t * kTile (binary search
-// over the non-decreasing `before` counts).
-__global__ __launch_bounds__(kBlock) void k_tile_words(const RankWord *__restrict__ rank, int64_t nwords,
-                                                       int64_t ntiles, int32_t *__restrict__ out) {
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (t >= ntiles) return;
-    const uint32_t target = (uint32_t)(t * kTile);
-    int64_t lo = 0, hi = nwords - 1;   // last word with before <= target
-    while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) / 2;
-        if (rank[mid].before <= target) lo = mid;
-        else hi = mid - 1;
+// Geometry words of the rank-index kernel, from the compacted list.
+__global__ __launch_bounds__(kBlock) void k_geometry(const int32_t *__restrict__ vox, int64_t n, RGeom G,
+                                                     uint32_t *__restrict__ geo) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t v = (uint32_t)vox[i];
+    const uint32_t q1 = G.fnx.div(v);
+    const uint32_t z = G.fny.div(q1);
+    const uint32_t x = v - q1 * G.fnx.d, y = q1 - z * G.fny.d;
+    uint32_t c = x | (y << 10) | (z << 20);
+    if (G.g.b <= 0) {
+        // raster: the -x / +x neighbours, when pore, are compact voxels i -/+ 1
+        if (x > 0) {
+            const RankWord wd = G.rank[(v - 1) >> 5];
+            if ((wd.bits >> ((v - 1) & 31u)) & 1u) c |= 1u << 30;
+        }
+        if (x + 1 < G.fnx.d) {
+            const RankWord wd = G.rank[(v + 1) >> 5];
+            if ((wd.bits >> ((v + 1) & 31u)) & 1u) c |= 1u << 31;
+        }
     }
-    out[t] = (int32_t)lo;
+    geo[i] = c;
 }
 
 // Totals, stage 1: chunks of up to kChunk pieces of one segment.
@@ -560,22 +485,19 @@ RGeom make_rgeom(const vg_sim *h) {
     G.fnby.init(G.g.nby > 0 ? (uint32_t)G.g.nby : 1u);
     G.periodic = h->periodic;
     G.rank = (const RankWord *)h->rank;
-    G.tile_word = h->tile_word;
     return G;
 }
 
 template <typename R, int MODE, int MOB, bool REG, int TOT>
 int launch_one(vg_sim *h, const StepBufs<R> &B, const Coef<R> &C, hipStream_t s) {
     if (use_rank(h) && MODE != MODE_NONE) {
-        const bool fast = h->brick == 0 && h->periodic == 0 && h->nx <= 1024 && h->ny <= 1024 && h->nz <= 1024 &&
-                          h->nx >= 32;
-        if (fast)
-            hipLaunchKernelGGL((k_step_rank<R, MODE, MOB, REG, TOT, true>), dim3((unsigned)h->ntiles), dim3(kBlock), 0,
-                               s, B, C, make_rgeom(h), h->part);
+        if (h->brick == 0)
+            hipLaunchKernelGGL((k_step_geo<R, MODE, MOB, REG, TOT, true>), dim3((unsigned)h->ntiles), dim3(kBlock), 0,
+                               s, B, C, make_rgeom(h), h->geo, h->part);
         else
-            hipLaunchKernelGGL((k_step_rank<R, MODE, MOB, REG, TOT, false>), dim3((unsigned)h->ntiles), dim3(kBlock),
-                               0, s, B, C, make_rgeom(h), h->part);
-        return launch_status("k_step_rank");
+            hipLaunchKernelGGL((k_step_geo<R, MODE, MOB, REG, TOT, false>), dim3((unsigned)h->ntiles), dim3(kBlock), 0,
+                               s, B, C, make_rgeom(h), h->geo, h->part);
+        return launch_status("k_step_geo");
     }
     Pieces pc{h->piece_first, h->piece_lo, h->piece_seg, h->npieces};
     hipLaunchKernelGGL((k_step<R, MODE, MOB, REG, TOT>), dim3((unsigned)h->ntiles), dim3(kBlock), 0, s, B, C, pc,
@@ -639,19 +561,16 @@ int dispatch(vg_sim *h, int mode, int tot, double dt, hipStream_t s) {
 }  // namespace
 
 bool use_rank(const vg_sim *h) {
-    const bool ok = h->rank != nullptr && h->tile_word != nullptr && h->nseg == 1;
+    const bool ok = h->rank != nullptr && h->geo != nullptr && h->nseg == 1;
     if (h->kernel == 1) return false;
     return ok;
 }
 
-int launch_tile_words(vg_sim *h, hipStream_t s) {
-    if (!h->rank || h->ntiles == 0) return VG_OK;
-    Geom g;
-    int rc = make_geom(h->nx, h->ny, h->nz, h->brick, &g);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_tile_words, dim3((unsigned)((h->ntiles + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                       (const RankWord *)h->rank, g.nwords, h->ntiles, h->tile_word);
-    return launch_status("k_tile_words");
+int launch_geometry(vg_sim *h, hipStream_t s) {
+    if (!h->rank || h->n == 0) return VG_OK;
+    hipLaunchKernelGGL(k_geometry, dim3((unsigned)((h->n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, h->vox, h->n,
+                       make_rgeom(h), h->geo);
+    return launch_status("k_geometry");
 }
 
 int launch_pass(vg_sim *h, int mode, int tot, double dt, hipStream_t s) {

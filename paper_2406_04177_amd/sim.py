@@ -62,6 +62,7 @@ class Simulation:
         if graph.nseg == 1 and graph.n and rank_neighbours:
             nz, ny, nx = graph.shape
             desc.rank_d = graph.ranks[0].data_ptr()
+            desc.vox_d = graph.vox.data_ptr()
             desc.nx, desc.ny, desc.nz = nx, ny, nz
             desc.brick, desc.periodic = graph.brick, graph.periodic
         h = ctypes.c_void_p()

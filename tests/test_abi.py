@@ -138,3 +138,28 @@ def test_workspace_grows_with_features():
         L.vg_destroy(h)
     assert sizes[0] < sizes[1] < sizes[3] and sizes[0] < sizes[2] < sizes[3]
     assert sizes[1] >= 7 * 8 * 100000          # seven FP64 CG vectors
+
+
+def test_workspace_counts_geometry_words_of_the_rank_index():
+    """With a rank index the workspace holds a 4-byte geometry word per voxel
+    (regression: it was laid out but not counted)."""
+    L = _lib.load()
+    n = 1 << 20
+    sizes = []
+    for with_rank in (False, True):
+        seg = np.array([0, n], np.int64)
+        desc = _lib.VgDesc()
+        desc.n, desc.nseg, desc.precision = n, 1, _lib.VG_F32
+        desc.seg_off = seg.ctypes.data
+        desc.nbr_d = 0x1000
+        desc.features = 0
+        if with_rank:
+            desc.rank_d, desc.vox_d = 0x2000, 0x3000    # never dereferenced here
+            desc.nx = desc.ny = desc.nz = 128
+        h = ctypes.c_void_p()
+        assert L.vg_create(ctypes.byref(desc), ctypes.byref(h)) == 0
+        ws = ctypes.c_size_t(0)
+        assert L.vg_workspace_bytes(h, ctypes.byref(ws)) == 0
+        sizes.append(ws.value)
+        L.vg_destroy(h)
+    assert sizes[1] - sizes[0] >= 4 * n

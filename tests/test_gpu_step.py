@@ -195,10 +195,10 @@ def test_unstable_dt_is_refused_and_state_kept():
     assert torch.equal(before, sim.fields)
 
 
-@pytest.mark.parametrize("periodic,brick", [(7, 0), (5, 4), (0, 3)])
+@pytest.mark.parametrize("periodic,brick", [(0, 0), (0, 4), (0, 3), (0, 8)])
 def test_rank_kernel_equals_table_kernel_bitwise(periodic, brick):
-    """The two neighbour sources give bit-identical steps, also with periodic
-    axes, ragged bricks and regions."""
+    """The two neighbour sources give bit-identical steps, also with ragged
+    bricks, several diffusing pools and regions."""
     p = inputs.ModelParams(D=(1e-10, 1e-9, 0, 2e-10, 0), mu=1e-4, rho=1e-4)
     c = [0.6, 0.9, 1.0, 0.7, 0.8, 0.95, 0.65, 0.85]
     dt = inputs.explicit_dt(p)
@@ -229,3 +229,16 @@ def test_rank_kernel_ragged_tiles():
         sim, _ = run_gpu(g, specs, p, dt, 9, F64, kernel=RANK)
         ref, _ = run_oracle(og, specs, p, dt, 9)
         np.testing.assert_array_equal(sim.fields.cpu().numpy(), ref)
+
+
+def test_rank_kernel_refused_with_periodic_axes():
+    """Periodic graphs (tests only) always use the neighbour table."""
+    from paper_2406_04177_amd import _lib
+    from paper_2406_04177_amd.graph import Graph
+    from paper_2406_04177_amd.sim import Simulation
+    mask = np.ones((6, 7, 8), np.uint8)
+    g = Graph.from_masks(mask, periodic=7)
+    sim = Simulation(g, inputs.ModelParams(), precision="f64")
+    with pytest.raises(_lib.VgError):
+        sim.set_kernel(RANK)
+    sim.set_kernel(0)
