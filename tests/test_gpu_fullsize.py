@@ -1,0 +1,75 @@
+"""Parity at the benchmark's full size (512^3, 17 % porosity, n ~ 20.8 M) in the
+launch configuration bench.py times: the graph bit for bit, a few FP64 steps
+bit for bit, FP32 steps within 1e-5, both neighbour sources, against the
+oracle run on the whole graph."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as orc
+from paper_2406_04177_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+N = 512
+
+
+@pytest.fixture(scope="module")
+def full():
+    from paper_2406_04177_amd.graph import Graph
+    mask = inputs.synthetic_volume((N, N, N), porosity=0.17, seed=0)
+    spec = inputs.init_uniform(mask, seed=0)
+    g = Graph.from_masks(mask)
+    og = orc.build_graph(mask)
+    print("full size: n =", g.n, flush=True)
+    return mask, spec, g, og
+
+
+def test_graph_bitwise_512(full):
+    mask, spec, g, og = full
+    assert g.n == og.n
+    np.testing.assert_array_equal(g.vox.cpu().numpy(), og.vox)
+    np.testing.assert_array_equal(g.nbr.cpu().numpy(), og.nbr)
+
+
+def run(g, spec, precision, kernel, steps, log_every=0):
+    from paper_2406_04177_amd.sim import Simulation
+    p = inputs.ModelParams()
+    sim = Simulation(g, p, precision=precision, implicit=False)
+    sim.set_kernel(kernel)
+    sim.set_fields(g.fields_from_specs(spec, torch.float64))
+    log = sim.step(steps, inputs.explicit_dt(p), log_every=log_every)
+    torch.cuda.synchronize()
+    out = sim.fields.cpu().numpy().astype(np.float64)
+    return out, (log.cpu().numpy() if log is not None else None)
+
+
+def test_fp64_steps_bitwise_512(full):
+    mask, spec, g, og = full
+    p = inputs.ModelParams()
+    steps = 6
+    ref, tot = orc.run(p, inputs.explicit_dt(p), og, orc.fields_from_spec(og, spec), steps)
+    for kernel in (1, 2):
+        got, log = run(g, spec, "f64", kernel, steps, log_every=3)
+        np.testing.assert_array_equal(got, ref)
+        np.testing.assert_allclose(log, tot[3::3], rtol=1e-13, atol=1e-300)
+
+
+def test_fp32_steps_512(full):
+    mask, spec, g, og = full
+    p = inputs.ModelParams()
+    steps = 40
+    ref, tot = orc.run(p, inputs.explicit_dt(p), og, orc.fields_from_spec(og, spec), steps)
+    outs = []
+    for kernel in (1, 2):
+        got, log = run(g, spec, "f32", kernel, steps, log_every=steps)
+        for s in range(5):
+            scale = np.abs(ref[s]).max()
+            if scale == 0:
+                assert np.all(got[s] == 0)
+                continue
+            err = np.abs(got[s] - ref[s]).max() / scale
+            assert err <= 1e-5, (kernel, s, err)
+        np.testing.assert_allclose(log[-1, 0, :5], tot[-1, 0, :5], rtol=1e-5)
+        outs.append(got)
+    np.testing.assert_array_equal(outs[0], outs[1])     # the two neighbour sources agree bit for bit
