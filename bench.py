@@ -38,6 +38,30 @@ BYTES_FUSED_F64 = 5 * 8 + 5 * 8 + 6 * 4
 # rank-index kernel: the pools, a 4-byte geometry word per voxel and the
 # pore-bitmap words (8 B per 32 positions, 8 / (32 * 0.17) ~ 1.5 B per pore voxel)
 BYTES_RANK_F32 = 5 * 4 + 5 * 4 + 4 + 8.0 / (32 * 0.17)
+# packed-offset kernel: the pools and two 4-byte offset words per voxel
+BYTES_OFFSET_F32 = 5 * 4 + 5 * 4 + 8
+KERNEL_NAMES = {1: "table", 2: "rank", 3: "offset"}
+KERNEL_FUNCS = {1: "k_step<..., table>", 2: "k_step_geo", 3: "k_step<..., offsets>"}
+OWN_BYTES = {1: BYTES_FUSED_F32, 2: BYTES_RANK_F32, 3: BYTES_OFFSET_F32}
+
+# HBM bytes per launch of the headline kernel read from hardware counters
+# (FETCH_SIZE x 2 + WRITE_SIZE, the factors of a plain 1 GiB device copy on the
+# same GPU), valid only for the kernel sources they were taken on: the sha256
+# of KERNEL_SOURCES must match, else the roofline reports traffic = null.
+KERNEL_SOURCES = ("paper_2406_04177_amd/csrc/vg_step.hip", "paper_2406_04177_amd/csrc/vg_internal.h",
+                  "paper_2406_04177_amd/build.py")
+MEASURED_TRAFFIC = {
+    # (kernel, size): (bytes per launch, sha256 of KERNEL_SOURCES)
+}
+
+
+def sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def log(msg):
@@ -71,6 +95,47 @@ def cpu_baseline(mask, spec, params, dt, steps):
             "sample": "%d explicit steps of the same 512^3 workload (n = %d), FP64, %.1f s" % (steps, og.n, sec)}
 
 
+def accuracy_256(steps, N=256):
+    import numpy as np
+    import torch
+    from paper_2406_04177_amd import inputs
+    from paper_2406_04177_amd.graph import Graph
+    from paper_2406_04177_amd.sim import Simulation
+    mask = inputs.synthetic_volume((N, N, N), porosity=0.17, seed=0)
+    spec = inputs.init_uniform(mask, seed=0)
+    params = inputs.ModelParams()
+    dt = inputs.explicit_dt(params, 0.9)
+    g = Graph.from_masks(mask)
+    res = {"workload": "%d^3 17%% porosity, %d explicit steps, totals every 100" % (N, steps), "n_pore_voxels": g.n}
+    out = {}
+    for prec, dtype in (("f32", torch.float32), ("f64", torch.float64)):
+        sim = Simulation(g, params, precision=prec, implicit=False)
+        sim.set_fields(g.fields_from_specs(spec, torch.float64).to(dtype))
+        sim.step(100, dt)
+        sim.set_fields(g.fields_from_specs(spec, torch.float64).to(dtype))
+        c0 = sim.totals()[0, 5]
+        ms, logt = timed(lambda: sim.step(steps, dt, log_every=100))
+        out[prec] = (sim.fields.double().cpu().numpy(), logt[:, 0, :].cpu().numpy(), c0)
+        res["%s_ms_per_step" % prec] = ms / steps
+        del sim
+    (x32, t32, c32), (x64, t64, c64) = out["f32"], out["f64"]
+    names = ("MB", "DOM", "SOM", "P4", "CO2")
+    res["field_rel_err"] = {names[s]: float(np.abs(x32[s] - x64[s]).max() / max(np.abs(x64[s]).max(), 1e-300))
+                            for s in range(5)}
+    curves = names + ("total",)
+    res["totals_curve_rel_err"] = {curves[s]: float((np.abs(t32[:, s] - t64[:, s])
+                                                     / np.maximum(np.abs(t64[:, s]), 1e-300)).max())
+                                   for s in range(6)}
+    res["total_carbon_drift_f64"] = float(np.abs(t64[:, 5] - c64).max() / c64)
+    res["total_carbon_drift_f32"] = float(np.abs(t32[:, 5] - c32).max() / c32)
+    res["fp32_speedup"] = res["f64_ms_per_step"] / res["f32_ms_per_step"]
+    res["reference"] = "the FP64 GPU step (bit-identical to the FP64 oracle)"
+    log("256^3 accuracy: FP32 %.4f ms/step, FP64 %.4f ms/step, field errors %s"
+        % (res["f32_ms_per_step"], res["f64_ms_per_step"],
+           ", ".join("%s %.1e" % kv for kv in res["field_rel_err"].items())))
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,8 +144,11 @@ def main(argv=None):
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--quick", action="store_true", help="headline only (no extra rows, no CPU baseline)")
     ap.add_argument("--cpu-steps", type=int, default=8)
-    ap.add_argument("--kernel", choices=("auto", "table", "rank"), default="auto",
+    ap.add_argument("--acc-steps", type=int, default=10000, help="steps of the 256^3 FP32-vs-FP64 row")
+    ap.add_argument("--kernel", choices=("auto", "table", "rank", "offset"), default="auto",
                     help="neighbour source of the explicit-step kernel")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="finish with three plain 1 GiB device copies (scale for HBM byte counters)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
@@ -110,8 +178,8 @@ def main(argv=None):
     log("n = %d pore voxels; graph build %.2f ms (incl. mask upload and host sync)" % (n, ms_graph))
 
     sim = Simulation(g, params, precision="f32", implicit=False, adjoint=False)
-    kernel = {"auto": 0, "table": 1, "rank": 2}[args.kernel]
-    sim.set_kernel(kernel)
+    sim.set_kernel({"auto": 0, "table": 1, "rank": 2, "offset": 3}[args.kernel])
+    kernel = sim.kernel_in_use()
     x0 = g.fields_from_specs(spec, torch.float32)
     sim.set_fields(x0)
     sim.step(args.warmup, dt, log_every=100)
@@ -120,15 +188,26 @@ def main(argv=None):
     ms, _ = timed(lambda: sim.step(K, dt, log_every=100, totals_out=tot_log if K >= 100 else None))
     ms_step = ms / K
     vps = n * K / (ms / 1e3)
-    rank_used = kernel == 2 or (kernel == 0 and g.nseg == 1)
-    own_bpv = BYTES_RANK_F32 if rank_used else BYTES_FUSED_F32
+    # the fused kernel's own average launch time: K paper steps launch a
+    # transformation-only pass, K-1 fused passes and a diffusion-only pass, one
+    # step launches the two end passes only; no totals in either
+    ms_k, _ = timed(lambda: sim.step(K, dt))
+    ms_1, _ = timed(lambda: sim.step(1, dt))
+    us_launch = (ms_k - ms_1) / (K - 1) * 1e3
+    own_bpv = OWN_BYTES[kernel]
     # the roofline counts the method's algorithmic bytes per voxel and step
     # (five pools read and written plus the 6-slot neighbour table, 64 B)
     # whichever neighbour source the kernel uses; own_bytes_per_voxel is what
-    # the rank-index kernel itself has to move
+    # the kernel's own neighbour source makes it move
     bpv = BYTES_FUSED_F32
-    achieved = bpv * n / (ms_step / 1e3) / 1e9
-    log("explicit FP32: %.4f ms/step, %.3e voxel-steps/s, %.0f GB/s algorithmic" % (ms_step, vps, achieved))
+    achieved = bpv * n / (us_launch / 1e6) / 1e9
+    kname = KERNEL_FUNCS[kernel]
+    traffic = None
+    rec = MEASURED_TRAFFIC.get((KERNEL_NAMES[kernel], N))
+    if rec is not None and rec[1] == sources_sha():
+        traffic = rec[0]
+    log("explicit FP32: %.4f ms/step, %.3e voxel-steps/s; fused kernel %.2f us/launch, %.0f GB/s algorithmic"
+        % (ms_step, vps, us_launch, achieved))
     out = {
         "metric": METRIC,
         "value": 5.0 * vps,
@@ -140,26 +219,30 @@ def main(argv=None):
                    "shape": [N, N, N], "n_pore_voxels": n, "dt_s": dt, "order": "transformation then diffusion",
                    "voxel_steps_per_s": vps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "%s<float, DT, DOM-only> (fused transformation + diffusion)"
-                               % ("k_step_geo" if rank_used else "k_step"),
-                     "bytes_per_voxel": bpv, "own_bytes_per_voxel": own_bpv,
-                     "own_frac": own_bpv * n / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "%s, FP32, DOM-only diffusion (fused transformation + diffusion)" % kname,
+                     "neighbour_source": KERNEL_NAMES[kernel],
+                     "launch_us": us_launch, "bytes_per_voxel": bpv, "bytes_per_launch": bpv * n,
+                     "own_bytes_per_voxel": own_bpv,
+                     "own_frac": own_bpv * n / (us_launch / 1e6) / 1e9 / HBM_PEAK_GBS},
     }
     del tot_log
 
     if not args.quick:
         rows = {}
         rows["a1_graph_build_ms"] = ms_graph
-        # the other neighbour source on the same state, for comparison
-        other = 1 if kernel != 1 else 2
-        sim.set_kernel(other)
-        sim.step(20, dt)
-        mso, _ = timed(lambda: sim.step(K // 2, dt, log_every=100))
-        rows["fp32_step_%s_kernel" % ("table" if other == 1 else "rank")] = {
-            "ms_per_step": mso / (K // 2), "bytes_per_voxel": BYTES_FUSED_F32 if other == 1 else BYTES_RANK_F32,
-            "achieved_GBs": (BYTES_FUSED_F32 if other == 1 else BYTES_RANK_F32) * n / (mso / (K // 2) / 1e3) / 1e9}
-        log("explicit FP32, %s kernel: %.4f ms/step" % ("table" if other == 1 else "rank", mso / (K // 2)))
+        # the other neighbour sources on the same state, for comparison
+        for other in (1, 2, 3):
+            if other == kernel:
+                continue
+            sim.set_kernel(other)
+            sim.step(20, dt)
+            mso, _ = timed(lambda: sim.step(K // 2, dt, log_every=100))
+            rows["fp32_step_%s_kernel" % KERNEL_NAMES[other]] = {
+                "ms_per_step": mso / (K // 2), "own_bytes_per_voxel": OWN_BYTES[other],
+                "achieved_GBs_64B": BYTES_FUSED_F32 * n / (mso / (K // 2) / 1e3) / 1e9,
+                "achieved_GBs_own": OWN_BYTES[other] * n / (mso / (K // 2) / 1e3) / 1e9}
+            log("explicit FP32, %s kernel: %.4f ms/step" % (KERNEL_NAMES[other], mso / (K // 2)))
         sim.set_kernel(kernel)
         # plain FP64 step on the same input
         sim64 = Simulation(g, params, precision="f64", implicit=True, adjoint=False)
@@ -213,11 +296,22 @@ def main(argv=None):
         out["adjoint_forward_ratio"] = (msr + msa) / msf
         del sima, states, lam
         torch.cuda.empty_cache()
+        # FP32 fields + FP64 totals against the plain FP64 step on the 256^3
+        # workload: 10^4 steps, totals every 100, error per species (fields,
+        # relative to each pool's max) and per totals curve (relative per point)
+        rows["fp32_vs_fp64_256"] = accuracy_256(args.acc_steps)
         # CPU baseline: the oracle on the host cores
         cb = cpu_baseline(mask, spec, params, dt, args.cpu_steps)
         out["cpu_baseline"] = cb
         log("cpu baseline: %.3e species updates/s on %d cores" % (cb["value"], cb["cores"]))
     print(json.dumps(out), flush=True)
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration copies done (3 x 1 GiB)")
     return 0
 
 

@@ -154,13 +154,20 @@ typedef struct vg_desc {
 /* Creates a handle (host memory only) and sets default parameters. */
 int vg_create(const vg_desc *desc, vg_sim **out);
 int vg_destroy(vg_sim *h);
-/* Neighbour source of the explicit-step kernels: VG_KERNEL_AUTO (rank index
- * when the descriptor has a usable one, else the table), VG_KERNEL_TABLE or
- * VG_KERNEL_RANK (VG_EINVAL without one).  Results are bit-identical. */
-#define VG_KERNEL_AUTO  0
-#define VG_KERNEL_TABLE 1
-#define VG_KERNEL_RANK  2
+/* Neighbour source of the explicit-step kernels: VG_KERNEL_TABLE (the 6-slot
+ * table), VG_KERNEL_RANK (the rank index; VG_EINVAL without one) or
+ * VG_KERNEL_OFFSET (two packed 32-bit offset words per voxel, built by
+ * vg_init_state from the table when no neighbour crosses a periodic wrap and
+ * the largest distances per axis fit 32 bits together; VG_EINVAL otherwise).
+ * VG_KERNEL_AUTO takes packed offsets when built, else the rank index when the
+ * descriptor has a usable one, else the table.  Results are bit-identical.
+ * vg_get_kernel reports the source the next explicit pass will use. */
+#define VG_KERNEL_AUTO   0
+#define VG_KERNEL_TABLE  1
+#define VG_KERNEL_RANK   2
+#define VG_KERNEL_OFFSET 3
 int vg_set_kernel(vg_sim *h, int variant);
+int vg_get_kernel(const vg_sim *h, int *variant_in_use);
 /* Sets the model parameters (validated: h > 0, K_DOM > 0, rates >= 0,
  * 0 <= beta <= 1, D >= 0; only D[1] may be nonzero unless mobile_all). */
 int vg_set_params(vg_sim *h, const vg_params *p);
@@ -170,13 +177,17 @@ int vg_set_regions(vg_sim *h, const double *c);
 /* Device memory the caller binds with vg_init_state:
  *   fields  [5][n] elements of the field type (float or double)
  *   alt     alt_elems elements of the field type (ping-pong of mobile pools)
- *   work    workspace_bytes bytes (reduction partials, CG vectors, adjoint
- *           ping-pong and gradient partials, as enabled by `features`). */
+ *   work    workspace_bytes bytes (reduction partials, packed neighbour
+ *           offsets (8 B per voxel), geometry words with a rank index, CG
+ *           vectors, adjoint ping-pong and gradient partials, as enabled by
+ *           `features`). */
 int vg_alt_elems(const vg_sim *h, int64_t *elems);
 int vg_workspace_bytes(const vg_sim *h, size_t *bytes);
 
-/* Binds the caller's buffers (fields already hold the initial masses) and
- * uploads the small per-handle tables into the workspace. */
+/* Binds the caller's buffers (fields already hold the initial masses),
+ * uploads the small per-handle tables into the workspace and builds the
+ * derived neighbour data (geometry words, packed offsets) from the graph.
+ * Synchronises the stream. */
 int vg_init_state(vg_sim *h, void *fields_d, void *alt_d, void *work_d, size_t work_bytes,
                   void *stream);
 

@@ -51,6 +51,9 @@ size_t layout(vg_sim *h, char *base) {
     h->seg_chunk = (int32_t *)take(sizeof(int32_t) * (size_t)(h->nseg + 1));
     h->chunk_part = (double *)take(sizeof(double) * VG_NPOOL * (size_t)h->nchunks);
     h->geo = h->rank ? (uint32_t *)take(sizeof(uint32_t) * (size_t)h->n) : nullptr;
+    h->off_m = (uint32_t *)take(sizeof(uint32_t) * (size_t)h->n);
+    h->off_p = (uint32_t *)take(sizeof(uint32_t) * (size_t)h->n);
+    h->off_stat = (uint32_t *)take(sizeof(uint32_t) * 4);
     const size_t nd = sizeof(double) * (size_t)h->n;
     if (h->features & VG_FEAT_CG) {
         h->cg_y = (double *)take(nd);
@@ -230,11 +233,18 @@ extern "C" int vg_destroy(vg_sim *h) {
 
 extern "C" int vg_set_kernel(vg_sim *h, int variant) {
     if (!h) { set_error("handle is NULL"); return VG_EINVAL; }
-    if (variant < VG_KERNEL_AUTO || variant > VG_KERNEL_RANK || (variant == VG_KERNEL_RANK && !h->rank)) {
+    if (variant < VG_KERNEL_AUTO || variant > VG_KERNEL_OFFSET || (variant == VG_KERNEL_RANK && !h->rank) ||
+        (variant == VG_KERNEL_OFFSET && !h->off_ok)) {
         set_error("kernel variant %d not available", variant);
         return VG_EINVAL;
     }
     h->kernel = variant;
+    return VG_OK;
+}
+
+extern "C" int vg_get_kernel(const vg_sim *h, int *variant_in_use) {
+    if (!h || !variant_in_use) { set_error("null pointer argument"); return VG_EINVAL; }
+    *variant_in_use = vg::use_offsets(h) ? VG_KERNEL_OFFSET : vg::use_rank(h) ? VG_KERNEL_RANK : VG_KERNEL_TABLE;
     return VG_OK;
 }
 
@@ -301,6 +311,7 @@ extern "C" int vg_init_state(vg_sim *h, void *fields_d, void *alt_d, void *work_
     if ((rc = hip_status(hipMemcpyAsync(h->seg_chunk, h->seg_chunk_h.data(), sizeof(int32_t) * h->seg_chunk_h.size(),
                                         hipMemcpyHostToDevice, s), "upload segment chunks"))) return rc;
     if ((rc = launch_geometry(h, s))) return rc;
+    if ((rc = build_offsets(h, s))) return rc;
     // the host tables must outlive the asynchronous copies
     if ((rc = hip_status(hipStreamSynchronize(s), "synchronise"))) return rc;
     h->bound = true;

@@ -208,6 +208,23 @@ __device__ __forceinline__ int32_t rank_lookup(const RankWord &wd, uint32_t p) {
 }
 
 
+// Packed neighbour offsets: two 32-bit words per voxel, one for the minus-side
+// neighbours (compact index i - d) and one for the plus side (i + d).  In
+// both, the z offset occupies bits [0, bz), y the next by bits and x the next
+// bx bits; an offset of 0 means the neighbour is absent.  Valid when every
+// minus-side neighbour precedes the voxel in the enumeration and every
+// plus-side one follows it (no periodic wrap) and the widths fit 32 bits.
+struct DLayout {
+    uint32_t bz = 0, by = 0, sx = 0;   // shifts of the y and x fields
+    uint32_t mz = 0, my = 0, mx = 0;   // field masks
+};
+
+__device__ __forceinline__ void unpack_offsets(const DLayout &L, uint32_t w, uint32_t (&d)[3]) {
+    d[0] = (w >> L.sx) & L.mx;
+    d[1] = (w >> L.bz) & L.my;
+    d[2] = w & L.mz;
+}
+
 }  // namespace vg
 
 // ---------------------------------------------------------------- handle
@@ -244,7 +261,12 @@ struct vg_sim {
     unsigned periodic = 0;
     const int32_t *vox = nullptr;   // compacted list (linear indices)
     uint32_t *geo = nullptr;        // [n] geometry words of the rank-index kernel
-    int kernel = 0;                 // 0 auto, 1 neighbour table, 2 rank index
+    int kernel = 0;                 // 0 auto, 1 neighbour table, 2 rank index, 3 packed offsets
+    // packed neighbour offsets (any volume or batch without periodic wrap)
+    uint32_t *off_m = nullptr, *off_p = nullptr;   // [n] each
+    uint32_t *off_stat = nullptr;                  // [4] max offset per axis, violation flag
+    bool off_ok = false;
+    vg::DLayout off_layout;
     std::vector<int32_t> piece_first_h, piece_seg_h, seg_first_h;
     std::vector<int64_t> piece_lo_h;
     int32_t *piece_first = nullptr, *piece_seg = nullptr, *seg_first = nullptr;
@@ -277,6 +299,8 @@ int launch_pass_bufs(vg_sim *h, int mode, int tot, double dt, const void *const 
 int launch_totals_finalize(vg_sim *h, double *out_rows, hipStream_t s);
 int launch_geometry(vg_sim *h, hipStream_t s);
 bool use_rank(const vg_sim *h);
+bool use_offsets(const vg_sim *h);
+int build_offsets(vg_sim *h, hipStream_t s);
 int restore_canonical(vg_sim *h, hipStream_t s);
 // vg_cg.hip
 int run_cg(vg_sim *h, int pool, double a, double rtol, int max_iter, int *iters, double *relres,

@@ -17,6 +17,11 @@
 //          its position (pore-bitmap word + popcount; the words are cache
 //          hits), so a pass moves ~46 B per voxel instead of 64 B.  Single
 //          volume, no periodic axis, every dimension <= 1024.
+//   offset two 32-bit words per voxel holding the distances i - j (minus side)
+//          and j - i (plus side) to its neighbours in the enumeration, packed
+//          by axis (48 B per voxel and pass, and the neighbour loads depend on
+//          one load only).  Any volume or batch without periodic wrap whose
+//          largest distances fit the packing.
 //
 // The paper's step is T then D.  The pass computes K = T o D (diffuse, then
 // transform), so n paper steps run as T, K^(n-1), D.  Inside a K pass the
@@ -73,10 +78,16 @@ template <typename R>
 struct StepBufs {
     const int32_t *nbr;     // [6][n]
     const uint16_t *rcode;  // [n] or null
+    const uint32_t *off_m;  // [n] packed offsets (minus side) or null
+    const uint32_t *off_p;  // [n] packed offsets (plus side) or null
+    DLayout dl;
     const R *src[VG_NPOOL];
     R *dst[VG_NPOOL];
     int64_t n;
 };
+
+// neighbour source of k_step
+enum { NS_TABLE = 0, NS_OFFSET = 1 };
 
 #ifndef VG_NT
 #define VG_NT 0
@@ -221,7 +232,7 @@ __device__ __forceinline__ void finish(const StepBufs<R> &B, const Coef<R> &C, c
     }
 }
 
-template <typename R, int MODE, int MOB, bool REG, int TOT>
+template <typename R, int MODE, int MOB, bool REG, int TOT, int NS>
 __global__ __launch_bounds__(kBlock) void k_step(StepBufs<R> B, Coef<R> C, Pieces pc, double *__restrict__ part) {
     __shared__ double lds[kWaves * VG_NPOOL];
     __shared__ R cl[VG_NREG];
@@ -244,8 +255,20 @@ __global__ __launch_bounds__(kBlock) void k_step(StepBufs<R> B, Coef<R> C, Piece
     if (do_d) {
 #pragma unroll
         for (int v = 0; v < kVPT; v++) {
+            if (NS == NS_TABLE) {
 #pragma unroll
-            for (int k = 0; k < 6; k++) j[v][k] = ld_once(&B.nbr[(int64_t)k * B.n + ic[v]]);
+                for (int k = 0; k < 6; k++) j[v][k] = ld_once(&B.nbr[(int64_t)k * B.n + ic[v]]);
+            } else {
+                uint32_t dm[3], dp[3];
+                unpack_offsets(B.dl, ld_once(&B.off_m[ic[v]]), dm);
+                unpack_offsets(B.dl, ld_once(&B.off_p[ic[v]]), dp);
+                const int32_t i32 = (int32_t)ic[v];
+#pragma unroll
+                for (int a = 0; a < 3; a++) {
+                    j[v][2 * a] = dm[a] ? i32 - (int32_t)dm[a] : -1;
+                    j[v][2 * a + 1] = dp[a] ? i32 + (int32_t)dp[a] : -1;
+                }
+            }
             if (REG) {
                 const uint32_t code = B.rcode[ic[v]];
                 const uint32_t own = code & 7u;
@@ -433,6 +456,56 @@ __global__ __launch_bounds__(kBlock) void k_geometry(const int32_t *__restrict__
     geo[i] = c;
 }
 
+// Packed offsets, pass 1: the largest distance per axis, and a flag when a
+// minus-side neighbour does not precede the voxel (or a plus-side one does
+// not follow it), as happens across a periodic wrap.
+__global__ __launch_bounds__(kBlock) void k_offset_stat(const int32_t *__restrict__ nbr, int64_t n,
+                                                        uint32_t *__restrict__ stat) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    uint32_t mx[3] = {0, 0, 0}, bad = 0;
+    if (i < n) {
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            const int32_t j = nbr[(int64_t)k * n + i];
+            if (j < 0) continue;
+            const int64_t d = (k & 1) ? (int64_t)j - i : i - (int64_t)j;
+            if (d <= 0) bad = 1;
+            else mx[k >> 1] = max(mx[k >> 1], (uint32_t)d);
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+        for (int a = 0; a < 3; a++) mx[a] = max(mx[a], (uint32_t)__shfl_xor((int)mx[a], o, 64));
+        bad |= (uint32_t)__shfl_xor((int)bad, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+            if (mx[a]) atomicMax(&stat[a], mx[a]);
+        if (bad) atomicOr(&stat[3], 1u);
+    }
+}
+
+// Packed offsets, pass 2: the two words of every voxel.
+__global__ __launch_bounds__(kBlock) void k_offsets(const int32_t *__restrict__ nbr, int64_t n, DLayout L,
+                                                    uint32_t *__restrict__ off_m, uint32_t *__restrict__ off_p) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t shift[3] = {L.sx, L.bz, 0};
+    uint32_t wm = 0, wp = 0;
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        const int32_t j = nbr[(int64_t)k * n + i];
+        if (j < 0) continue;
+        const uint32_t d = (k & 1) ? (uint32_t)((int64_t)j - i) : (uint32_t)(i - (int64_t)j);
+        if (k & 1) wp |= d << shift[k >> 1];
+        else wm |= d << shift[k >> 1];
+    }
+    off_m[i] = wm;
+    off_p[i] = wp;
+}
+
 // Totals, stage 1: chunks of up to kChunk pieces of one segment.
 __global__ __launch_bounds__(kBlock) void k_tot_chunks(const double *__restrict__ part,
                                                        const int32_t *__restrict__ chunk_first,
@@ -490,6 +563,12 @@ RGeom make_rgeom(const vg_sim *h) {
 
 template <typename R, int MODE, int MOB, bool REG, int TOT>
 int launch_one(vg_sim *h, const StepBufs<R> &B, const Coef<R> &C, hipStream_t s) {
+    Pieces pc{h->piece_first, h->piece_lo, h->piece_seg, h->npieces};
+    if (use_offsets(h) && MODE != MODE_NONE && MODE != MODE_T) {
+        hipLaunchKernelGGL((k_step<R, MODE, MOB, REG, TOT, NS_OFFSET>), dim3((unsigned)h->ntiles), dim3(kBlock), 0, s,
+                           B, C, pc, h->part);
+        return launch_status("k_step offsets");
+    }
     if (use_rank(h) && MODE != MODE_NONE) {
         if (h->brick == 0)
             hipLaunchKernelGGL((k_step_geo<R, MODE, MOB, REG, TOT, true>), dim3((unsigned)h->ntiles), dim3(kBlock), 0,
@@ -499,9 +578,8 @@ int launch_one(vg_sim *h, const StepBufs<R> &B, const Coef<R> &C, hipStream_t s)
                                s, B, C, make_rgeom(h), h->geo, h->part);
         return launch_status("k_step_geo");
     }
-    Pieces pc{h->piece_first, h->piece_lo, h->piece_seg, h->npieces};
-    hipLaunchKernelGGL((k_step<R, MODE, MOB, REG, TOT>), dim3((unsigned)h->ntiles), dim3(kBlock), 0, s, B, C, pc,
-                       h->part);
+    hipLaunchKernelGGL((k_step<R, MODE, MOB, REG, TOT, NS_TABLE>), dim3((unsigned)h->ntiles), dim3(kBlock), 0, s, B,
+                       C, pc, h->part);
     return launch_status("k_step");
 }
 
@@ -537,6 +615,9 @@ int dispatch(vg_sim *h, int mode, int tot, double dt, hipStream_t s) {
     StepBufs<R> B;
     B.nbr = h->nbr;
     B.rcode = h->rcode;
+    B.off_m = h->off_m;
+    B.off_p = h->off_p;
+    B.dl = h->off_layout;
     B.n = h->n;
     const int mob = h->mobile_mode();
     R *canon = (R *)h->fields;
@@ -560,10 +641,54 @@ int dispatch(vg_sim *h, int mode, int tot, double dt, hipStream_t s) {
 
 }  // namespace
 
+// Neighbour source: an explicit choice, else packed offsets when they fit,
+// else the rank index when there is one, else the table.
+bool use_offsets(const vg_sim *h) {
+    return h->off_ok && (h->kernel == VG_KERNEL_AUTO || h->kernel == VG_KERNEL_OFFSET);
+}
+
 bool use_rank(const vg_sim *h) {
     const bool ok = h->rank != nullptr && h->geo != nullptr && h->nseg == 1;
-    if (h->kernel == 1) return false;
-    return ok;
+    if (h->kernel == VG_KERNEL_RANK) return ok;
+    return ok && h->kernel == VG_KERNEL_AUTO && !h->off_ok;
+}
+
+static uint32_t bit_width(uint32_t v) {
+    uint32_t b = 0;
+    while (v) { b++; v >>= 1; }
+    return b;
+}
+
+// Measures the neighbour distances and, when they fit, writes the packed
+// offsets.  Synchronises the stream (the layout is chosen on the host).
+int build_offsets(vg_sim *h, hipStream_t s) {
+    h->off_ok = false;
+    if (h->n == 0 || !h->off_m || !h->nbr) return VG_OK;
+    int rc;
+    if ((rc = hip_status(hipMemsetAsync(h->off_stat, 0, 4 * sizeof(uint32_t), s), "clear offset statistics")))
+        return rc;
+    const unsigned blocks = (unsigned)((h->n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_offset_stat, dim3(blocks), dim3(kBlock), 0, s, h->nbr, h->n, h->off_stat);
+    if ((rc = launch_status("k_offset_stat"))) return rc;
+    uint32_t st[4] = {0, 0, 0, 0};
+    if ((rc = hip_status(hipMemcpyAsync(st, h->off_stat, sizeof(st), hipMemcpyDeviceToHost, s), "read offsets")))
+        return rc;
+    if ((rc = hip_status(hipStreamSynchronize(s), "synchronise"))) return rc;
+    const uint32_t bx = bit_width(st[0]), by = bit_width(st[1]), bz = bit_width(st[2]);
+    if (st[3] || bx + by + bz > 32) return VG_OK;     // periodic wrap, or too far apart: no packed offsets
+    auto mask = [](uint32_t b) { return b >= 32 ? 0xffffffffu : (1u << b) - 1u; };
+    DLayout L;
+    L.bz = bz & 31u;                     // an empty field's shift is never used
+    L.by = by;
+    L.sx = (bz + by) & 31u;
+    L.mz = mask(bz);
+    L.my = mask(by);
+    L.mx = mask(bx);
+    hipLaunchKernelGGL(k_offsets, dim3(blocks), dim3(kBlock), 0, s, h->nbr, h->n, L, h->off_m, h->off_p);
+    if ((rc = launch_status("k_offsets"))) return rc;
+    h->off_layout = L;
+    h->off_ok = true;
+    return VG_OK;
 }
 
 int launch_geometry(vg_sim *h, hipStream_t s) {
@@ -587,11 +712,13 @@ int launch_pass_bufs(vg_sim *h, int mode, int tot, double dt, const void *const 
     if (h->prec == VG_F64) {
         StepBufs<double> B;
         B.nbr = h->nbr; B.rcode = h->rcode; B.n = h->n;
+        B.off_m = h->off_m; B.off_p = h->off_p; B.dl = h->off_layout;
         for (int p = 0; p < VG_NPOOL; p++) { B.src[p] = (const double *)src[p]; B.dst[p] = (double *)dst[p]; }
         return dispatch_bufs<double>(h, mode, tot, dt, B, s);
     }
     StepBufs<float> B;
     B.nbr = h->nbr; B.rcode = h->rcode; B.n = h->n;
+    B.off_m = h->off_m; B.off_p = h->off_p; B.dl = h->off_layout;
     for (int p = 0; p < VG_NPOOL; p++) { B.src[p] = (const float *)src[p]; B.dst[p] = (float *)dst[p]; }
     return dispatch_bufs<float>(h, mode, tot, dt, B, s);
 }

@@ -177,3 +177,16 @@ def workload_inputs(key: str, shape=None):
         inits.append(init_spots(m, seed) if w.init == "spots" else init_uniform(m, seed))
     return masks, inits
 
+
+
+# Parameters the gradient workload perturbs to make its target curve: the
+# diffusing pool's D, the uptake rate, the respiration rate and the eight region
+# factors, as indices into the 20-entry parameter vector
+# [D_0..D_4, v_DOM, K_DOM, rho, mu, beta, v_SOM, v_P4, c_0..c_7].
+PERTURBED = (1, 5, 7) + tuple(range(12, 20))
+
+
+def target_factors(seed: int = 1000, spread: float = 0.1) -> dict:
+    """Multipliers 1 + U(-spread, spread) for the PERTURBED entries, in order."""
+    d = np.random.default_rng(seed).uniform(-spread, spread, len(PERTURBED))
+    return {q: 1.0 + float(v) for q, v in zip(PERTURBED, d)}

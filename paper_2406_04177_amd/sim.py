@@ -87,8 +87,14 @@ class Simulation:
         return _lib.stream_ptr(self.stream)
 
     def set_kernel(self, variant: int):
-        """Neighbour source of the explicit step: _lib.VG_KERNEL_AUTO / TABLE / RANK."""
+        """Neighbour source of the explicit step: _lib.VG_KERNEL_AUTO / TABLE / RANK / OFFSET."""
         _lib.check(self.L.vg_set_kernel(self.h, int(variant)), "vg_set_kernel")
+
+    def kernel_in_use(self) -> int:
+        """The neighbour source the next explicit pass uses (TABLE, RANK or OFFSET)."""
+        v = ctypes.c_int(-1)
+        _lib.check(self.L.vg_get_kernel(self.h, ctypes.byref(v)), "vg_get_kernel")
+        return v.value
 
     def set_params(self, params: ModelParams):
         self.params = params

@@ -1,6 +1,6 @@
 """Parity at the benchmark's full size (512^3, 17 % porosity, n ~ 20.8 M) in the
 launch configuration bench.py times: the graph bit for bit, a few FP64 steps
-bit for bit, FP32 steps within 1e-5, both neighbour sources, against the
+bit for bit, FP32 steps within 1e-5, every neighbour source, against the
 oracle run on the whole graph."""
 import numpy as np
 import pytest
@@ -49,7 +49,7 @@ def test_fp64_steps_bitwise_512(full):
     p = inputs.ModelParams()
     steps = 6
     ref, tot = orc.run(p, inputs.explicit_dt(p), og, orc.fields_from_spec(og, spec), steps)
-    for kernel in (1, 2):
+    for kernel in (1, 2, 3):
         got, log = run(g, spec, "f64", kernel, steps, log_every=3)
         np.testing.assert_array_equal(got, ref)
         np.testing.assert_allclose(log, tot[3::3], rtol=1e-13, atol=1e-300)
@@ -61,7 +61,7 @@ def test_fp32_steps_512(full):
     steps = 40
     ref, tot = orc.run(p, inputs.explicit_dt(p), og, orc.fields_from_spec(og, spec), steps)
     outs = []
-    for kernel in (1, 2):
+    for kernel in (1, 2, 3):
         got, log = run(g, spec, "f32", kernel, steps, log_every=steps)
         for s in range(5):
             scale = np.abs(ref[s]).max()
@@ -72,4 +72,5 @@ def test_fp32_steps_512(full):
             assert err <= 1e-5, (kernel, s, err)
         np.testing.assert_allclose(log[-1, 0, :5], tot[-1, 0, :5], rtol=1e-5)
         outs.append(got)
-    np.testing.assert_array_equal(outs[0], outs[1])     # the two neighbour sources agree bit for bit
+    for o in outs[1:]:
+        np.testing.assert_array_equal(outs[0], o)     # the neighbour sources agree bit for bit

@@ -34,8 +34,8 @@ def setup(shape=(48, 48, 48), seed=0, init="spots", params=None, masks=None, reg
     return g, og, specs
 
 
-TABLE, RANK = 1, 2      # neighbour source of the step kernels (identical results)
-KERNELS = pytest.mark.parametrize("kernel", [TABLE, RANK], ids=["table", "rank"])
+TABLE, RANK, OFFSET = 1, 2, 3      # neighbour source of the step kernels (identical results)
+KERNELS = pytest.mark.parametrize("kernel", [TABLE, RANK, OFFSET], ids=["table", "rank", "offset"])
 
 
 def run_gpu(g, specs, params, dt, steps, precision, log_every=0, order=0, regions=None, mobile_all=None,
@@ -113,14 +113,16 @@ def test_fp64_mortality_to_p4_bitwise(kernel):
     np.testing.assert_array_equal(sim.fields.cpu().numpy(), ref)
 
 
-def test_batch_segments_totals():
+@pytest.mark.parametrize("kernel", [TABLE, OFFSET], ids=["table", "offset"])
+def test_batch_segments_totals(kernel):
     masks = [inputs.synthetic_volume((24, 20, 16), porosity=por, seed=b)
              for b, por in enumerate((0.12, 0.25, 0.18))]
     masks.insert(2, np.zeros((24, 20, 16), np.uint8))
     p = inputs.ModelParams(mu=1e-4, rho=1e-4)
     dt = inputs.explicit_dt(p, factor=0.8)
     g, og, specs = setup(masks=masks, init="dense")
-    sim, log = run_gpu(g, specs, p, dt, 40, F64, log_every=1)
+    sim, log = run_gpu(g, specs, p, dt, 40, F64, log_every=1, kernel=kernel)
+    assert sim.kernel_in_use() == kernel
     ref, tot = run_oracle(og, specs, p, dt, 40)
     np.testing.assert_array_equal(sim.fields.cpu().numpy(), ref)
     np.testing.assert_allclose(log, tot[1:], rtol=1e-13, atol=1e-300)
@@ -139,8 +141,9 @@ def test_brick_order_equals_raster_after_unpermuting():
     a, _ = run_gpu(gr, specs, p, dt, 25, F64, kernel=TABLE)
     vr, vb = gr.vox.cpu().numpy(), gb.vox.cpu().numpy()
     perm = np.searchsorted(vr, vb)
-    for kernel in (TABLE, RANK):
+    for kernel in (TABLE, RANK, OFFSET):
         b, _ = run_gpu(gb, specs, p, dt, 25, F64, kernel=kernel)
+        assert b.kernel_in_use() == kernel
         np.testing.assert_array_equal(b.fields.cpu().numpy(), a.fields.cpu().numpy()[:, perm])
 
 
@@ -207,9 +210,11 @@ def test_rank_kernel_equals_table_kernel_bitwise(periodic, brick):
     from paper_2406_04177_amd.graph import Graph
     g = Graph.from_masks(mask, brick=brick, periodic=periodic, regions=True)
     a, la = run_gpu(g, specs, p, dt, 17, F64, log_every=4, regions=c, kernel=TABLE)
-    b, lb = run_gpu(g, specs, p, dt, 17, F64, log_every=4, regions=c, kernel=RANK)
-    np.testing.assert_array_equal(a.fields.cpu().numpy(), b.fields.cpu().numpy())
-    np.testing.assert_allclose(la, lb, rtol=1e-14)
+    for other in (RANK, OFFSET):
+        b, lb = run_gpu(g, specs, p, dt, 17, F64, log_every=4, regions=c, kernel=other)
+        assert b.kernel_in_use() == other
+        np.testing.assert_array_equal(a.fields.cpu().numpy(), b.fields.cpu().numpy())
+        np.testing.assert_allclose(la, lb, rtol=1e-14)
     og = orc.build_graph(mask, brick=brick, periodic=periodic)
     ref, _ = run_oracle(og, specs, p, dt, 17, regions=c)
     np.testing.assert_array_equal(b.fields.cpu().numpy(), ref)
@@ -226,19 +231,45 @@ def test_rank_kernel_ragged_tiles():
         specs = [inputs.init_random_all(mask, 1)]
         g = Graph.from_masks(mask)
         og = orc.build_graph(mask)
-        sim, _ = run_gpu(g, specs, p, dt, 9, F64, kernel=RANK)
         ref, _ = run_oracle(og, specs, p, dt, 9)
-        np.testing.assert_array_equal(sim.fields.cpu().numpy(), ref)
+        for kernel in (RANK, OFFSET):
+            sim, _ = run_gpu(g, specs, p, dt, 9, F64, kernel=kernel)
+            np.testing.assert_array_equal(sim.fields.cpu().numpy(), ref)
 
 
-def test_rank_kernel_refused_with_periodic_axes():
+def test_rank_and_offset_kernels_refused_with_periodic_axes():
     """Periodic graphs (tests only) always use the neighbour table."""
     from paper_2406_04177_amd import _lib
     from paper_2406_04177_amd.graph import Graph
     from paper_2406_04177_amd.sim import Simulation
     mask = np.ones((6, 7, 8), np.uint8)
-    g = Graph.from_masks(mask, periodic=7)
-    sim = Simulation(g, inputs.ModelParams(), precision="f64")
+    for periodic in (1, 2, 4, 7):
+        g = Graph.from_masks(mask, periodic=periodic)
+        sim = Simulation(g, inputs.ModelParams(), precision="f64")
+        for k in (RANK, OFFSET):
+            with pytest.raises(_lib.VgError):
+                sim.set_kernel(k)
+        sim.set_kernel(0)
+        assert sim.kernel_in_use() == TABLE
+
+
+def test_offsets_refused_when_distances_do_not_fit():
+    """A 2 x 2 x 2^17 box of pore: the z and y distances need 19 + 18 bits,
+    more than one 32-bit word, so the step uses the table."""
+    from paper_2406_04177_amd import _lib
+    from paper_2406_04177_amd.graph import Graph
+    from paper_2406_04177_amd.sim import Simulation
+    mask = np.ones((2, 2, 1 << 17), np.uint8)
+    g = Graph.from_masks(mask)
+    sim = Simulation(g, inputs.ModelParams(), precision="f64", implicit=False, rank_neighbours=False)
     with pytest.raises(_lib.VgError):
-        sim.set_kernel(RANK)
-    sim.set_kernel(0)
+        sim.set_kernel(OFFSET)
+    assert sim.kernel_in_use() == TABLE
+
+
+def test_auto_takes_offsets_for_a_raster_volume():
+    from paper_2406_04177_amd.graph import Graph
+    from paper_2406_04177_amd.sim import Simulation
+    mask = inputs.synthetic_volume((20, 20, 20), seed=1)
+    sim = Simulation(Graph.from_masks(mask), inputs.ModelParams(), precision="f32", implicit=False)
+    assert sim.kernel_in_use() == OFFSET
