@@ -40,9 +40,13 @@ BYTES_FUSED_F64 = 5 * 8 + 5 * 8 + 6 * 4
 BYTES_RANK_F32 = 5 * 4 + 5 * 4 + 4 + 8.0 / (32 * 0.17)
 # packed-offset kernel: the pools and two 4-byte offset words per voxel
 BYTES_OFFSET_F32 = 5 * 4 + 5 * 4 + 8
-KERNEL_NAMES = {1: "table", 2: "rank", 3: "offset"}
-KERNEL_FUNCS = {1: "k_step<..., table>", 2: "k_step_geo", 3: "k_step<..., offsets>"}
-OWN_BYTES = {1: BYTES_FUSED_F32, 2: BYTES_RANK_F32, 3: BYTES_OFFSET_F32}
+# relative-code kernel: the pools, one 4-byte code word per voxel and 32 B of
+# base distances per 64 voxels
+BYTES_RELATIVE_F32 = 5 * 4 + 5 * 4 + 4 + 32.0 / 64
+KERNEL_NAMES = {1: "table", 2: "rank", 3: "offset", 4: "relative"}
+KERNEL_FUNCS = {1: "k_step (6-slot table)", 2: "k_step_geo (rank index)", 3: "k_step_off (packed offsets)",
+                4: "k_step_off (relative codes)"}
+OWN_BYTES = {1: BYTES_FUSED_F32, 2: BYTES_RANK_F32, 3: BYTES_OFFSET_F32, 4: BYTES_RELATIVE_F32}
 
 # HBM bytes per launch of the headline kernel read from hardware counters
 # (FETCH_SIZE x 2 + WRITE_SIZE, the factors of a plain 1 GiB device copy on the
@@ -143,9 +147,10 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--quick", action="store_true", help="headline only (no extra rows, no CPU baseline)")
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=400,
+                    help="steps of the oracle CPU baseline (about 10-15 s on 16 cores)")
     ap.add_argument("--acc-steps", type=int, default=10000, help="steps of the 256^3 FP32-vs-FP64 row")
-    ap.add_argument("--kernel", choices=("auto", "table", "rank", "offset"), default="auto",
+    ap.add_argument("--kernel", choices=("auto", "table", "rank", "offset", "relative"), default="auto",
                     help="neighbour source of the explicit-step kernel")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="finish with three plain 1 GiB device copies (scale for HBM byte counters)")
@@ -178,7 +183,7 @@ def main(argv=None):
     log("n = %d pore voxels; graph build %.2f ms (incl. mask upload and host sync)" % (n, ms_graph))
 
     sim = Simulation(g, params, precision="f32", implicit=False, adjoint=False)
-    sim.set_kernel({"auto": 0, "table": 1, "rank": 2, "offset": 3}[args.kernel])
+    sim.set_kernel({"auto": 0, "table": 1, "rank": 2, "offset": 3, "relative": 4}[args.kernel])
     kernel = sim.kernel_in_use()
     x0 = g.fields_from_specs(spec, torch.float32)
     sim.set_fields(x0)
@@ -232,7 +237,7 @@ def main(argv=None):
         rows = {}
         rows["a1_graph_build_ms"] = ms_graph
         # the other neighbour sources on the same state, for comparison
-        for other in (1, 2, 3):
+        for other in (1, 2, 3, 4):
             if other == kernel:
                 continue
             sim.set_kernel(other)

@@ -155,17 +155,22 @@ typedef struct vg_desc {
 int vg_create(const vg_desc *desc, vg_sim **out);
 int vg_destroy(vg_sim *h);
 /* Neighbour source of the explicit-step kernels: VG_KERNEL_TABLE (the 6-slot
- * table), VG_KERNEL_RANK (the rank index; VG_EINVAL without one) or
- * VG_KERNEL_OFFSET (two packed 32-bit offset words per voxel, built by
- * vg_init_state from the table when no neighbour crosses a periodic wrap and
- * the largest distances per axis fit 32 bits together; VG_EINVAL otherwise).
- * VG_KERNEL_AUTO takes packed offsets when built, else the rank index when the
- * descriptor has a usable one, else the table.  Results are bit-identical.
- * vg_get_kernel reports the source the next explicit pass will use. */
-#define VG_KERNEL_AUTO   0
-#define VG_KERNEL_TABLE  1
-#define VG_KERNEL_RANK   2
-#define VG_KERNEL_OFFSET 3
+ * table), VG_KERNEL_RANK (the rank index; VG_EINVAL without one),
+ * VG_KERNEL_OFFSET (two packed 32-bit words of neighbour distances per voxel)
+ * or VG_KERNEL_RELATIVE (one 32-bit word of per-slot codes per voxel,
+ * relative to per-64-voxel base distances).  vg_init_state builds the last
+ * two from the table when no neighbour crosses a periodic wrap and the
+ * distances (OFFSET), or their spread within each group of 64 voxels
+ * (RELATIVE), fit the packing; choosing one that was not built is VG_EINVAL.
+ * VG_KERNEL_AUTO takes the first of RELATIVE, OFFSET, RANK (when the
+ * descriptor has a usable rank index) and TABLE that is available.  Results
+ * are bit-identical.  vg_get_kernel reports the source the next explicit
+ * pass will use. */
+#define VG_KERNEL_AUTO     0
+#define VG_KERNEL_TABLE    1
+#define VG_KERNEL_RANK     2
+#define VG_KERNEL_OFFSET   3
+#define VG_KERNEL_RELATIVE 4
 int vg_set_kernel(vg_sim *h, int variant);
 int vg_get_kernel(const vg_sim *h, int *variant_in_use);
 /* Sets the model parameters (validated: h > 0, K_DOM > 0, rates >= 0,
@@ -178,9 +183,9 @@ int vg_set_regions(vg_sim *h, const double *c);
  *   fields  [5][n] elements of the field type (float or double)
  *   alt     alt_elems elements of the field type (ping-pong of mobile pools)
  *   work    workspace_bytes bytes (reduction partials, packed neighbour
- *           offsets (8 B per voxel), geometry words with a rank index, CG
- *           vectors, adjoint ping-pong and gradient partials, as enabled by
- *           `features`). */
+ *           offsets and codes (12.5 B per voxel), geometry words with a rank
+ *           index, CG vectors, adjoint ping-pong and gradient partials, as
+ *           enabled by `features`). */
 int vg_alt_elems(const vg_sim *h, int64_t *elems);
 int vg_workspace_bytes(const vg_sim *h, size_t *bytes);
 

@@ -20,7 +20,7 @@ VG_ORDER_TD, VG_ORDER_DT = 0, 1
 VG_FORCE = 1
 VG_FEAT_CG, VG_FEAT_ADJ = 1, 2
 VG_NPOOL, VG_NREG, VG_NGRAD = 5, 8, 20
-VG_KERNEL_AUTO, VG_KERNEL_TABLE, VG_KERNEL_RANK, VG_KERNEL_OFFSET = 0, 1, 2, 3
+VG_KERNEL_AUTO, VG_KERNEL_TABLE, VG_KERNEL_RANK, VG_KERNEL_OFFSET, VG_KERNEL_RELATIVE = 0, 1, 2, 3, 4
 
 EXPORTS = ("vg_strerror", "vg_last_error", "vg_version", "vg_rank_bytes", "vg_count_pores",
            "vg_build_graph", "vg_lookup", "vg_region_codes", "vg_create", "vg_destroy",

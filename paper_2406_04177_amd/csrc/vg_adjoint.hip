@@ -122,13 +122,13 @@ __device__ __forceinline__ void transform_rev(const Coef<R> &C, const R (&x)[VG_
 
 template <typename R>
 struct AdjBufs {
-    const int32_t *nbr;
-    const uint16_t *rcode;
-    const R *st;       // stored state of this step, pool s at st + s*n
-    const R *lin;      // lambda^(k+1)
-    R *lout;           // lambda^k
-    const double *seed;   // [nseg][5] for this step
-    int64_t n, ntiles;
+    const int32_t *nbr = nullptr;
+    const uint16_t *rcode = nullptr;
+    const R *st = nullptr;       // stored state of this step, pool s at st + s*n
+    const R *lin = nullptr;      // lambda^(k+1)
+    R *lout = nullptr;           // lambda^k
+    const double *seed = nullptr;   // [nseg][5] for this step
+    int64_t n = 0, ntiles = 0;
 };
 
 template <int MOB>

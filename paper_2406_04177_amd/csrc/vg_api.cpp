@@ -53,7 +53,9 @@ size_t layout(vg_sim *h, char *base) {
     h->geo = h->rank ? (uint32_t *)take(sizeof(uint32_t) * (size_t)h->n) : nullptr;
     h->off_m = (uint32_t *)take(sizeof(uint32_t) * (size_t)h->n);
     h->off_p = (uint32_t *)take(sizeof(uint32_t) * (size_t)h->n);
-    h->off_stat = (uint32_t *)take(sizeof(uint32_t) * 4);
+    h->off_stat = (uint32_t *)take(sizeof(uint32_t) * 8);
+    h->rel_w = (uint32_t *)take(sizeof(uint32_t) * (size_t)h->n);
+    h->rel_base = (uint32_t *)take(sizeof(uint32_t) * 8 * (size_t)((h->n + kGroup - 1) / kGroup));
     const size_t nd = sizeof(double) * (size_t)h->n;
     if (h->features & VG_FEAT_CG) {
         h->cg_y = (double *)take(nd);
@@ -233,8 +235,8 @@ extern "C" int vg_destroy(vg_sim *h) {
 
 extern "C" int vg_set_kernel(vg_sim *h, int variant) {
     if (!h) { set_error("handle is NULL"); return VG_EINVAL; }
-    if (variant < VG_KERNEL_AUTO || variant > VG_KERNEL_OFFSET || (variant == VG_KERNEL_RANK && !h->rank) ||
-        (variant == VG_KERNEL_OFFSET && !h->off_ok)) {
+    if (variant < VG_KERNEL_AUTO || variant > VG_KERNEL_RELATIVE || (variant == VG_KERNEL_RANK && !h->rank) ||
+        (variant == VG_KERNEL_OFFSET && !h->off_ok) || (variant == VG_KERNEL_RELATIVE && !h->rel_ok)) {
         set_error("kernel variant %d not available", variant);
         return VG_EINVAL;
     }
@@ -244,7 +246,10 @@ extern "C" int vg_set_kernel(vg_sim *h, int variant) {
 
 extern "C" int vg_get_kernel(const vg_sim *h, int *variant_in_use) {
     if (!h || !variant_in_use) { set_error("null pointer argument"); return VG_EINVAL; }
-    *variant_in_use = vg::use_offsets(h) ? VG_KERNEL_OFFSET : vg::use_rank(h) ? VG_KERNEL_RANK : VG_KERNEL_TABLE;
+    *variant_in_use = vg::use_relative(h) ? VG_KERNEL_RELATIVE
+                      : vg::use_offsets(h) ? VG_KERNEL_OFFSET
+                      : vg::use_rank(h)    ? VG_KERNEL_RANK
+                                           : VG_KERNEL_TABLE;
     return VG_OK;
 }
 

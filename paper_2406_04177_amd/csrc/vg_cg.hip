@@ -26,12 +26,12 @@ __device__ __forceinline__ double weight(const uint16_t *rcode, const double *cl
 }
 
 struct CgArgs {
-    const int32_t *nbr;
-    const uint16_t *rcode;
-    int64_t n;
-    int64_t ntiles;
-    double a;
-    double c[VG_NREG];
+    const int32_t *nbr = nullptr;
+    const uint16_t *rcode = nullptr;
+    int64_t n = 0;
+    int64_t ntiles = 0;
+    double a = 0;
+    double c[VG_NREG] = {};
 };
 
 template <typename R, bool REG>

@@ -71,13 +71,24 @@ struct RankWord {
 };
 
 // ---------------------------------------------------------------- mapping
-// Block index -> tile index such that each XCD (blocks are dealt round-robin
-// to the 8 XCDs) works on one contiguous range of tiles, so the neighbour
-// gathers of a tile hit the L2 that already holds its neighbours.
+// Block index -> tile index.  With VG_XCD_MAP each XCD (blocks are dealt
+// round-robin to the 8 XCDs) works on one contiguous range of tiles, so the
+// neighbour gathers of a tile hit the L2 that already holds its neighbours.
+// Measured on the streaming passes it is slower (5-6 %) than the identity:
+// the shared last-level cache already serves the gathers, and eight streams
+// far apart in memory use HBM less well than one sweep in address order.
+#ifndef VG_XCD_MAP
+#define VG_XCD_MAP 0
+#endif
 __device__ inline int64_t xcd_tile(int64_t b, int64_t nb) {
+#if VG_XCD_MAP
     const int64_t q = nb / kNumXcd, r = nb % kNumXcd;
     const int64_t x = b % kNumXcd, k = b / kNumXcd;
     return x * q + (x < r ? x : r) + k;
+#else
+    (void)nb;
+    return b;
+#endif
 }
 
 // ---------------------------------------------------------------- reductions
@@ -219,6 +230,19 @@ struct DLayout {
     uint32_t mz = 0, my = 0, mx = 0;   // field masks
 };
 
+// Relative neighbour codes: one 32-bit word per voxel with a code per slot
+// k (0..5 = -x, +x, -y, +y, -z, +z) in bits [sh[k], sh[k] + width), and per
+// group of kGroup consecutive voxels one base distance per slot (8 words,
+// the last two unused).  Code 0 = absent, code c >= 1 = distance base + c - 1
+// (minus side: neighbour i - distance, plus side: i + distance).  The bases
+// are the smallest distances in the group, so the codes only have to span the
+// spread of the distances within 64 voxels (a few dozen in raster order).
+constexpr int kGroup = 64;
+struct RLayout {
+    uint32_t sh[6] = {0, 0, 0, 0, 0, 0};
+    uint32_t mk[6] = {0, 0, 0, 0, 0, 0};
+};
+
 __device__ __forceinline__ void unpack_offsets(const DLayout &L, uint32_t w, uint32_t (&d)[3]) {
     d[0] = (w >> L.sx) & L.mx;
     d[1] = (w >> L.bz) & L.my;
@@ -264,9 +288,14 @@ struct vg_sim {
     int kernel = 0;                 // 0 auto, 1 neighbour table, 2 rank index, 3 packed offsets
     // packed neighbour offsets (any volume or batch without periodic wrap)
     uint32_t *off_m = nullptr, *off_p = nullptr;   // [n] each
-    uint32_t *off_stat = nullptr;                  // [4] max offset per axis, violation flag
+    uint32_t *off_stat = nullptr;                  // [8] max offset per axis, violation flag, code spans
     bool off_ok = false;
     vg::DLayout off_layout;
+    // relative neighbour codes (4 B per voxel plus 32 B per 64 voxels)
+    uint32_t *rel_w = nullptr;      // [n]
+    uint32_t *rel_base = nullptr;   // [ceil(n / 64)][8]
+    bool rel_ok = false;
+    vg::RLayout rel_layout;
     std::vector<int32_t> piece_first_h, piece_seg_h, seg_first_h;
     std::vector<int64_t> piece_lo_h;
     int32_t *piece_first = nullptr, *piece_seg = nullptr, *seg_first = nullptr;
@@ -300,6 +329,7 @@ int launch_totals_finalize(vg_sim *h, double *out_rows, hipStream_t s);
 int launch_geometry(vg_sim *h, hipStream_t s);
 bool use_rank(const vg_sim *h);
 bool use_offsets(const vg_sim *h);
+bool use_relative(const vg_sim *h);
 int build_offsets(vg_sim *h, hipStream_t s);
 int restore_canonical(vg_sim *h, hipStream_t s);
 // vg_cg.hip

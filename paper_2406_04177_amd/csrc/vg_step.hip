@@ -76,18 +76,36 @@ __device__ __forceinline__ void transform(const Coef<R> &C, R &m1, R &m2, R &m3,
 
 template <typename R>
 struct StepBufs {
-    const int32_t *nbr;     // [6][n]
-    const uint16_t *rcode;  // [n] or null
-    const uint32_t *off_m;  // [n] packed offsets (minus side) or null
-    const uint32_t *off_p;  // [n] packed offsets (plus side) or null
+    const int32_t *nbr = nullptr;       // [6][n]
+    const uint16_t *rcode = nullptr;    // [n] or null
+    const uint32_t *off_m = nullptr;    // [n] packed offsets (minus side) or null
+    const uint32_t *off_p = nullptr;    // [n] packed offsets (plus side) or null
     DLayout dl;
-    const R *src[VG_NPOOL];
-    R *dst[VG_NPOOL];
-    int64_t n;
+    const uint32_t *rel_w = nullptr;    // [n] relative neighbour codes or null
+    const uint32_t *rel_base = nullptr; // [groups][8] base distances or null
+    RLayout rl;
+    const R *src[VG_NPOOL] = {};
+    R *dst[VG_NPOOL] = {};
+    int64_t n = 0;
 };
 
-// neighbour source of k_step
-enum { NS_TABLE = 0, NS_OFFSET = 1 };
+// The graph-side members of a pass's buffers, all taken from the handle (the
+// pool pointers are the caller's).
+template <typename R>
+StepBufs<R> graph_bufs(const vg_sim *h) {
+    StepBufs<R> B;
+    B.nbr = h->nbr;
+    B.rcode = h->rcode;
+    B.off_m = h->off_m;
+    B.off_p = h->off_p;
+    B.dl = h->off_layout;
+    B.rel_w = h->rel_w;
+    B.rel_base = h->rel_base;
+    B.rl = h->rel_layout;
+    B.n = h->n;
+    return B;
+}
+
 
 #ifndef VG_NT
 #define VG_NT 0
@@ -232,7 +250,30 @@ __device__ __forceinline__ void finish(const StepBufs<R> &B, const Coef<R> &C, c
     }
 }
 
-template <typename R, int MODE, int MOB, bool REG, int TOT, int NS>
+// Per-piece sums of the thread's accumulators (a piece is the part of a tile
+// inside one segment), written to part[piece][pool] in a fixed order.
+__device__ __forceinline__ void tile_totals(const Pieces &pc, int64_t tile, const double (&acc)[kVPT][VG_NPOOL],
+                                            double *__restrict__ part, double *lds) {
+    const int32_t p0 = pc.piece_first[tile], p1 = pc.piece_first[tile + 1];
+    for (int32_t p = p0; p < p1; p++) {
+        const int64_t lo = pc.piece_lo[p], hi = pc.piece_lo[p + 1];
+        double v5[VG_NPOOL] = {0, 0, 0, 0, 0};
+#pragma unroll
+        for (int v = 0; v < kVPT; v++) {
+            const int64_t i = tile * kTile + v * kBlock + threadIdx.x;
+            const bool in = i >= lo && i < hi;
+#pragma unroll
+            for (int s = 0; s < VG_NPOOL; s++) v5[s] += in ? acc[v][s] : 0.0;
+        }
+        block_sum<VG_NPOOL>(v5, lds);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int s = 0; s < VG_NPOOL; s++) part[(int64_t)p * VG_NPOOL + s] = v5[s];
+        }
+    }
+}
+
+template <typename R, int MODE, int MOB, bool REG, int TOT>
 __global__ __launch_bounds__(kBlock) void k_step(StepBufs<R> B, Coef<R> C, Pieces pc, double *__restrict__ part) {
     __shared__ double lds[kWaves * VG_NPOOL];
     __shared__ R cl[VG_NREG];
@@ -255,20 +296,8 @@ __global__ __launch_bounds__(kBlock) void k_step(StepBufs<R> B, Coef<R> C, Piece
     if (do_d) {
 #pragma unroll
         for (int v = 0; v < kVPT; v++) {
-            if (NS == NS_TABLE) {
 #pragma unroll
-                for (int k = 0; k < 6; k++) j[v][k] = ld_once(&B.nbr[(int64_t)k * B.n + ic[v]]);
-            } else {
-                uint32_t dm[3], dp[3];
-                unpack_offsets(B.dl, ld_once(&B.off_m[ic[v]]), dm);
-                unpack_offsets(B.dl, ld_once(&B.off_p[ic[v]]), dp);
-                const int32_t i32 = (int32_t)ic[v];
-#pragma unroll
-                for (int a = 0; a < 3; a++) {
-                    j[v][2 * a] = dm[a] ? i32 - (int32_t)dm[a] : -1;
-                    j[v][2 * a + 1] = dp[a] ? i32 + (int32_t)dp[a] : -1;
-                }
-            }
+            for (int k = 0; k < 6; k++) j[v][k] = ld_once(&B.nbr[(int64_t)k * B.n + ic[v]]);
             if (REG) {
                 const uint32_t code = B.rcode[ic[v]];
                 const uint32_t own = code & 7u;
@@ -284,25 +313,146 @@ __global__ __launch_bounds__(kBlock) void k_step(StepBufs<R> B, Coef<R> C, Piece
     load_own<R, MODE, MOB, TOT>(B, ic, x);
     double acc[kVPT][VG_NPOOL];
     finish<R, MODE, MOB, REG, TOT>(B, C, ic, act, j, w, x, acc);
-    if (TOT != TOT_NONE) {
-        const int32_t p0 = pc.piece_first[tile], p1 = pc.piece_first[tile + 1];
-        for (int32_t p = p0; p < p1; p++) {
-            const int64_t lo = pc.piece_lo[p], hi = pc.piece_lo[p + 1];
-            double v5[VG_NPOOL] = {0, 0, 0, 0, 0};
+    if (TOT != TOT_NONE) tile_totals(pc, tile, acc, part, lds);
+}
+
+// Element idx of an array whose base is uniform across the wave: a 32-bit
+// byte offset from the base, so that the whole address arithmetic of a voxel
+// is one shift (valid while n * sizeof(T) < 2^32, checked on the host).
+template <typename T>
+__device__ __forceinline__ const T &at(const T *base, uint32_t idx) {
+    return *(const T *)((const char *)base + (idx * (uint32_t)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ T &at(T *base, uint32_t idx) {
+    return *(T *)((char *)base + (idx * (uint32_t)sizeof(T)));
+}
+
+// Packed-offset variant of the diffusing passes (D and DT).  Neighbour j of
+// voxel i is i - d or i + d with d unpacked from the voxel's two offset words;
+// an absent neighbour has d = 0 and so reads the voxel itself, whose
+// difference x_i - x_i is exactly +0 (the absent slot's zero) for finite
+// values, so no selects are needed.  All indices are 32-bit.
+template <typename R, int MODE, int MOB, bool REG, int TOT, bool RELC>
+__global__ __launch_bounds__(kBlock) void k_step_off(StepBufs<R> B, Coef<R> C, Pieces pc, double *__restrict__ part) {
+    static_assert(MODE == MODE_D || MODE == MODE_DT, "diffusing passes only");
+    __shared__ double lds[kWaves * VG_NPOOL];
+    __shared__ R cl[VG_NREG];
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t n = (uint32_t)B.n;
+    if (REG) {
+        if (threadIdx.x < VG_NREG) cl[threadIdx.x] = C.c[threadIdx.x];
+        __syncthreads();
+    }
+    uint32_t ic[kVPT];
+    bool act[kVPT];
 #pragma unroll
-            for (int v = 0; v < kVPT; v++) {
-                const int64_t i = tile * kTile + v * kBlock + threadIdx.x;
-                const bool in = i >= lo && i < hi;
+    for (int v = 0; v < kVPT; v++) {
+        const uint32_t i = (uint32_t)tile * (uint32_t)kTile + (uint32_t)(v * kBlock) + threadIdx.x;
+        act[v] = i < n;
+        ic[v] = act[v] ? i : n - 1;
+    }
+    uint32_t wm[kVPT], wp[kVPT];
 #pragma unroll
-                for (int s = 0; s < VG_NPOOL; s++) v5[s] += in ? acc[v][s] : 0.0;
+    for (int v = 0; v < kVPT; v++) {
+        if (RELC) {
+            wm[v] = ld_once(&at(B.rel_w, ic[v]));
+            wp[v] = 0;
+        } else {
+            wm[v] = ld_once(&at(B.off_m, ic[v]));
+            wp[v] = ld_once(&at(B.off_p, ic[v]));
+        }
+    }
+    R x[kVPT][VG_NPOOL];
+#pragma unroll
+    for (int v = 0; v < kVPT; v++)
+#pragma unroll
+        for (int s = 0; s < VG_NPOOL; s++)
+            x[v][s] = reads<MODE, MOB, TOT>(s) ? (mobile<MOB>(s) ? at(B.src[s], ic[v]) : ld_once(&at(B.src[s], ic[v])))
+                                               : R(0);
+    uint32_t j[kVPT][6];
+    R w[kVPT][6];
+#pragma unroll
+    for (int v = 0; v < kVPT; v++) {
+        if (RELC) {
+            // the 64 voxels of a wave form one group (lanes past n hold n - 1,
+            // which lies in the same group), so the group index is uniform
+            const uint32_t grp = __builtin_amdgcn_readfirstlane(ic[v] / (uint32_t)kGroup);
+            const uint32_t *bp = B.rel_base + (size_t)grp * 8;
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                const uint32_t c = (wm[v] >> B.rl.sh[k]) & B.rl.mk[k];
+                const uint32_t d = c ? bp[k] + (c - 1u) : 0u;
+                j[v][k] = (k & 1) ? ic[v] + d : ic[v] - d;
             }
-            block_sum<VG_NPOOL>(v5, lds);
-            if (threadIdx.x == 0) {
+        } else {
+            uint32_t dm[3], dp[3];
+            unpack_offsets(B.dl, wm[v], dm);
+            unpack_offsets(B.dl, wp[v], dp);
 #pragma unroll
-                for (int s = 0; s < VG_NPOOL; s++) part[(int64_t)p * VG_NPOOL + s] = v5[s];
+            for (int a = 0; a < 3; a++) {
+                j[v][2 * a] = ic[v] - dm[a];
+                j[v][2 * a + 1] = ic[v] + dp[a];
+            }
+        }
+        if (REG) {
+            const uint32_t code = at(B.rcode, ic[v]);
+            const uint32_t own = code & 7u;
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                const uint32_t other = own ^ (((code >> (3 + k)) & 1u) << (k >> 1));
+                w[v][k] = R(0.5) * (cl[own] + cl[other]);
             }
         }
     }
+    double acc[kVPT][VG_NPOOL];
+#pragma unroll
+    for (int v = 0; v < kVPT; v++)
+#pragma unroll
+        for (int s = 0; s < VG_NPOOL; s++) acc[v][s] = (TOT == TOT_IN && act[v]) ? (double)x[v][s] : 0.0;
+    // Scheme 1: every gather of the thread first, then the sums
+    constexpr int NM = MOB == 2 ? VG_NPOOL : 1;
+    R g[kVPT][NM][6];
+#pragma unroll
+    for (int v = 0; v < kVPT; v++)
+#pragma unroll
+        for (int m = 0; m < NM; m++)
+#pragma unroll
+            for (int k = 0; k < 6; k++) g[v][m][k] = at(B.src[NM == 1 ? 1 : m], j[v][k]);
+#pragma unroll
+    for (int v = 0; v < kVPT; v++)
+#pragma unroll
+        for (int m = 0; m < NM; m++) {
+            const int s = NM == 1 ? 1 : m;
+            const R xi = x[v][s];
+            R d[6];
+#pragma unroll
+            for (int k = 0; k < 6; k++) d[k] = REG ? w[v][k] * (g[v][m][k] - xi) : g[v][m][k] - xi;
+            const R sum = ((d[0] + d[1]) + (d[2] + d[3])) + (d[4] + d[5]);
+            x[v][s] = xi + C.a[s] * sum;
+        }
+#pragma unroll
+    for (int v = 0; v < kVPT; v++) {
+        if (TOT == TOT_MID && act[v]) {
+#pragma unroll
+            for (int s = 0; s < VG_NPOOL; s++) acc[v][s] = (double)x[v][s];
+        }
+        if (MODE == MODE_DT) transform(C, x[v][0], x[v][1], x[v][2], x[v][3], x[v][4]);
+        if (TOT == TOT_OUT && act[v]) {
+#pragma unroll
+            for (int s = 0; s < VG_NPOOL; s++) acc[v][s] = (double)x[v][s];
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < kVPT; v++) {
+        if (!act[v]) continue;
+#pragma unroll
+        for (int s = 0; s < VG_NPOOL; s++) {
+            if (mobile<MOB>(s)) at(B.dst[s], ic[v]) = x[v][s];
+            else if (MODE != MODE_D) st_once(&at(B.dst[s], ic[v]), x[v][s]);
+        }
+    }
+    if (TOT != TOT_NONE) tile_totals(pc, tile, acc, part, lds);
 }
 
 // Rank-index variant (single volume: one piece per tile).  Each voxel has a
@@ -506,6 +656,54 @@ __global__ __launch_bounds__(kBlock) void k_offsets(const int32_t *__restrict__ 
     off_p[i] = wp;
 }
 
+// Relative codes, pass 1: per group of 64 voxels (one wave) and slot, the
+// smallest distance (the base) and the spread + 1 of the distances; the
+// largest spread + 1 per axis goes to stat[4 + axis].  Assumes the slot
+// directions that k_offset_stat verifies.
+__global__ __launch_bounds__(kBlock) void k_rel_stat(const int32_t *__restrict__ nbr, int64_t n,
+                                                     uint32_t *__restrict__ base, uint32_t *__restrict__ stat) {
+    static_assert(kGroup == 64, "a group is one wave");
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    uint32_t span[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        const int32_t j = i < n ? nbr[(int64_t)k * n + i] : -1;
+        const bool pres = j >= 0;
+        const uint32_t d = pres ? (uint32_t)((k & 1) ? (int64_t)j - i : i - (int64_t)j) : 0u;
+        uint32_t lo = pres ? d : 0xffffffffu, hi = pres ? d : 0u;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, 64));
+            hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, 64));
+        }
+        if ((threadIdx.x & 63) == 0 && i < n) base[(i / kGroup) * 8 + k] = lo == 0xffffffffu ? 0u : lo;
+        if (lo != 0xffffffffu) span[k >> 1] = max(span[k >> 1], hi - lo + 1u);
+    }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+            if (span[a]) atomicMax(&stat[4 + a], span[a]);
+    }
+}
+
+// Relative codes, pass 2: the code word of every voxel.
+__global__ __launch_bounds__(kBlock) void k_rel_pack(const int32_t *__restrict__ nbr, int64_t n,
+                                                     const uint32_t *__restrict__ base, RLayout L,
+                                                     uint32_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t *bp = base + (i / kGroup) * 8;
+    uint32_t w = 0;
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        const int32_t j = nbr[(int64_t)k * n + i];
+        if (j < 0) continue;
+        const uint32_t d = (uint32_t)((k & 1) ? (int64_t)j - i : i - (int64_t)j);
+        w |= (d - bp[k] + 1u) << L.sh[k];
+    }
+    out[i] = w;
+}
+
 // Totals, stage 1: chunks of up to kChunk pieces of one segment.
 __global__ __launch_bounds__(kBlock) void k_tot_chunks(const double *__restrict__ part,
                                                        const int32_t *__restrict__ chunk_first,
@@ -564,10 +762,17 @@ RGeom make_rgeom(const vg_sim *h) {
 template <typename R, int MODE, int MOB, bool REG, int TOT>
 int launch_one(vg_sim *h, const StepBufs<R> &B, const Coef<R> &C, hipStream_t s) {
     Pieces pc{h->piece_first, h->piece_lo, h->piece_seg, h->npieces};
-    if (use_offsets(h) && MODE != MODE_NONE && MODE != MODE_T) {
-        hipLaunchKernelGGL((k_step<R, MODE, MOB, REG, TOT, NS_OFFSET>), dim3((unsigned)h->ntiles), dim3(kBlock), 0, s,
-                           B, C, pc, h->part);
-        return launch_status("k_step offsets");
+    if constexpr (MODE == MODE_D || MODE == MODE_DT) {
+        if (use_relative(h)) {
+            hipLaunchKernelGGL((k_step_off<R, MODE, MOB, REG, TOT, true>), dim3((unsigned)h->ntiles), dim3(kBlock), 0,
+                               s, B, C, pc, h->part);
+            return launch_status("k_step_off relative");
+        }
+        if (use_offsets(h)) {
+            hipLaunchKernelGGL((k_step_off<R, MODE, MOB, REG, TOT, false>), dim3((unsigned)h->ntiles), dim3(kBlock), 0,
+                               s, B, C, pc, h->part);
+            return launch_status("k_step_off");
+        }
     }
     if (use_rank(h) && MODE != MODE_NONE) {
         if (h->brick == 0)
@@ -578,7 +783,7 @@ int launch_one(vg_sim *h, const StepBufs<R> &B, const Coef<R> &C, hipStream_t s)
                                s, B, C, make_rgeom(h), h->geo, h->part);
         return launch_status("k_step_geo");
     }
-    hipLaunchKernelGGL((k_step<R, MODE, MOB, REG, TOT, NS_TABLE>), dim3((unsigned)h->ntiles), dim3(kBlock), 0, s, B,
+    hipLaunchKernelGGL((k_step<R, MODE, MOB, REG, TOT>), dim3((unsigned)h->ntiles), dim3(kBlock), 0, s, B,
                        C, pc, h->part);
     return launch_status("k_step");
 }
@@ -612,13 +817,7 @@ int dispatch_bufs(vg_sim *h, int mode, int tot, double dt, const StepBufs<R> &B,
 
 template <typename R>
 int dispatch(vg_sim *h, int mode, int tot, double dt, hipStream_t s) {
-    StepBufs<R> B;
-    B.nbr = h->nbr;
-    B.rcode = h->rcode;
-    B.off_m = h->off_m;
-    B.off_p = h->off_p;
-    B.dl = h->off_layout;
-    B.n = h->n;
+    StepBufs<R> B = graph_bufs<R>(h);
     const int mob = h->mobile_mode();
     R *canon = (R *)h->fields;
     R *alt = (R *)h->alt;
@@ -643,14 +842,19 @@ int dispatch(vg_sim *h, int mode, int tot, double dt, hipStream_t s) {
 
 // Neighbour source: an explicit choice, else packed offsets when they fit,
 // else the rank index when there is one, else the table.
+bool use_relative(const vg_sim *h) {
+    return h->rel_ok && (h->kernel == VG_KERNEL_AUTO || h->kernel == VG_KERNEL_RELATIVE);
+}
+
 bool use_offsets(const vg_sim *h) {
-    return h->off_ok && (h->kernel == VG_KERNEL_AUTO || h->kernel == VG_KERNEL_OFFSET);
+    if (h->kernel == VG_KERNEL_OFFSET) return h->off_ok;
+    return h->off_ok && h->kernel == VG_KERNEL_AUTO && !h->rel_ok;
 }
 
 bool use_rank(const vg_sim *h) {
     const bool ok = h->rank != nullptr && h->geo != nullptr && h->nseg == 1;
     if (h->kernel == VG_KERNEL_RANK) return ok;
-    return ok && h->kernel == VG_KERNEL_AUTO && !h->off_ok;
+    return ok && h->kernel == VG_KERNEL_AUTO && !h->off_ok && !h->rel_ok;
 }
 
 static uint32_t bit_width(uint32_t v) {
@@ -663,20 +867,44 @@ static uint32_t bit_width(uint32_t v) {
 // offsets.  Synchronises the stream (the layout is chosen on the host).
 int build_offsets(vg_sim *h, hipStream_t s) {
     h->off_ok = false;
-    if (h->n == 0 || !h->off_m || !h->nbr) return VG_OK;
+    h->rel_ok = false;
+    if (h->n == 0 || !h->off_m || !h->rel_w || !h->nbr) return VG_OK;
     int rc;
-    if ((rc = hip_status(hipMemsetAsync(h->off_stat, 0, 4 * sizeof(uint32_t), s), "clear offset statistics")))
+    if ((rc = hip_status(hipMemsetAsync(h->off_stat, 0, 8 * sizeof(uint32_t), s), "clear offset statistics")))
         return rc;
     const unsigned blocks = (unsigned)((h->n + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_offset_stat, dim3(blocks), dim3(kBlock), 0, s, h->nbr, h->n, h->off_stat);
     if ((rc = launch_status("k_offset_stat"))) return rc;
-    uint32_t st[4] = {0, 0, 0, 0};
+    hipLaunchKernelGGL(k_rel_stat, dim3(blocks), dim3(kBlock), 0, s, h->nbr, h->n, h->rel_base, h->off_stat);
+    if ((rc = launch_status("k_rel_stat"))) return rc;
+    uint32_t st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if ((rc = hip_status(hipMemcpyAsync(st, h->off_stat, sizeof(st), hipMemcpyDeviceToHost, s), "read offsets")))
         return rc;
     if ((rc = hip_status(hipStreamSynchronize(s), "synchronise"))) return rc;
     const uint32_t bx = bit_width(st[0]), by = bit_width(st[1]), bz = bit_width(st[2]);
-    if (st[3] || bx + by + bz > 32) return VG_OK;     // periodic wrap, or too far apart: no packed offsets
+    // periodic wrap or byte offsets beyond 32 bits: neither packing
+    if (st[3] || (uint64_t)h->n * h->elem() >= ((uint64_t)1 << 32)) return VG_OK;
     auto mask = [](uint32_t b) { return b >= 32 ? 0xffffffffu : (1u << b) - 1u; };
+    // relative codes: widths from the largest spread + 1 per axis
+    const uint32_t cx = bit_width(st[4]), cy = bit_width(st[5]), cz = bit_width(st[6]);
+    if (2 * (cx + cy + cz) <= 32) {
+        RLayout R;
+        const uint32_t width[6] = {cx, cx, cy, cy, cz, cz};
+        const uint32_t order[6] = {4, 5, 2, 3, 0, 1};      // z-, z+, y-, y+, x-, x+ from bit 0 up
+        uint32_t at_bit = 0;
+        for (int q = 0; q < 6; q++) {
+            const uint32_t k = order[q];
+            R.sh[k] = at_bit & 31u;                         // a zero-width field's shift is never used
+            R.mk[k] = mask(width[k]);
+            at_bit += width[k];
+        }
+        hipLaunchKernelGGL(k_rel_pack, dim3(blocks), dim3(kBlock), 0, s, h->nbr, h->n, h->rel_base, R, h->rel_w);
+        if ((rc = launch_status("k_rel_pack"))) return rc;
+        h->rel_layout = R;
+        h->rel_ok = true;
+    }
+    // neighbours too far apart: no packed offsets
+    if (bx + by + bz > 32) return VG_OK;
     DLayout L;
     L.bz = bz & 31u;                     // an empty field's shift is never used
     L.by = by;
@@ -710,15 +938,11 @@ int launch_pass_bufs(vg_sim *h, int mode, int tot, double dt, const void *const 
                      void *const dst[VG_NPOOL], hipStream_t s) {
     if (h->n == 0) return VG_OK;
     if (h->prec == VG_F64) {
-        StepBufs<double> B;
-        B.nbr = h->nbr; B.rcode = h->rcode; B.n = h->n;
-        B.off_m = h->off_m; B.off_p = h->off_p; B.dl = h->off_layout;
+        StepBufs<double> B = graph_bufs<double>(h);
         for (int p = 0; p < VG_NPOOL; p++) { B.src[p] = (const double *)src[p]; B.dst[p] = (double *)dst[p]; }
         return dispatch_bufs<double>(h, mode, tot, dt, B, s);
     }
-    StepBufs<float> B;
-    B.nbr = h->nbr; B.rcode = h->rcode; B.n = h->n;
-    B.off_m = h->off_m; B.off_p = h->off_p; B.dl = h->off_layout;
+    StepBufs<float> B = graph_bufs<float>(h);
     for (int p = 0; p < VG_NPOOL; p++) { B.src[p] = (const float *)src[p]; B.dst[p] = (float *)dst[p]; }
     return dispatch_bufs<float>(h, mode, tot, dt, B, s);
 }

@@ -87,11 +87,11 @@ class Simulation:
         return _lib.stream_ptr(self.stream)
 
     def set_kernel(self, variant: int):
-        """Neighbour source of the explicit step: _lib.VG_KERNEL_AUTO / TABLE / RANK / OFFSET."""
+        """Neighbour source of the explicit step: _lib.VG_KERNEL_AUTO / TABLE / RANK / OFFSET / RELATIVE."""
         _lib.check(self.L.vg_set_kernel(self.h, int(variant)), "vg_set_kernel")
 
     def kernel_in_use(self) -> int:
-        """The neighbour source the next explicit pass uses (TABLE, RANK or OFFSET)."""
+        """The neighbour source the next explicit pass uses (TABLE, RANK, OFFSET or RELATIVE)."""
         v = ctypes.c_int(-1)
         _lib.check(self.L.vg_get_kernel(self.h, ctypes.byref(v)), "vg_get_kernel")
         return v.value

@@ -180,3 +180,42 @@ def test_gradient_matches_central_differences_on_gpu_fp64():
         if abs(grad[q] - fd) > 1e-3 * abs(fd) + noise:
             bad.append((q, grad[q], fd, noise))
     assert not bad, bad
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_record_identical_for_every_neighbour_source(precision):
+    """The adjoint's forward recording runs the step kernels on the caller's
+    state buffers: every neighbour source records the same states, bit for
+    bit, and they equal the oracle's (FP64)."""
+    from paper_2406_04177_amd import _lib
+    from paper_2406_04177_amd.graph import Graph
+    from paper_2406_04177_amd.sim import Simulation
+    masks, specs = batch(seed=5)
+    p = rates()
+    c = [1.0, 0.9, 0.8, 1.05, 0.95, 0.85, 1.0, 0.9]
+    dt = inputs.explicit_dt(p, 0.8)
+    g = Graph.from_masks(masks, regions=True)
+    dtype = torch.float64 if precision == "f64" else torch.float32
+    x0 = g.fields_from_specs(specs, dtype)
+    k = 9
+    out = {}
+    for kernel in (_lib.VG_KERNEL_TABLE, _lib.VG_KERNEL_OFFSET, _lib.VG_KERNEL_RELATIVE):
+        sim = Simulation(g, p, precision=precision, implicit=False, adjoint=True, regions=c)
+        sim.set_kernel(kernel)
+        assert sim.kernel_in_use() == kernel
+        sim.set_fields(x0)
+        states = torch.empty((k, 5, g.n), dtype=dtype, device="cuda")
+        sim.record(k, dt, states)
+        torch.cuda.synchronize()
+        out[kernel] = states.cpu().numpy()
+    ref = out[_lib.VG_KERNEL_TABLE]
+    for kernel, st in out.items():
+        np.testing.assert_array_equal(st, ref)
+    if precision == "f64":
+        og = orc.build_batch(masks)
+        w = orc.edge_weights(og, orc.octant_regions(og), c)
+        xs = orc.run_states(p, dt, og, orc.fields_from_spec(og, specs), k - 1, w=w)
+        # states[0] = x^0, states[j] = T(x^(j-1) after j-1 full steps' diffusion), as recorded
+        np.testing.assert_array_equal(ref[0], xs[0])
+        for j in range(1, k):
+            np.testing.assert_array_equal(ref[j], orc.transform(p, dt, xs[j - 1]))

@@ -49,7 +49,7 @@ def test_fp64_steps_bitwise_512(full):
     p = inputs.ModelParams()
     steps = 6
     ref, tot = orc.run(p, inputs.explicit_dt(p), og, orc.fields_from_spec(og, spec), steps)
-    for kernel in (1, 2, 3):
+    for kernel in (1, 2, 3, 4):
         got, log = run(g, spec, "f64", kernel, steps, log_every=3)
         np.testing.assert_array_equal(got, ref)
         np.testing.assert_allclose(log, tot[3::3], rtol=1e-13, atol=1e-300)
@@ -61,7 +61,7 @@ def test_fp32_steps_512(full):
     steps = 40
     ref, tot = orc.run(p, inputs.explicit_dt(p), og, orc.fields_from_spec(og, spec), steps)
     outs = []
-    for kernel in (1, 2, 3):
+    for kernel in (1, 2, 3, 4):
         got, log = run(g, spec, "f32", kernel, steps, log_every=steps)
         for s in range(5):
             scale = np.abs(ref[s]).max()

@@ -34,8 +34,21 @@ def setup(shape=(48, 48, 48), seed=0, init="spots", params=None, masks=None, reg
     return g, og, specs
 
 
-TABLE, RANK, OFFSET = 1, 2, 3      # neighbour source of the step kernels (identical results)
-KERNELS = pytest.mark.parametrize("kernel", [TABLE, RANK, OFFSET], ids=["table", "rank", "offset"])
+TABLE, RANK, OFFSET, RELATIVE = 1, 2, 3, 4      # neighbour source of the step kernels (identical results)
+KERNELS = pytest.mark.parametrize("kernel", [TABLE, RANK, OFFSET, RELATIVE], ids=["table", "rank", "offset", "relative"])
+
+
+def available(g, kernel):
+    """Whether the graph admits a neighbour source (the packed ones depend on
+    the distances in the enumeration: brick orders rarely fit them)."""
+    from paper_2406_04177_amd import _lib
+    from paper_2406_04177_amd.sim import Simulation
+    sim = Simulation(g, inputs.ModelParams(), precision="f32", implicit=False)
+    try:
+        sim.set_kernel(kernel)
+    except _lib.VgError:
+        return False
+    return True
 
 
 def run_gpu(g, specs, params, dt, steps, precision, log_every=0, order=0, regions=None, mobile_all=None,
@@ -113,7 +126,7 @@ def test_fp64_mortality_to_p4_bitwise(kernel):
     np.testing.assert_array_equal(sim.fields.cpu().numpy(), ref)
 
 
-@pytest.mark.parametrize("kernel", [TABLE, OFFSET], ids=["table", "offset"])
+@pytest.mark.parametrize("kernel", [TABLE, OFFSET, RELATIVE], ids=["table", "offset", "relative"])
 def test_batch_segments_totals(kernel):
     masks = [inputs.synthetic_volume((24, 20, 16), porosity=por, seed=b)
              for b, por in enumerate((0.12, 0.25, 0.18))]
@@ -141,10 +154,15 @@ def test_brick_order_equals_raster_after_unpermuting():
     a, _ = run_gpu(gr, specs, p, dt, 25, F64, kernel=TABLE)
     vr, vb = gr.vox.cpu().numpy(), gb.vox.cpu().numpy()
     perm = np.searchsorted(vr, vb)
-    for kernel in (TABLE, RANK, OFFSET):
+    ran = []
+    for kernel in (TABLE, RANK, OFFSET, RELATIVE):
+        if not available(gb, kernel):
+            continue
+        ran.append(kernel)
         b, _ = run_gpu(gb, specs, p, dt, 25, F64, kernel=kernel)
         assert b.kernel_in_use() == kernel
         np.testing.assert_array_equal(b.fields.cpu().numpy(), a.fields.cpu().numpy()[:, perm])
+    assert ran[:2] == [TABLE, RANK], ran
 
 
 @KERNELS
@@ -210,7 +228,10 @@ def test_rank_kernel_equals_table_kernel_bitwise(periodic, brick):
     from paper_2406_04177_amd.graph import Graph
     g = Graph.from_masks(mask, brick=brick, periodic=periodic, regions=True)
     a, la = run_gpu(g, specs, p, dt, 17, F64, log_every=4, regions=c, kernel=TABLE)
-    for other in (RANK, OFFSET):
+    for other in (RANK, OFFSET, RELATIVE):
+        if other != RANK and not available(g, other):
+            assert brick > 0      # raster order always admits both packings here
+            continue
         b, lb = run_gpu(g, specs, p, dt, 17, F64, log_every=4, regions=c, kernel=other)
         assert b.kernel_in_use() == other
         np.testing.assert_array_equal(a.fields.cpu().numpy(), b.fields.cpu().numpy())
@@ -232,7 +253,7 @@ def test_rank_kernel_ragged_tiles():
         g = Graph.from_masks(mask)
         og = orc.build_graph(mask)
         ref, _ = run_oracle(og, specs, p, dt, 9)
-        for kernel in (RANK, OFFSET):
+        for kernel in (RANK, OFFSET, RELATIVE):
             sim, _ = run_gpu(g, specs, p, dt, 9, F64, kernel=kernel)
             np.testing.assert_array_equal(sim.fields.cpu().numpy(), ref)
 
@@ -246,7 +267,7 @@ def test_rank_and_offset_kernels_refused_with_periodic_axes():
     for periodic in (1, 2, 4, 7):
         g = Graph.from_masks(mask, periodic=periodic)
         sim = Simulation(g, inputs.ModelParams(), precision="f64")
-        for k in (RANK, OFFSET):
+        for k in (RANK, OFFSET, RELATIVE):
             with pytest.raises(_lib.VgError):
                 sim.set_kernel(k)
         sim.set_kernel(0)
@@ -255,7 +276,8 @@ def test_rank_and_offset_kernels_refused_with_periodic_axes():
 
 def test_offsets_refused_when_distances_do_not_fit():
     """A 2 x 2 x 2^17 box of pore: the z and y distances need 19 + 18 bits,
-    more than one 32-bit word, so the step uses the table."""
+    more than one 32-bit word, so there are no packed offsets (the relative
+    codes fit: every distance is the same within a group)."""
     from paper_2406_04177_amd import _lib
     from paper_2406_04177_amd.graph import Graph
     from paper_2406_04177_amd.sim import Simulation
@@ -264,12 +286,38 @@ def test_offsets_refused_when_distances_do_not_fit():
     sim = Simulation(g, inputs.ModelParams(), precision="f64", implicit=False, rank_neighbours=False)
     with pytest.raises(_lib.VgError):
         sim.set_kernel(OFFSET)
+    assert sim.kernel_in_use() == RELATIVE
+    sim.set_kernel(TABLE)
     assert sim.kernel_in_use() == TABLE
 
 
-def test_auto_takes_offsets_for_a_raster_volume():
+def test_relative_codes_refused_when_spreads_do_not_fit():
+    """A 16^3 box of pore in 4^3 bricks: within a group of 64 voxels the
+    distances jump between in-brick and cross-brick neighbours (spreads of
+    61, 241 and 961 need 2 * (6 + 8 + 10) bits), so there are no relative
+    codes, while the largest distances (61, 244, 976: 6 + 8 + 10 bits) fit
+    the packed offsets."""
+    from paper_2406_04177_amd import _lib
+    from paper_2406_04177_amd.graph import Graph
+    from paper_2406_04177_amd.sim import Simulation
+    mask = np.ones((16, 16, 16), np.uint8)
+    g = Graph.from_masks(mask, brick=4)
+    sim = Simulation(g, inputs.ModelParams(), precision="f64", implicit=False)
+    with pytest.raises(_lib.VgError):
+        sim.set_kernel(RELATIVE)
+    assert sim.kernel_in_use() == OFFSET
+    specs = [inputs.init_random_all(mask, 3)]
+    og = orc.build_graph(mask, brick=4)
+    p = inputs.ModelParams(mu=1e-4, rho=1e-4)
+    dt = inputs.explicit_dt(p)
+    ref, _ = run_oracle(og, specs, p, dt, 5)
+    got, _ = run_gpu(g, specs, p, dt, 5, F64, kernel=OFFSET)
+    np.testing.assert_array_equal(got.fields.cpu().numpy(), ref)
+
+
+def test_auto_takes_relative_codes_for_a_raster_volume():
     from paper_2406_04177_amd.graph import Graph
     from paper_2406_04177_amd.sim import Simulation
     mask = inputs.synthetic_volume((20, 20, 20), seed=1)
     sim = Simulation(Graph.from_masks(mask), inputs.ModelParams(), precision="f32", implicit=False)
-    assert sim.kernel_in_use() == OFFSET
+    assert sim.kernel_in_use() == RELATIVE
