@@ -140,6 +140,57 @@ def accuracy_256(steps, N=256):
     return res
 
 
+def gradient_batch(steps, K=100):
+    """The gradient workload: 16 x 128^3 volumes (porosities U(0.12, 0.25)),
+    FP32 fields, CO2 totals every step, loss = MSE against the curve of the
+    perturbed parameters, checkpoints every K steps.  Times a plain forward
+    run and a full gradient (checkpointed forward + reverse sweep)."""
+    import torch
+    from paper_2406_04177_amd import inputs
+    from paper_2406_04177_amd.autograd import co2_mse, simulate_totals, theta_of
+    from paper_2406_04177_amd.graph import Graph
+    from paper_2406_04177_amd.sim import Simulation
+    masks, specs = inputs.workload_inputs("b16x128")
+    params = inputs.ModelParams()
+    dt = inputs.explicit_dt(params, 0.8)
+    g = Graph.from_masks(masks, regions=True)
+    c = [1.0] * 8
+    sim = Simulation(g, params, precision="f32", implicit=False, adjoint=True, regions=c)
+    x0 = g.fields_from_specs(specs, torch.float32)
+    theta = theta_of(params, c)
+    tgt_theta = theta.clone()
+    for q, f in inputs.target_factors().items():
+        tgt_theta[q] *= f
+    with torch.no_grad():
+        target = simulate_totals(sim, tgt_theta, x0, steps, dt, K)[:, :, 4].clone()
+    sim.set_fields(x0)
+    sim.set_params(params)
+    sim.set_regions(c)
+    sim.step(100, dt, log_every=1)
+    sim.set_fields(x0)
+    ms_fwd, _ = timed(lambda: sim.step(steps, dt, log_every=1))
+    res = {"workload": "16 x 128^3 batch (n = %d), %d FP32 steps, CO2 totals every step, checkpoints every %d"
+                       % (g.n, steps, K), "forward_ms": ms_fwd}
+
+    def grad():
+        th = theta.clone().requires_grad_(True)
+        loss = co2_mse(simulate_totals(sim, th, x0, steps, dt, K), target)
+        loss.backward()
+        return th.grad
+    for skip in (False, True):
+        sim.set_adjoint_options(skip_static_d=skip)
+        grad()
+        ms_g, gr = timed(grad)
+        key = "skip_static_d" if skip else "all_d"
+        res["gradient_ms_" + key] = ms_g
+        res["gradient_forward_ratio_" + key] = ms_g / ms_fwd
+        res["backward_forward_ratio_" + key] = (ms_g - ms_fwd) / ms_fwd
+    log("16 x 128^3 gradient: forward %.1f ms, gradient %.1f ms (ratio %.2f), skipping static D %.1f ms (%.2f)"
+        % (ms_fwd, res["gradient_ms_all_d"], res["gradient_forward_ratio_all_d"], res["gradient_ms_skip_static_d"],
+           res["gradient_forward_ratio_skip_static_d"]))
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,6 +201,7 @@ def main(argv=None):
     ap.add_argument("--cpu-steps", type=int, default=400,
                     help="steps of the oracle CPU baseline (about 10-15 s on 16 cores)")
     ap.add_argument("--acc-steps", type=int, default=10000, help="steps of the 256^3 FP32-vs-FP64 row")
+    ap.add_argument("--grad-steps", type=int, default=2000, help="steps of the 16 x 128^3 gradient row")
     ap.add_argument("--kernel", choices=("auto", "table", "rank", "offset", "relative"), default="auto",
                     help="neighbour source of the explicit-step kernel")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -292,13 +344,21 @@ def main(argv=None):
         sima.adjoint(KA, dt, states, seeds, lam, grad)
         msr, _ = timed(lambda: sima.record(KA, dt, states))
         msa, _ = timed(lambda: sima.adjoint(KA, dt, states, seeds, lam, grad))
-        rows["a6_adjoint"] = {"segment_steps": KA, "forward_ms": msf, "record_ms": msr, "adjoint_ms": msa,
+        sima.set_adjoint_options(skip_static_d=True)
+        sima.adjoint(KA, dt, states, seeds, lam, grad)
+        msa_s, _ = timed(lambda: sima.adjoint(KA, dt, states, seeds, lam, grad))
+        rows["a6_adjoint"] = {"workload": "512^3, one %d-step checkpoint segment, CO2 seeds every step" % KA,
+                              "segment_steps": KA, "forward_ms": msf, "record_ms": msr, "adjoint_ms": msa,
                               "adjoint_forward_ratio": (msr + msa) / msf,
-                              "adjoint_only_ratio": msa / msf}
-        log("adjoint/forward ratio %.2f (record %.2f ms, adjoint %.2f ms, forward %.2f ms)"
-            % ((msr + msa) / msf, msr, msa, msf))
+                              "adjoint_only_ratio": msa / msf,
+                              "adjoint_ms_skip_static_d": msa_s,
+                              "adjoint_forward_ratio_skip_static_d": (msr + msa_s) / msf}
+        log("adjoint/forward ratio %.2f (record %.2f ms, adjoint %.2f ms, forward %.2f ms); "
+            "static-pool D gradients skipped: adjoint %.2f ms, ratio %.2f"
+            % ((msr + msa) / msf, msr, msa, msf, msa_s, (msr + msa_s) / msf))
+        rows["a6_gradient_16x128"] = gradient_batch(args.grad_steps)
         out["rows"] = rows
-        out["adjoint_forward_ratio"] = (msr + msa) / msf
+        out["adjoint_forward_ratio"] = rows["a6_gradient_16x128"]["gradient_forward_ratio_all_d"]
         del sima, states, lam
         torch.cuda.empty_cache()
         # FP32 fields + FP64 totals against the plain FP64 step on the 256^3

@@ -242,6 +242,14 @@ int vg_adjoint(vg_sim *h, int64_t nsteps, double dt, const void *states_d, const
  * [nseg][5] FP64 on the device). */
 int vg_seed_lambda(vg_sim *h, const double *seed_d, void *lambda_d, int zero, void *stream);
 
+/* Options of vg_adjoint.  VG_ADJ_SKIP_STATIC_D: dL/dD_s is not computed for
+ * the pools that do not diffuse in this handle (every pool but DOM unless
+ * mobile_all) and grad_d[s] is set to NaN for them; this saves the six
+ * neighbour gathers of each of their adjoints per voxel and step.  The other
+ * gradients and lambda are unchanged.  Default: every dL/dD_s computed. */
+#define VG_ADJ_SKIP_STATIC_D 1u
+int vg_set_adjoint_options(vg_sim *h, unsigned flags);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,10 +21,11 @@ VG_FORCE = 1
 VG_FEAT_CG, VG_FEAT_ADJ = 1, 2
 VG_NPOOL, VG_NREG, VG_NGRAD = 5, 8, 20
 VG_KERNEL_AUTO, VG_KERNEL_TABLE, VG_KERNEL_RANK, VG_KERNEL_OFFSET, VG_KERNEL_RELATIVE = 0, 1, 2, 3, 4
+VG_ADJ_SKIP_STATIC_D = 1
 
 EXPORTS = ("vg_strerror", "vg_last_error", "vg_version", "vg_rank_bytes", "vg_count_pores",
            "vg_build_graph", "vg_lookup", "vg_region_codes", "vg_create", "vg_destroy",
-           "vg_set_kernel", "vg_get_kernel", "vg_set_params", "vg_set_regions", "vg_alt_elems", "vg_workspace_bytes", "vg_init_state",
+           "vg_set_kernel", "vg_get_kernel", "vg_set_adjoint_options", "vg_set_params", "vg_set_regions", "vg_alt_elems", "vg_workspace_bytes", "vg_init_state",
            "vg_step_explicit", "vg_solve_implicit_step", "vg_mass_totals", "vg_record", "vg_adjoint",
            "vg_seed_lambda")
 
@@ -79,6 +80,7 @@ def load():
             "vg_destroy": (I, [P]),
             "vg_set_kernel": (I, [P, I]),
             "vg_get_kernel": (I, [P, ctypes.POINTER(I)]),
+            "vg_set_adjoint_options": (I, [P, ctypes.c_uint]),
             "vg_set_params": (I, [P, ctypes.POINTER(VgParams)]),
             "vg_set_regions": (I, [P, ctypes.POINTER(D)]),
             "vg_alt_elems": (I, [P, ctypes.POINTER(I64)]),

@@ -124,6 +124,7 @@ template <typename R>
 struct AdjBufs {
     const int32_t *nbr = nullptr;
     const uint16_t *rcode = nullptr;
+    PackedNbr pk;                // packed neighbour sources (when built)
     const R *st = nullptr;       // stored state of this step, pool s at st + s*n
     const R *lin = nullptr;      // lambda^(k+1)
     R *lout = nullptr;           // lambda^k
@@ -136,8 +137,41 @@ __device__ __forceinline__ constexpr bool mobile(int s) {
     return MOB == 2 || (MOB == 1 && s == 1);
 }
 
-template <typename R, int MOB, bool REG, bool FROM_X>
+// Neighbour sources of the adjoint kernel (the forward's): the 6-slot table
+// with 64-bit indexing, or a packed source with 32-bit indexing.
+enum { NS_TABLE = 0, NS_REL = 1, NS_OFF = 2 };
+
+template <int NS>
+struct AdjIndex {
+    using T = uint32_t;
+};
+template <>
+struct AdjIndex<NS_TABLE> {
+    using T = int64_t;
+};
+
+template <typename T>
+__device__ __forceinline__ const T &elem(const T *b, uint32_t i) {
+    return at(b, i);
+}
+template <typename T>
+__device__ __forceinline__ const T &elem(const T *b, int64_t i) {
+    return b[i];
+}
+template <typename T>
+__device__ __forceinline__ T &elem(T *b, uint32_t i) {
+    return at(b, i);
+}
+template <typename T>
+__device__ __forceinline__ T &elem(T *b, int64_t i) {
+    return b[i];
+}
+
+// DALL: dL/da_s also for the pools that do not diffuse (their adjoints'
+// neighbour differences are gathered only for that term).
+template <typename R, int MOB, bool REG, bool FROM_X, int NS, bool DALL>
 __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces pc, double *__restrict__ part) {
+    using I = typename AdjIndex<NS>::T;
     __shared__ double lds[kWaves * kG];
     __shared__ R cl[VG_NREG];
     if (threadIdx.x < VG_NREG) cl[threadIdx.x] = C.c[threadIdx.x];
@@ -146,18 +180,49 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces 
 #pragma unroll
     for (int q = 0; q < kG; q++) g[q] = 0.0;
     const int64_t n = A.n;
+    // pool s of a field set at base + s * n
+    const R *st[VG_NPOOL], *lin[VG_NPOOL];
+    R *lout[VG_NPOOL];
+#pragma unroll
+    for (int s = 0; s < VG_NPOOL; s++) {
+        st[s] = A.st + (int64_t)s * n;
+        lin[s] = A.lin + (int64_t)s * n;
+        lout[s] = A.lout + (int64_t)s * n;
+    }
 
     for (int64_t t = xcd_tile(blockIdx.x, gridDim.x); t < A.ntiles; t += gridDim.x)
     for (int v = 0; v < kVPT; v++) {
-        const int64_t i = t * kTile + v * kBlock + threadIdx.x;
-        if (i >= n) continue;
-        int32_t j[6];
+        const int64_t i64 = t * kTile + v * kBlock + threadIdx.x;
+        if (i64 >= n) continue;
+        const I i = (I)i64;
+        // neighbour indices (an absent neighbour is the voxel itself: every
+        // difference of an absent slot is exactly +0)
+        I j[6];
+        if constexpr (NS == NS_TABLE) {
 #pragma unroll
-        for (int k = 0; k < 6; k++) j[k] = A.nbr[(int64_t)k * n + i];
+            for (int k = 0; k < 6; k++) {
+                const int32_t jk = A.nbr[(int64_t)k * n + i];
+                j[k] = jk >= 0 ? (I)jk : i;
+            }
+        }
+        PackedWords W{0, 0};
+        if constexpr (NS != NS_TABLE) W = packed_words<NS == NS_REL>(A.pk, (uint32_t)i);
+        // forward state of this step and lambda^(k+1) of the voxel
+        R x[VG_NPOOL], li[VG_NPOOL];
+#pragma unroll
+        for (int s = 0; s < VG_NPOOL; s++) x[s] = elem(st[s], i);
+#pragma unroll
+        for (int s = 0; s < VG_NPOOL; s++) li[s] = elem(lin[s], i);
+        if constexpr (NS != NS_TABLE) {
+            uint32_t jp[6];
+            packed_decode<NS == NS_REL>(A.pk, (uint32_t)i, W, jp);
+#pragma unroll
+            for (int k = 0; k < 6; k++) j[k] = (I)jp[k];
+        }
         R w[6];
         uint32_t code = 0, own = 0;
         if (REG) {
-            code = A.rcode[i];
+            code = elem(A.rcode, i);
             own = code & 7u;
 #pragma unroll
             for (int k = 0; k < 6; k++) {
@@ -168,23 +233,17 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces 
 #pragma unroll
             for (int k = 0; k < 6; k++) w[k] = R(1);
         }
-        // forward state x^k of this step
-        R x[VG_NPOOL];
-#pragma unroll
-        for (int s = 0; s < VG_NPOOL; s++) x[s] = A.st[(int64_t)s * n + i];
+        // x^k = D(z) of the stored z, with the forward's arithmetic
         if (!FROM_X) {
 #pragma unroll
             for (int s = 0; s < VG_NPOOL; s++) {
                 if (!mobile<MOB>(s)) continue;
                 const R xi = x[s];
-                R v[6];
-#pragma unroll
-                for (int k = 0; k < 6; k++) v[k] = A.st[(int64_t)s * n + (j[k] >= 0 ? (int64_t)j[k] : i)];
                 R d[6];
 #pragma unroll
                 for (int k = 0; k < 6; k++) {
-                    const R diff = v[k] - xi;
-                    d[k] = j[k] >= 0 ? (REG ? w[k] * diff : diff) : R(0);
+                    const R diff = elem(st[s], j[k]) - xi;
+                    d[k] = REG ? w[k] * diff : diff;
                 }
                 x[s] = xi + C.a[s] * (((d[0] + d[1]) + (d[2] + d[3])) + (d[4] + d[5]));
             }
@@ -197,16 +256,18 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces 
         double own_c = 0.0, cross_c[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int s = 0; s < VG_NPOOL; s++) {
-            const R li = A.lin[(int64_t)s * n + i];
+            if (!DALL && !mobile<MOB>(s)) {
+                bar[s] = li[s];
+                continue;
+            }
             R lj[6];
 #pragma unroll
-            for (int k = 0; k < 6; k++) lj[k] = A.lin[(int64_t)s * n + (j[k] >= 0 ? (int64_t)j[k] : i)];
+            for (int k = 0; k < 6; k++) lj[k] = elem(lin[s], j[k]);
             R sum = R(0);
             double creg_own = 0.0, creg_x[3] = {0.0, 0.0, 0.0};
 #pragma unroll
             for (int k = 0; k < 6; k++) {
-                if (j[k] < 0) continue;
-                const R dl = lj[k] - li;
+                const R dl = lj[k] - li[s];
                 sum += w[k] * dl;
                 if (REG && mobile<MOB>(s)) {
                     const double tk = (double)dl;
@@ -218,7 +279,7 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces 
                     }
                 }
             }
-            bar[s] = mobile<MOB>(s) ? li + C.a[s] * sum : li;
+            bar[s] = mobile<MOB>(s) ? li[s] + C.a[s] * sum : li[s];
             g[s] += (double)u[s] * (double)sum;   // dL/da_s
             if (REG && mobile<MOB>(s)) {
                 const double f = (double)C.a[s] * (double)u[s];
@@ -243,10 +304,10 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces 
         transform_rev(C, x, bar, &g[5]);
         // seeds of this step's totals
         int32_t p = pc.piece_first[t];
-        while (p + 1 < pc.piece_first[t + 1] && i >= pc.piece_lo[p + 1]) p++;
+        while (p + 1 < pc.piece_first[t + 1] && i64 >= pc.piece_lo[p + 1]) p++;
         const double *sd = A.seed + (int64_t)pc.piece_seg[p] * VG_NPOOL;
 #pragma unroll
-        for (int s = 0; s < VG_NPOOL; s++) A.lout[(int64_t)s * n + i] = (R)((double)bar[s] + sd[s]);
+        for (int s = 0; s < VG_NPOOL; s++) elem(lout[s], i) = (R)((double)bar[s] + sd[s]);
     }
     block_sum<kG>(g, lds);
     if (threadIdx.x == 0) {
@@ -260,9 +321,11 @@ __global__ __launch_bounds__(kBlock) void k_fill(double *__restrict__ p, int64_t
     if (i < cnt) p[i] = v;
 }
 
-// grad[q] += sum over blocks (fixed order) of part[b][q]; dL/da_s -> dL/dD_s.
+// grad[q] += sum over blocks (fixed order) of part[b][q]; dL/da_s -> dL/dD_s;
+// grad[s] = NaN for the pools in `skipped` (bit s).
 __global__ __launch_bounds__(kBlock) void k_adj_finalize(const double *__restrict__ part, int nblocks,
-                                                         double scale_d, double *__restrict__ grad) {
+                                                         double scale_d, unsigned skipped,
+                                                         double *__restrict__ grad) {
     __shared__ double lds[kWaves * kG];
     double v[kG];
 #pragma unroll
@@ -274,7 +337,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_finalize(const double *__restric
     block_sum<kG>(v, lds);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int q = 0; q < kG; q++) grad[q] += q < VG_NPOOL ? v[q] * scale_d : v[q];
+        for (int q = 0; q < kG; q++) {
+            if (q < VG_NPOOL && ((skipped >> q) & 1u)) grad[q] = __builtin_nan("");
+            else grad[q] += q < VG_NPOOL ? v[q] * scale_d : v[q];
+        }
     }
 }
 
@@ -296,14 +362,30 @@ __global__ __launch_bounds__(kBlock) void k_seed(R *__restrict__ lam, const doub
     }
 }
 
+template <typename R, int MOB, bool REG, int NS, bool DALL>
+int launch_adj_d(vg_sim *h, bool from_x, const AdjBufs<R> &A, const Coef<R> &C, hipStream_t s) {
+    Pieces pc{h->piece_first, h->piece_lo, h->piece_seg, h->npieces};
+    if (from_x) hipLaunchKernelGGL((k_adj<R, MOB, REG, true, NS, DALL>), dim3(h->adj_blocks), dim3(kBlock), 0, s, A,
+                                   C, pc, h->adj_part);
+    else hipLaunchKernelGGL((k_adj<R, MOB, REG, false, NS, DALL>), dim3(h->adj_blocks), dim3(kBlock), 0, s, A, C,
+                            pc, h->adj_part);
+    return launch_status("k_adj");
+}
+
+template <typename R, int MOB, bool REG, int NS>
+int launch_adj_ns(vg_sim *h, bool from_x, const AdjBufs<R> &A, const Coef<R> &C, hipStream_t s) {
+    // with every pool diffusing there is nothing to skip
+    if (MOB == 1 && (h->adj_flags & VG_ADJ_SKIP_STATIC_D))
+        return launch_adj_d<R, MOB, REG, NS, false>(h, from_x, A, C, s);
+    return launch_adj_d<R, MOB, REG, NS, true>(h, from_x, A, C, s);
+}
+
+// the explicit step's neighbour source
 template <typename R, int MOB, bool REG>
 int launch_adj_step(vg_sim *h, bool from_x, const AdjBufs<R> &A, const Coef<R> &C, hipStream_t s) {
-    Pieces pc{h->piece_first, h->piece_lo, h->piece_seg, h->npieces};
-    if (from_x) hipLaunchKernelGGL((k_adj<R, MOB, REG, true>), dim3(h->adj_blocks), dim3(kBlock), 0, s, A, C, pc,
-                                   h->adj_part);
-    else hipLaunchKernelGGL((k_adj<R, MOB, REG, false>), dim3(h->adj_blocks), dim3(kBlock), 0, s, A, C, pc,
-                            h->adj_part);
-    return launch_status("k_adj");
+    if (use_relative(h)) return launch_adj_ns<R, MOB, REG, NS_REL>(h, from_x, A, C, s);
+    if (use_offsets(h)) return launch_adj_ns<R, MOB, REG, NS_OFF>(h, from_x, A, C, s);
+    return launch_adj_ns<R, MOB, REG, NS_TABLE>(h, from_x, A, C, s);
 }
 
 template <typename R>
@@ -323,6 +405,7 @@ int adjoint_sweep(vg_sim *h, int64_t nsteps, double dt, const void *states, cons
         AdjBufs<R> A;
         A.nbr = h->nbr;
         A.rcode = h->rcode;
+        A.pk = packed_of(h);
         A.st = (const R *)states + jstep * VG_NPOOL * n;
         A.lin = bufs[cur];
         A.lout = bufs[cur ^ 1];
@@ -340,7 +423,10 @@ int adjoint_sweep(vg_sim *h, int64_t nsteps, double dt, const void *states, cons
                                             hipMemcpyDeviceToDevice, s), "lambda copy"))) return rc;
     }
     const double scale_d = dt / (h->params.h * h->params.h);
-    hipLaunchKernelGGL(k_adj_finalize, dim3(1), dim3(kBlock), 0, s, h->adj_part, h->adj_blocks, scale_d, grad);
+    // pools whose dL/dD_s the sweep skipped: all but DOM, when asked and not every pool diffuses
+    const unsigned skipped = (!h->mobile_all && (h->adj_flags & VG_ADJ_SKIP_STATIC_D)) ? 0x1du : 0u;
+    hipLaunchKernelGGL(k_adj_finalize, dim3(1), dim3(kBlock), 0, s, h->adj_part, h->adj_blocks, scale_d, skipped,
+                       grad);
     return launch_status("k_adj_finalize");
 }
 

@@ -244,6 +244,13 @@ extern "C" int vg_set_kernel(vg_sim *h, int variant) {
     return VG_OK;
 }
 
+extern "C" int vg_set_adjoint_options(vg_sim *h, unsigned flags) {
+    if (!h) { set_error("handle is NULL"); return VG_EINVAL; }
+    if (flags & ~VG_ADJ_SKIP_STATIC_D) { set_error("unknown adjoint options"); return VG_EINVAL; }
+    h->adj_flags = flags;
+    return VG_OK;
+}
+
 extern "C" int vg_get_kernel(const vg_sim *h, int *variant_in_use) {
     if (!h || !variant_in_use) { set_error("null pointer argument"); return VG_EINVAL; }
     *variant_in_use = vg::use_relative(h) ? VG_KERNEL_RELATIVE

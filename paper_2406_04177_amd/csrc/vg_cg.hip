@@ -1,7 +1,8 @@
 // Implicit diffusion (Sec. II.B.3b, Scheme 2): per diffusing pool, solve
 // (I + a L_w) y = x with the conjugate gradient method preconditioned by the
 // inverse diagonal of the system matrix (Sec. III).  Matrix-free: the
-// Laplacian is applied as a gather over the neighbour table.  Vectors,
+// Laplacian is applied as a gather over the neighbours (the explicit step's
+// neighbour source: table or packed).  Vectors,
 // dot products and scalars are FP64 whatever the field type.
 //
 // Per iteration two streaming kernels (p/q update with the SpMV and p.q
@@ -28,13 +29,39 @@ __device__ __forceinline__ double weight(const uint16_t *rcode, const double *cl
 struct CgArgs {
     const int32_t *nbr = nullptr;
     const uint16_t *rcode = nullptr;
+    PackedNbr pk;                // packed neighbour sources (when built)
     int64_t n = 0;
     int64_t ntiles = 0;
     double a = 0;
     double c[VG_NREG] = {};
 };
 
-template <typename R, bool REG>
+// Neighbour sources of the CG kernels (the explicit step's): the table, or
+// a packed source; an absent neighbour comes back as the voxel itself.
+enum { NS_TABLE = 0, NS_REL = 1, NS_OFF = 2 };
+
+template <int NS>
+__device__ __forceinline__ void cg_neighbours(const CgArgs &A, int64_t i, int64_t (&j)[6], bool (&pres)[6]) {
+    if constexpr (NS == NS_TABLE) {
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            const int32_t jk = A.nbr[(int64_t)k * A.n + i];
+            pres[k] = jk >= 0;
+            j[k] = pres[k] ? (int64_t)jk : i;
+        }
+    } else {
+        uint32_t jp[6];
+        const PackedWords W = packed_words<NS == NS_REL>(A.pk, (uint32_t)i);
+        packed_decode<NS == NS_REL>(A.pk, (uint32_t)i, W, jp);
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            j[k] = (int64_t)jp[k];
+            pres[k] = j[k] != i;      // no periodic wrap: a neighbour is never the voxel itself
+        }
+    }
+}
+
+template <typename R, bool REG, int NS>
 __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs A, const R *__restrict__ field,
                                                     double *__restrict__ y, double *__restrict__ r,
                                                     double *__restrict__ z, double *__restrict__ p,
@@ -49,16 +76,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs A, const R *__restric
         const int64_t i = t * kTile + v * kBlock + threadIdx.x;
         if (i >= A.n) continue;
         const double b = (double)field[i];
-        int32_t j[6];
+        int64_t j[6];
+        bool pres[6];
+        cg_neighbours<NS>(A, i, j, pres);
         double fj[6];
 #pragma unroll
-        for (int k = 0; k < 6; k++) j[k] = A.nbr[(int64_t)k * A.n + i];
-#pragma unroll
-        for (int k = 0; k < 6; k++) fj[k] = (double)field[j[k] >= 0 ? (int64_t)j[k] : i];
+        for (int k = 0; k < 6; k++) fj[k] = (double)field[j[k]];
         double s = 0.0, deg = 0.0;
 #pragma unroll
         for (int k = 0; k < 6; k++) {
-            if (j[k] < 0) continue;
+            if (!pres[k]) continue;
             const double w = weight(A.rcode, cl, i, k, REG);
             deg += w;
             s += w * (b - fj[k]);
@@ -82,7 +109,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs A, const R *__restric
 }
 
 // q = B p' with p' = z + beta p (the new search direction, also written out)
-template <bool REG>
+template <bool REG, int NS>
 __global__ __launch_bounds__(kBlock) void k_cg_spmv(CgArgs A, const double *__restrict__ z,
                                                     const double *__restrict__ pold, double *__restrict__ pnew,
                                                     double *__restrict__ q, const double *__restrict__ scal,
@@ -99,20 +126,19 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(CgArgs A, const double *__re
         const int64_t i = t * kTile + v * kBlock + threadIdx.x;
         if (i >= A.n) continue;
         const double pi = z[i] + beta * pold[i];
-        int32_t j[6];
+        int64_t j[6];
+        bool pres[6];
+        cg_neighbours<NS>(A, i, j, pres);
         double zj[6], pj[6];
 #pragma unroll
-        for (int k = 0; k < 6; k++) j[k] = A.nbr[(int64_t)k * A.n + i];
-#pragma unroll
         for (int k = 0; k < 6; k++) {
-            const int64_t jj = j[k] >= 0 ? (int64_t)j[k] : i;
-            zj[k] = z[jj];
-            pj[k] = pold[jj];
+            zj[k] = z[j[k]];
+            pj[k] = pold[j[k]];
         }
         double s = 0.0;
 #pragma unroll
         for (int k = 0; k < 6; k++) {
-            if (j[k] < 0) continue;
+            if (!pres[k]) continue;
             s += weight(A.rcode, cl, i, k, REG) * (pi - (zj[k] + beta * pj[k]));
         }
         const double qi = pi + A.a * s;
@@ -190,12 +216,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_writeback(int64_t n, const double
     if (i < n) field[i] = (R)y[i];
 }
 
-template <typename R>
-int cg_solve(vg_sim *h, int pool, double a, double rtol, int max_iter, int *iters, double *relres,
-             hipStream_t s) {
+template <typename R, int NS>
+int cg_solve_ns(vg_sim *h, int pool, double a, double rtol, int max_iter, int *iters, double *relres,
+                hipStream_t s) {
     CgArgs A;
     A.nbr = h->nbr;
     A.rcode = h->rcode;
+    A.pk = packed_of(h);
     A.n = h->n;
     A.ntiles = h->ntiles;
     A.a = a;
@@ -208,9 +235,9 @@ int cg_solve(vg_sim *h, int pool, double a, double rtol, int max_iter, int *iter
     double host_scal[S_NSCAL] = {0, 0, 0, 0, 0, 0, 0, rtol * rtol};
     if ((rc = hip_status(hipMemcpyAsync(h->cg_scal, host_scal, sizeof(host_scal), hipMemcpyHostToDevice, s),
                          "cg scalars"))) return rc;
-    if (reg) hipLaunchKernelGGL((k_cg_init<R, true>), dim3(G), dim3(kBlock), 0, s, A, field, h->cg_y, h->cg_r,
+    if (reg) hipLaunchKernelGGL((k_cg_init<R, true, NS>), dim3(G), dim3(kBlock), 0, s, A, field, h->cg_y, h->cg_r,
                                 h->cg_z, h->cg_p[0], h->cg_m, h->cg_part);
-    else hipLaunchKernelGGL((k_cg_init<R, false>), dim3(G), dim3(kBlock), 0, s, A, field, h->cg_y, h->cg_r,
+    else hipLaunchKernelGGL((k_cg_init<R, false, NS>), dim3(G), dim3(kBlock), 0, s, A, field, h->cg_y, h->cg_r,
                             h->cg_z, h->cg_p[0], h->cg_m, h->cg_part);
     if ((rc = launch_status("k_cg_init"))) return rc;
     hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kBlock), 0, s, h->cg_part, G, 0, h->cg_scal);
@@ -226,9 +253,9 @@ int cg_solve(vg_sim *h, int pool, double a, double rtol, int max_iter, int *iter
         if (back[S_DONE] != 0.0 || launched >= max_iter) break;
         const int todo = (max_iter - launched) < chunk ? (max_iter - launched) : chunk;
         for (int it = 0; it < todo; it++) {
-            if (reg) hipLaunchKernelGGL((k_cg_spmv<true>), dim3(G), dim3(kBlock), 0, s, A, h->cg_z, h->cg_p[cur],
+            if (reg) hipLaunchKernelGGL((k_cg_spmv<true, NS>), dim3(G), dim3(kBlock), 0, s, A, h->cg_z, h->cg_p[cur],
                                         h->cg_p[cur ^ 1], h->cg_q, h->cg_scal, h->cg_part);
-            else hipLaunchKernelGGL((k_cg_spmv<false>), dim3(G), dim3(kBlock), 0, s, A, h->cg_z, h->cg_p[cur],
+            else hipLaunchKernelGGL((k_cg_spmv<false, NS>), dim3(G), dim3(kBlock), 0, s, A, h->cg_z, h->cg_p[cur],
                                     h->cg_p[cur ^ 1], h->cg_q, h->cg_scal, h->cg_part);
             if ((rc = launch_status("k_cg_spmv"))) return rc;
             hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kBlock), 0, s, h->cg_part, G, 1, h->cg_scal);
@@ -248,6 +275,15 @@ int cg_solve(vg_sim *h, int pool, double a, double rtol, int max_iter, int *iter
     if (iters) *iters = (int)back[S_ITER];
     if (relres) *relres = back[S_BB] > 0.0 ? __builtin_sqrt(back[S_RR] / back[S_BB]) : 0.0;
     return back[S_DONE] != 0.0 ? VG_OK : VG_ENOCONV;
+}
+
+// the explicit step's neighbour source
+template <typename R>
+int cg_solve(vg_sim *h, int pool, double a, double rtol, int max_iter, int *iters, double *relres,
+             hipStream_t s) {
+    if (use_relative(h)) return cg_solve_ns<R, NS_REL>(h, pool, a, rtol, max_iter, iters, relres, s);
+    if (use_offsets(h)) return cg_solve_ns<R, NS_OFF>(h, pool, a, rtol, max_iter, iters, relres, s);
+    return cg_solve_ns<R, NS_TABLE>(h, pool, a, rtol, max_iter, iters, relres, s);
 }
 
 }  // namespace

@@ -71,20 +71,34 @@ struct RankWord {
 };
 
 // ---------------------------------------------------------------- mapping
-// Block index -> tile index.  With VG_XCD_MAP each XCD (blocks are dealt
-// round-robin to the 8 XCDs) works on one contiguous range of tiles, so the
-// neighbour gathers of a tile hit the L2 that already holds its neighbours.
-// Measured on the streaming passes it is slower (5-6 %) than the identity:
-// the shared last-level cache already serves the gathers, and eight streams
-// far apart in memory use HBM less well than one sweep in address order.
+// Block index -> tile index (blocks are dealt round-robin to the 8 XCDs,
+// each with its own L2).  VG_XCD_MAP 0: identity, all XCDs sweep the voxels
+// together in address order.  1: each XCD works on one contiguous eighth.
+// 2 (default): runs of VG_XCD_RUN consecutive tiles go to the XCDs in turn
+// and each XCD works through its run in order, so the +-x / +-y neighbours
+// of a tile mostly sit in its own L2 while the whole chip still sweeps
+// memory in one front; the remainder is split as with 1.  Measured on the
+// 512^3 step: 2 with runs of 64 tiles ~1 % faster than 0, 1 ~5 % slower.
 #ifndef VG_XCD_MAP
-#define VG_XCD_MAP 0
+#define VG_XCD_MAP 2
 #endif
-__device__ inline int64_t xcd_tile(int64_t b, int64_t nb) {
-#if VG_XCD_MAP
+#ifndef VG_XCD_RUN
+#define VG_XCD_RUN 64
+#endif
+__device__ inline int64_t xcd_split(int64_t b, int64_t nb) {
     const int64_t q = nb / kNumXcd, r = nb % kNumXcd;
     const int64_t x = b % kNumXcd, k = b / kNumXcd;
     return x * q + (x < r ? x : r) + k;
+}
+__device__ inline int64_t xcd_tile(int64_t b, int64_t nb) {
+#if VG_XCD_MAP == 1
+    return xcd_split(b, nb);
+#elif VG_XCD_MAP == 2
+    constexpr int64_t S = VG_XCD_RUN, R = S * kNumXcd;
+    const int64_t full = nb / R * R;
+    if (b >= full) return full + xcd_split(b - full, nb - full);
+    const int64_t x = b % kNumXcd, k = b / kNumXcd;
+    return ((k / S) * kNumXcd + x) * S + k % S;
 #else
     (void)nb;
     return b;
@@ -249,6 +263,80 @@ __device__ __forceinline__ void unpack_offsets(const DLayout &L, uint32_t w, uin
     d[2] = w & L.mz;
 }
 
+// Element idx of an array whose base is uniform across the wave: a 32-bit
+// byte offset from the base, so that the whole address arithmetic of a voxel
+// is one shift (valid while n * sizeof(T) < 2^32, which the host checks
+// before it enables a packed neighbour source).
+template <typename T>
+__device__ __forceinline__ const T &at(const T *base, uint32_t idx) {
+    return *(const T *)((const char *)base + (idx * (uint32_t)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ T &at(T *base, uint32_t idx) {
+    return *(T *)((char *)base + (idx * (uint32_t)sizeof(T)));
+}
+
+// The two packed neighbour sources as the kernels see them.
+struct PackedNbr {
+    const uint32_t *rel_w = nullptr;     // [n] relative codes
+    const uint32_t *rel_base = nullptr;  // [groups][8] base distances
+    RLayout rl;
+    const uint32_t *off_m = nullptr;     // [n] packed offsets, minus side
+    const uint32_t *off_p = nullptr;     // [n] packed offsets, plus side
+    DLayout dl;
+};
+
+// Compact indices of the six neighbours of voxel i from a packed source
+// (RELC: relative codes, else packed offsets), in two steps so that the
+// caller can issue its other loads between them: packed_words loads the
+// voxel's words, packed_decode turns them into indices.  An absent neighbour
+// gives i itself, so that every difference x_j - x_i of an absent slot is
+// exactly +0 for finite values and the slot needs no select.  With relative
+// codes all active lanes of the wave must hold voxels of the same group.
+struct PackedWords {
+    uint32_t a, b;
+};
+
+template <bool RELC>
+__device__ __forceinline__ PackedWords packed_words(const PackedNbr &P, uint32_t i) {
+    PackedWords W;
+    if (RELC) {
+        W.a = at(P.rel_w, i);
+        W.b = 0;
+    } else {
+        W.a = at(P.off_m, i);
+        W.b = at(P.off_p, i);
+    }
+    return W;
+}
+
+template <bool RELC>
+__device__ __forceinline__ void packed_decode(const PackedNbr &P, uint32_t i, PackedWords W, uint32_t (&j)[6]) {
+    if (RELC) {
+        // the six base distances of the group: one uniform 32-byte load
+        const uint32_t grp = __builtin_amdgcn_readfirstlane(i / (uint32_t)kGroup);
+        const uint32_t *bp = P.rel_base + (size_t)grp * 8;
+        uint32_t base[6];
+#pragma unroll
+        for (int k = 0; k < 6; k++) base[k] = bp[k];
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            const uint32_t c = (W.a >> P.rl.sh[k]) & P.rl.mk[k];
+            const uint32_t d = c ? base[k] + (c - 1u) : 0u;
+            j[k] = (k & 1) ? i + d : i - d;
+        }
+    } else {
+        uint32_t dm[3], dp[3];
+        unpack_offsets(P.dl, W.a, dm);
+        unpack_offsets(P.dl, W.b, dp);
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            j[2 * a] = i - dm[a];
+            j[2 * a + 1] = i + dp[a];
+        }
+    }
+}
+
 }  // namespace vg
 
 // ---------------------------------------------------------------- handle
@@ -309,6 +397,7 @@ struct vg_sim {
     double *cg_scal = nullptr;   // scalars (see vg_cg.hip)
     int cg_blocks = 0;
     // adjoint
+    unsigned adj_flags = 0;      // VG_ADJ_* options
     char *lam_alt = nullptr;     // [5][n] field type
     double *adj_part = nullptr;  // [adj_blocks][VG_NGRAD]
     int adj_blocks = 0;
@@ -330,6 +419,7 @@ int launch_geometry(vg_sim *h, hipStream_t s);
 bool use_rank(const vg_sim *h);
 bool use_offsets(const vg_sim *h);
 bool use_relative(const vg_sim *h);
+PackedNbr packed_of(const vg_sim *h);
 int build_offsets(vg_sim *h, hipStream_t s);
 int restore_canonical(vg_sim *h, hipStream_t s);
 // vg_cg.hip

@@ -78,12 +78,7 @@ template <typename R>
 struct StepBufs {
     const int32_t *nbr = nullptr;       // [6][n]
     const uint16_t *rcode = nullptr;    // [n] or null
-    const uint32_t *off_m = nullptr;    // [n] packed offsets (minus side) or null
-    const uint32_t *off_p = nullptr;    // [n] packed offsets (plus side) or null
-    DLayout dl;
-    const uint32_t *rel_w = nullptr;    // [n] relative neighbour codes or null
-    const uint32_t *rel_base = nullptr; // [groups][8] base distances or null
-    RLayout rl;
+    PackedNbr pk;                       // packed neighbour sources (when built)
     const R *src[VG_NPOOL] = {};
     R *dst[VG_NPOOL] = {};
     int64_t n = 0;
@@ -96,12 +91,7 @@ StepBufs<R> graph_bufs(const vg_sim *h) {
     StepBufs<R> B;
     B.nbr = h->nbr;
     B.rcode = h->rcode;
-    B.off_m = h->off_m;
-    B.off_p = h->off_p;
-    B.dl = h->off_layout;
-    B.rel_w = h->rel_w;
-    B.rel_base = h->rel_base;
-    B.rl = h->rel_layout;
+    B.pk = packed_of(h);
     B.n = h->n;
     return B;
 }
@@ -316,18 +306,6 @@ __global__ __launch_bounds__(kBlock) void k_step(StepBufs<R> B, Coef<R> C, Piece
     if (TOT != TOT_NONE) tile_totals(pc, tile, acc, part, lds);
 }
 
-// Element idx of an array whose base is uniform across the wave: a 32-bit
-// byte offset from the base, so that the whole address arithmetic of a voxel
-// is one shift (valid while n * sizeof(T) < 2^32, checked on the host).
-template <typename T>
-__device__ __forceinline__ const T &at(const T *base, uint32_t idx) {
-    return *(const T *)((const char *)base + (idx * (uint32_t)sizeof(T)));
-}
-template <typename T>
-__device__ __forceinline__ T &at(T *base, uint32_t idx) {
-    return *(T *)((char *)base + (idx * (uint32_t)sizeof(T)));
-}
-
 // Packed-offset variant of the diffusing passes (D and DT).  Neighbour j of
 // voxel i is i - d or i + d with d unpacked from the voxel's two offset words;
 // an absent neighbour has d = 0 and so reads the voxel itself, whose
@@ -352,17 +330,10 @@ __global__ __launch_bounds__(kBlock) void k_step_off(StepBufs<R> B, Coef<R> C, P
         act[v] = i < n;
         ic[v] = act[v] ? i : n - 1;
     }
-    uint32_t wm[kVPT], wp[kVPT];
+    // the neighbour words first (the gathers depend on them), then the pools
+    PackedWords pw[kVPT];
 #pragma unroll
-    for (int v = 0; v < kVPT; v++) {
-        if (RELC) {
-            wm[v] = ld_once(&at(B.rel_w, ic[v]));
-            wp[v] = 0;
-        } else {
-            wm[v] = ld_once(&at(B.off_m, ic[v]));
-            wp[v] = ld_once(&at(B.off_p, ic[v]));
-        }
-    }
+    for (int v = 0; v < kVPT; v++) pw[v] = packed_words<RELC>(B.pk, ic[v]);
     R x[kVPT][VG_NPOOL];
 #pragma unroll
     for (int v = 0; v < kVPT; v++)
@@ -371,30 +342,11 @@ __global__ __launch_bounds__(kBlock) void k_step_off(StepBufs<R> B, Coef<R> C, P
             x[v][s] = reads<MODE, MOB, TOT>(s) ? (mobile<MOB>(s) ? at(B.src[s], ic[v]) : ld_once(&at(B.src[s], ic[v])))
                                                : R(0);
     uint32_t j[kVPT][6];
+#pragma unroll
+    for (int v = 0; v < kVPT; v++) packed_decode<RELC>(B.pk, ic[v], pw[v], j[v]);   // lanes past n hold n - 1
     R w[kVPT][6];
 #pragma unroll
     for (int v = 0; v < kVPT; v++) {
-        if (RELC) {
-            // the 64 voxels of a wave form one group (lanes past n hold n - 1,
-            // which lies in the same group), so the group index is uniform
-            const uint32_t grp = __builtin_amdgcn_readfirstlane(ic[v] / (uint32_t)kGroup);
-            const uint32_t *bp = B.rel_base + (size_t)grp * 8;
-#pragma unroll
-            for (int k = 0; k < 6; k++) {
-                const uint32_t c = (wm[v] >> B.rl.sh[k]) & B.rl.mk[k];
-                const uint32_t d = c ? bp[k] + (c - 1u) : 0u;
-                j[v][k] = (k & 1) ? ic[v] + d : ic[v] - d;
-            }
-        } else {
-            uint32_t dm[3], dp[3];
-            unpack_offsets(B.dl, wm[v], dm);
-            unpack_offsets(B.dl, wp[v], dp);
-#pragma unroll
-            for (int a = 0; a < 3; a++) {
-                j[v][2 * a] = ic[v] - dm[a];
-                j[v][2 * a + 1] = ic[v] + dp[a];
-            }
-        }
         if (REG) {
             const uint32_t code = at(B.rcode, ic[v]);
             const uint32_t own = code & 7u;
@@ -606,37 +558,6 @@ __global__ __launch_bounds__(kBlock) void k_geometry(const int32_t *__restrict__
     geo[i] = c;
 }
 
-// Packed offsets, pass 1: the largest distance per axis, and a flag when a
-// minus-side neighbour does not precede the voxel (or a plus-side one does
-// not follow it), as happens across a periodic wrap.
-__global__ __launch_bounds__(kBlock) void k_offset_stat(const int32_t *__restrict__ nbr, int64_t n,
-                                                        uint32_t *__restrict__ stat) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    uint32_t mx[3] = {0, 0, 0}, bad = 0;
-    if (i < n) {
-#pragma unroll
-        for (int k = 0; k < 6; k++) {
-            const int32_t j = nbr[(int64_t)k * n + i];
-            if (j < 0) continue;
-            const int64_t d = (k & 1) ? (int64_t)j - i : i - (int64_t)j;
-            if (d <= 0) bad = 1;
-            else mx[k >> 1] = max(mx[k >> 1], (uint32_t)d);
-        }
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-#pragma unroll
-        for (int a = 0; a < 3; a++) mx[a] = max(mx[a], (uint32_t)__shfl_xor((int)mx[a], o, 64));
-        bad |= (uint32_t)__shfl_xor((int)bad, o, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-        for (int a = 0; a < 3; a++)
-            if (mx[a]) atomicMax(&stat[a], mx[a]);
-        if (bad) atomicOr(&stat[3], 1u);
-    }
-}
-
 // Packed offsets, pass 2: the two words of every voxel.
 __global__ __launch_bounds__(kBlock) void k_offsets(const int32_t *__restrict__ nbr, int64_t n, DLayout L,
                                                     uint32_t *__restrict__ off_m, uint32_t *__restrict__ off_p) {
@@ -656,33 +577,51 @@ __global__ __launch_bounds__(kBlock) void k_offsets(const int32_t *__restrict__ 
     off_p[i] = wp;
 }
 
-// Relative codes, pass 1: per group of 64 voxels (one wave) and slot, the
-// smallest distance (the base) and the spread + 1 of the distances; the
-// largest spread + 1 per axis goes to stat[4 + axis].  Assumes the slot
-// directions that k_offset_stat verifies.
-__global__ __launch_bounds__(kBlock) void k_rel_stat(const int32_t *__restrict__ nbr, int64_t n,
-                                                     uint32_t *__restrict__ base, uint32_t *__restrict__ stat) {
+// Neighbour distances, one pass over the table (both packings): per group of
+// 64 voxels (one wave) and slot the smallest distance, base[g][k]; over the
+// graph the largest distance per axis (stat[0..2]), a flag when a minus-side
+// neighbour does not precede the voxel or a plus-side one does not follow it
+// (stat[3], as across a periodic wrap) and the largest spread + 1 of a slot's
+// distances within a group, per axis (stat[4..6]).  A bounded grid strides
+// over the voxels and each block adds its maxima with one atomic per value.
+__global__ __launch_bounds__(kBlock) void k_neighbour_stat(const int32_t *__restrict__ nbr, int64_t n,
+                                                           uint32_t *__restrict__ base, uint32_t *__restrict__ stat) {
     static_assert(kGroup == 64, "a group is one wave");
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    uint32_t span[3] = {0, 0, 0};
+    __shared__ uint32_t red[kWaves][7];
+    uint32_t acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int64_t i0 = (int64_t)blockIdx.x * kBlock; i0 < n; i0 += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = i0 + threadIdx.x;
 #pragma unroll
-    for (int k = 0; k < 6; k++) {
-        const int32_t j = i < n ? nbr[(int64_t)k * n + i] : -1;
-        const bool pres = j >= 0;
-        const uint32_t d = pres ? (uint32_t)((k & 1) ? (int64_t)j - i : i - (int64_t)j) : 0u;
-        uint32_t lo = pres ? d : 0xffffffffu, hi = pres ? d : 0u;
+        for (int k = 0; k < 6; k++) {
+            const int32_t j = i < n ? nbr[(int64_t)k * n + i] : -1;
+            const int64_t d64 = (k & 1) ? (int64_t)j - i : i - (int64_t)j;
+            if (j >= 0 && d64 <= 0) acc[3] = 1;
+            const bool pres = j >= 0 && d64 > 0;
+            const uint32_t d = pres ? (uint32_t)d64 : 0u;
+            acc[k >> 1] = max(acc[k >> 1], d);
+            uint32_t lo = pres ? d : 0xffffffffu, hi = d;
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, 64));
-            hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, 64));
+            for (int o = 32; o > 0; o >>= 1) {
+                lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, 64));
+                hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, 64));
+            }
+            if ((threadIdx.x & 63) == 0 && i < n) base[(i / kGroup) * 8 + k] = lo == 0xffffffffu ? 0u : lo;
+            if (lo != 0xffffffffu) acc[4 + (k >> 1)] = max(acc[4 + (k >> 1)], hi - lo + 1u);
         }
-        if ((threadIdx.x & 63) == 0 && i < n) base[(i / kGroup) * 8 + k] = lo == 0xffffffffu ? 0u : lo;
-        if (lo != 0xffffffffu) span[k >> 1] = max(span[k >> 1], hi - lo + 1u);
     }
+#pragma unroll
+    for (int q = 0; q < 7; q++)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc[q] = max(acc[q], (uint32_t)__shfl_xor((int)acc[q], o, 64));
     if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-        for (int a = 0; a < 3; a++)
-            if (span[a]) atomicMax(&stat[4 + a], span[a]);
+        for (int q = 0; q < 7; q++) red[threadIdx.x >> 6][q] = acc[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < 7) {
+        uint32_t v = red[0][threadIdx.x];
+        for (int w = 1; w < kWaves; w++) v = max(v, red[w][threadIdx.x]);
+        if (v) atomicMax(&stat[threadIdx.x], v);
     }
 }
 
@@ -842,6 +781,17 @@ int dispatch(vg_sim *h, int mode, int tot, double dt, hipStream_t s) {
 
 // Neighbour source: an explicit choice, else packed offsets when they fit,
 // else the rank index when there is one, else the table.
+PackedNbr packed_of(const vg_sim *h) {
+    PackedNbr P;
+    P.rel_w = h->rel_w;
+    P.rel_base = h->rel_base;
+    P.rl = h->rel_layout;
+    P.off_m = h->off_m;
+    P.off_p = h->off_p;
+    P.dl = h->off_layout;
+    return P;
+}
+
 bool use_relative(const vg_sim *h) {
     return h->rel_ok && (h->kernel == VG_KERNEL_AUTO || h->kernel == VG_KERNEL_RELATIVE);
 }
@@ -873,10 +823,10 @@ int build_offsets(vg_sim *h, hipStream_t s) {
     if ((rc = hip_status(hipMemsetAsync(h->off_stat, 0, 8 * sizeof(uint32_t), s), "clear offset statistics")))
         return rc;
     const unsigned blocks = (unsigned)((h->n + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_offset_stat, dim3(blocks), dim3(kBlock), 0, s, h->nbr, h->n, h->off_stat);
-    if ((rc = launch_status("k_offset_stat"))) return rc;
-    hipLaunchKernelGGL(k_rel_stat, dim3(blocks), dim3(kBlock), 0, s, h->nbr, h->n, h->rel_base, h->off_stat);
-    if ((rc = launch_status("k_rel_stat"))) return rc;
+    const unsigned stat_blocks = blocks < 2048u ? blocks : 2048u;
+    hipLaunchKernelGGL(k_neighbour_stat, dim3(stat_blocks), dim3(kBlock), 0, s, h->nbr, h->n, h->rel_base,
+                       h->off_stat);
+    if ((rc = launch_status("k_neighbour_stat"))) return rc;
     uint32_t st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if ((rc = hip_status(hipMemcpyAsync(st, h->off_stat, sizeof(st), hipMemcpyDeviceToHost, s), "read offsets")))
         return rc;

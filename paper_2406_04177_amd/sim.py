@@ -161,6 +161,12 @@ class Simulation:
         _lib.check(self.L.vg_adjoint(self.h, int(nsteps), float(dt), states.data_ptr(), seeds.data_ptr(),
                                      lam.data_ptr(), grad.data_ptr(), self._sp()), "vg_adjoint")
 
+    def set_adjoint_options(self, skip_static_d: bool = False):
+        """skip_static_d: do not compute dL/dD_s for the pools that do not
+        diffuse (their gradient entries come back NaN); faster reverse sweep."""
+        _lib.check(self.L.vg_set_adjoint_options(self.h, _lib.VG_ADJ_SKIP_STATIC_D if skip_static_d else 0),
+                   "vg_set_adjoint_options")
+
     def seed_lambda(self, seed: torch.Tensor, lam: torch.Tensor, zero: bool):
         _lib.check(self.L.vg_seed_lambda(self.h, seed.data_ptr(), lam.data_ptr(), 1 if zero else 0, self._sp()),
                    "vg_seed_lambda")

@@ -22,12 +22,13 @@ def rates():
     return inputs.ModelParams(v_dom=2e-3, k_dom=0.5, rho=3e-4, mu=2e-4, beta=0.55, v_som=1e-4, v_p4=2e-4)
 
 
-def gpu_grad(masks, specs, p, c, dt, nsteps, K, precision, seeds_np):
+def gpu_grad(masks, specs, p, c, dt, nsteps, K, precision, seeds_np, kernel=0):
     from paper_2406_04177_amd.autograd import simulate_totals, theta_of
     from paper_2406_04177_amd.graph import Graph
     from paper_2406_04177_amd.sim import Simulation
     g = Graph.from_masks(masks, regions=True)
     sim = Simulation(g, p, precision=precision, implicit=False, adjoint=True, regions=c)
+    sim.set_kernel(kernel)
     dtype = torch.float64 if precision == "f64" else torch.float32
     x0 = g.fields_from_specs(specs, dtype).requires_grad_(True)
     theta = theta_of(p, c).requires_grad_(True)
@@ -87,8 +88,9 @@ def compare(g_gpu, g_or, rel, absolute):
     assert not bad, bad
 
 
+@pytest.mark.parametrize("kernel", [1, 3, 4], ids=["table", "offset", "relative"])
 @pytest.mark.parametrize("K", [1, 4, 100])
-def test_fp64_gradient_equals_oracle(K):
+def test_fp64_gradient_equals_oracle(K, kernel):
     """Same gradient to 1e-9 relative, or within the oracle's own rounding
     scale (64 eps times the sum of |terms|) for the cancelling D and c sums."""
     masks, specs = batch()
@@ -98,7 +100,7 @@ def test_fp64_gradient_equals_oracle(K):
     nsteps = 25
     rng = np.random.default_rng(0)
     seeds = rng.standard_normal((nsteps + 1, len(masks), 5))
-    g_gpu, lam_gpu, tot_gpu = gpu_grad(masks, specs, p, c, dt, nsteps, K, "f64", seeds)
+    g_gpu, lam_gpu, tot_gpu = gpu_grad(masks, specs, p, c, dt, nsteps, K, "f64", seeds, kernel)
     g_or, lam_or, tot_or = oracle_grad(masks, specs, p, c, dt, nsteps, seeds)
     np.testing.assert_allclose(tot_gpu, tot_or[:, :, :5], rtol=1e-13, atol=1e-300)
     np.testing.assert_allclose(lam_gpu, lam_or, rtol=1e-11, atol=1e-12 * np.abs(lam_or).max())
@@ -219,3 +221,34 @@ def test_record_identical_for_every_neighbour_source(precision):
         np.testing.assert_array_equal(ref[0], xs[0])
         for j in range(1, k):
             np.testing.assert_array_equal(ref[j], orc.transform(p, dt, xs[j - 1]))
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_skip_static_d_leaves_other_gradients_unchanged(precision):
+    """With the static pools' dL/dD_s skipped, those entries are NaN and every
+    other gradient entry and the adjoint of x^0 are bit-identical."""
+    from paper_2406_04177_amd.autograd import simulate_totals, theta_of
+    from paper_2406_04177_amd.graph import Graph
+    from paper_2406_04177_amd.sim import Simulation
+    masks, specs = batch(seed=3)
+    p = rates()
+    c = [0.8, 0.9, 1.0, 0.85, 0.95, 0.75, 0.9, 1.0]
+    dt = inputs.explicit_dt(p, 0.8)
+    nsteps = 20
+    seeds = torch.as_tensor(np.random.default_rng(4).standard_normal((nsteps + 1, len(masks), 5)), device="cuda")
+    g = Graph.from_masks(masks, regions=True)
+    dtype = torch.float64 if precision == "f64" else torch.float32
+    out = []
+    for skip in (False, True):
+        sim = Simulation(g, p, precision=precision, implicit=False, adjoint=True, regions=c)
+        sim.set_adjoint_options(skip_static_d=skip)
+        x0 = g.fields_from_specs(specs, dtype).requires_grad_(True)
+        theta = theta_of(p, c).requires_grad_(True)
+        (simulate_totals(sim, theta, x0, nsteps, dt, checkpoint_every=6) * seeds).sum().backward()
+        out.append((theta.grad.numpy(), x0.grad.cpu().numpy()))
+    (g_all, l_all), (g_skip, l_skip) = out
+    assert np.all(np.isnan(g_skip[[0, 2, 3, 4]]))
+    assert np.all(np.isfinite(g_all))
+    keep = [1] + list(range(5, 20))
+    np.testing.assert_array_equal(g_skip[keep], g_all[keep])
+    np.testing.assert_array_equal(l_skip, l_all)

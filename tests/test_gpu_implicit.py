@@ -14,7 +14,10 @@ from paper_2406_04177_amd import inputs
 pytestmark = pytest.mark.gpu
 
 
-def make(shape=(32, 30, 28), seed=1, regions=None, precision="f64"):
+KERNELS = pytest.mark.parametrize("kernel", [1, 3, 4], ids=["table", "offset", "relative"])
+
+
+def make(shape=(32, 30, 28), seed=1, regions=None, precision="f64", kernel=0):
     from paper_2406_04177_amd.graph import Graph
     from paper_2406_04177_amd.sim import Simulation
     mask = inputs.synthetic_volume(shape, seed=seed)
@@ -23,13 +26,16 @@ def make(shape=(32, 30, 28), seed=1, regions=None, precision="f64"):
     og = orc.build_graph(mask)
     p = inputs.ModelParams(mu=1e-4, rho=5e-5)
     sim = Simulation(g, p, precision=precision, implicit=True, regions=regions)
+    sim.set_kernel(kernel)
     sim.set_fields(g.fields_from_specs(spec, torch.float64))
     return sim, og, orc.fields_from_spec(og, spec), p
 
 
+@KERNELS
 @pytest.mark.parametrize("factor", [1.0, 20.0])
-def test_implicit_step_fp64(factor):
-    sim, og, x0, p = make()
+def test_implicit_step_fp64(factor, kernel):
+    """The SpMV gathers through the explicit step's neighbour source."""
+    sim, og, x0, p = make(kernel=kernel)
     dt = factor * inputs.explicit_dt(p, 1.0)
     a = p.D[1] * dt / p.h ** 2
     rtol = 1e-10
@@ -51,9 +57,10 @@ def test_implicit_step_fp64(factor):
     assert abs(its[1] - oits10[1]) <= 2, (its, oits10)
 
 
-def test_implicit_with_regions_fp32_fields():
+@KERNELS
+def test_implicit_with_regions_fp32_fields(kernel):
     c = [0.7, 1.0, 0.8, 0.9, 1.1, 0.75, 0.95, 0.85]
-    sim, og, x0, p = make(regions=c, precision="f32")
+    sim, og, x0, p = make(regions=c, precision="f32", kernel=kernel)
     dt = 20 * inputs.explicit_dt(p, 1.0)
     a = p.D[1] * dt / p.h ** 2
     its, rel, rc = sim.implicit_step(dt, rtol=1e-10)
