@@ -51,10 +51,11 @@ class _TotalsFn(torch.autograd.Function):
         tot = torch.empty((nsteps + 1, nseg, 6), dtype=torch.float64, device=dev)
         tot[0] = torch.from_numpy(sim.totals()).to(dev)
         ckpts = []
+        keep = any(ctx.needs_input_grad[:2])      # no checkpoints when no gradient is wanted
         k0 = 0
         while k0 < nsteps:
             k = min(K, nsteps - k0)
-            ckpts.append((k0, k, sim.fields.clone()))
+            ckpts.append((k0, k, sim.fields.clone() if keep else None))
             sim.step(k, dt, log_every=1, totals_out=tot[k0 + 1:k0 + 1 + k])
             k0 += k
         ctx.sim, ctx.dt, ctx.ckpts, ctx.nsteps = sim, dt, ckpts, nsteps

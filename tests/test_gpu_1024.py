@@ -1,0 +1,148 @@
+"""The large single-volume workload: 1024^3 at 17 % porosity (n ~ 178 M),
+brick-ordered compacted list (8^3 bricks), FP32 fields with FP64 totals.
+
+  * the graph bit for bit against the oracle's;
+  * 3 FP64 steps bit for bit against the oracle, with the rank index and the
+    neighbour table; 20 FP32 steps within 1e-5 per pool;
+  * the configured 2000 FP32 steps: the two neighbour sources bit-identical,
+    total carbon conserved within FP32 rounding, and every pool within the
+    FP32 rounding bound of the FP64 run (itself bit-identical to the oracle
+    step for step, as checked above);
+  * the adjoint over the first 200 steps with checkpoints every 20: FP32
+    gradients against central differences of the GPU FP64 forward.
+Raster order is also built: it admits the packed neighbour sources, which
+must give the same steps (after un-permuting) as the brick order."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as orc
+from paper_2406_04177_amd import inputs
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
+
+N = 1024
+BRICK = 8
+TABLE, RANK, RELATIVE = 1, 2, 4
+
+
+@pytest.fixture(scope="module")
+def big():
+    from paper_2406_04177_amd.graph import Graph
+    mask = inputs.synthetic_volume((N, N, N), porosity=0.17, seed=0)
+    spec = inputs.init_uniform(mask, seed=0)
+    g = Graph.from_masks(mask, brick=BRICK)
+    print("1024^3: n =", g.n, flush=True)
+    return mask, spec, g
+
+
+def run(g, spec, precision, kernel, steps, log_every=0, params=None):
+    from paper_2406_04177_amd.sim import Simulation
+    p = params or inputs.ModelParams()
+    sim = Simulation(g, p, precision=precision, implicit=False)
+    sim.set_kernel(kernel)
+    assert sim.kernel_in_use() == kernel
+    sim.set_fields(g.fields_from_specs(spec, torch.float64))
+    log = sim.step(steps, inputs.explicit_dt(p), log_every=log_every)
+    torch.cuda.synchronize()
+    out = sim.fields.cpu().numpy()
+    del sim
+    torch.cuda.empty_cache()
+    return out, (log.cpu().numpy() if log is not None else None)
+
+
+def test_graph_and_short_runs_against_oracle(big):
+    mask, spec, g = big
+    og = orc.build_graph(mask, brick=BRICK)
+    assert g.n == og.n
+    np.testing.assert_array_equal(g.vox.cpu().numpy(), og.vox)
+    np.testing.assert_array_equal(g.nbr.cpu().numpy(), og.nbr)
+    p = inputs.ModelParams()
+    dt = inputs.explicit_dt(p)
+    x0 = orc.fields_from_spec(og, spec)
+    ref3, _ = orc.run(p, dt, og, x0, 3, with_totals=False)
+    for kernel in (RANK, TABLE):
+        got, _ = run(g, spec, "f64", kernel, 3)
+        np.testing.assert_array_equal(got, ref3)
+    del ref3
+    ref20, _ = orc.run(p, dt, og, x0, 20, with_totals=False)
+    got, _ = run(g, spec, "f32", RANK, 20)
+    for s in range(5):
+        scale = np.abs(ref20[s]).max()
+        err = np.abs(got[s].astype(np.float64) - ref20[s]).max() / scale if scale > 0 else np.abs(got[s]).max()
+        assert err <= 1e-5, (s, err)
+
+
+def test_2000_steps(big):
+    mask, spec, g = big
+    steps = 2000
+    a, la = run(g, spec, "f32", RANK, steps, log_every=100)
+    b, lb = run(g, spec, "f32", TABLE, steps, log_every=100)
+    np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(la, lb)
+    del b
+    ref, lr = run(g, spec, "f64", RANK, steps, log_every=100)
+    bound = 4 * steps * 2.0 ** -24
+    errs = []
+    for s in range(5):
+        scale = np.abs(ref[s]).max()
+        errs.append(float(np.abs(a[s].astype(np.float64) - ref[s]).max() / scale) if scale > 0 else 0.0)
+    print("1024^3 FP32 vs FP64 after 2000 steps, per pool:", errs, flush=True)
+    assert max(errs) <= bound, errs
+    # totals: the FP64 run conserves carbon to 1e-12, the FP32 run to its rounding bound
+    tot64, tot32 = lr[:, 0, 5], la[:, 0, 5]
+    assert np.abs(tot64 - tot64[0]).max() / tot64[0] <= 1e-12
+    assert np.abs(tot32 - tot64).max() / tot64[0] <= bound
+
+
+def test_raster_order_packed_source_matches_brick_order(big):
+    from paper_2406_04177_amd.graph import Graph
+    mask, spec, gb = big
+    gr = Graph.from_masks(mask)
+    steps = 50
+    a, _ = run(gr, spec, "f32", RELATIVE, steps)
+    b, _ = run(gb, spec, "f32", RANK, steps)
+    perm = np.searchsorted(gr.vox.cpu().numpy(), gb.vox.cpu().numpy())
+    np.testing.assert_array_equal(b, a[:, perm])
+
+
+def test_adjoint_first_200_steps(big):
+    from paper_2406_04177_amd.autograd import co2_mse, simulate_totals, theta_of
+    from paper_2406_04177_amd.graph import Graph
+    from paper_2406_04177_amd.sim import Simulation
+    mask, spec, _ = big
+    g = Graph.from_masks(mask, brick=BRICK, regions=True)
+    p = inputs.ModelParams()
+    dt = inputs.explicit_dt(p, 0.8)
+    steps, K = 200, 20
+    c = [1.0] * 8
+    theta = theta_of(p, c)
+    tgt = theta.clone()
+    for q, f in inputs.target_factors().items():
+        tgt[q] *= f
+    sim64 = Simulation(g, p, precision="f64", implicit=False, adjoint=True, regions=c)
+    x64 = g.fields_from_specs(spec, torch.float64)
+    with torch.no_grad():
+        target = simulate_totals(sim64, tgt, x64, steps, dt, K)[:, :, 4].clone()
+
+    def loss64(th):
+        with torch.no_grad():
+            return float(co2_mse(simulate_totals(sim64, th, x64, steps, dt, K), target))
+
+    sim32 = Simulation(g, p, precision="f32", implicit=False, adjoint=True, regions=c)
+    sim32.set_adjoint_options(skip_static_d=True)
+    th = theta.clone().requires_grad_(True)
+    co2_mse(simulate_totals(sim32, th, g.fields_from_specs(spec, torch.float32), steps, dt, K), target).backward()
+    grad = th.grad.numpy()
+    assert np.all(np.isnan(grad[[0, 2, 3, 4]]))
+    checked = [1, 5, 7, 12, 19]
+    errs = {}
+    for q in checked:
+        eps = 1e-4 * float(theta[q])
+        tp, tm = theta.clone(), theta.clone()
+        tp[q] += eps
+        tm[q] -= eps
+        fd = (loss64(tp) - loss64(tm)) / (2 * eps)
+        errs[q] = abs(grad[q] - fd) / abs(fd)
+    print("1024^3 adjoint (FP32) vs FD (FP64), relative:", errs, flush=True)
+    assert max(errs.values()) <= 1e-3, errs
