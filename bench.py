@@ -55,7 +55,11 @@ OWN_BYTES = {1: BYTES_FUSED_F32, 2: BYTES_RANK_F32, 3: BYTES_OFFSET_F32, 4: BYTE
 KERNEL_SOURCES = ("paper_2406_04177_amd/csrc/vg_step.hip", "paper_2406_04177_amd/csrc/vg_internal.h",
                   "paper_2406_04177_amd/build.py")
 MEASURED_TRAFFIC = {
-    # (kernel, size): (bytes per launch, sha256 of KERNEL_SOURCES)
+    # (neighbour source, size): (bytes per launch, sha256 of KERNEL_SOURCES);
+    # from profiles/k_step_off_relative_f32_512cube.md: FETCH_SIZE 336667.4 KiB
+    # x 2 + WRITE_SIZE 407860.0 KiB x 1 per launch
+    ("relative", 512): (336667.4 * 1024 * 2 + 407860.0 * 1024,
+                        "053dbeb2122d881b9be6d01fafc849d9a84588f878e88a2c7a5e08f5a2eca650"),
 }
 
 
@@ -208,7 +212,7 @@ def main(argv=None):
                     help="finish with three plain 1 GiB device copies (scale for HBM byte counters)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
+        print("bench.py runs on one GPU only: there is no multi-GPU path (the z-slab sharding is a design, not code)",
               file=sys.stderr)
         return 2
 
