@@ -190,3 +190,10 @@ def target_factors(seed: int = 1000, spread: float = 0.1) -> dict:
     """Multipliers 1 + U(-spread, spread) for the PERTURBED entries, in order."""
     d = np.random.default_rng(seed).uniform(-spread, spread, len(PERTURBED))
     return {q: 1.0 + float(v) for q, v in zip(PERTURBED, d)}
+
+
+def epoch_subsets(nvol: int, size: int, epochs: int, seed: int = 0) -> list:
+    """Volumes used by each epoch of a stochastic fit: `size` distinct volumes
+    per epoch, sorted, from default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    return [np.sort(rng.choice(nvol, size=size, replace=False)) for _ in range(epochs)]
