@@ -69,6 +69,8 @@ def lib():
             L.orc_totals.argtypes = [i64, P, i32, P, P]
             L.orc_run.restype = i32
             L.orc_run.argtypes = [P, dbl, i32, i64, P, P, P, i64, i32, P, P]
+            L.orc_run_subcycled.restype = i32
+            L.orc_run_subcycled.argtypes = [P, dbl, dbl, i64, i64, P, P, P]
             L.orc_apply_B.restype = None
             L.orc_apply_B.argtypes = [dbl, i64, P, P, P, P]
             L.orc_pcg.restype = i32
@@ -90,11 +92,13 @@ def _c(a, dtype):
 
 
 def pack_params(params) -> np.ndarray:
-    """prm[14] from any object with attributes D, h, v_dom, k_dom, rho, mu,
-    beta, v_som, v_p4, mort_to_p4 (SI units)."""
+    """prm[15] from any object with attributes D, h, v_dom, k_dom, rho, mu,
+    beta, v_som, v_p4, mort_to_p4 (SI units) and optionally sequential
+    (Algorithm 2 instead of Algorithm 1)."""
     return np.array(list(map(float, params.D)) + [params.h, params.v_dom, params.k_dom, params.rho,
                     params.mu, params.beta, params.v_som, params.v_p4,
-                    1.0 if params.mort_to_p4 else 0.0], dtype=np.float64)
+                    1.0 if params.mort_to_p4 else 0.0,
+                    1.0 if getattr(params, "sequential", False) else 0.0], dtype=np.float64)
 
 
 # ---------------------------------------------------------------------------
@@ -241,6 +245,17 @@ def run(params, dt: float, graph: OracleGraph, x: np.ndarray, nsteps: int, order
     return x, tot
 
 
+def run_subcycled(params, dt_t: float, dt_d: float, graph: OracleGraph, x: np.ndarray, nt: int, w=None):
+    """Unequal transformation / diffusion steps over nt * dt_t (see
+    ``orc_run_subcycled``).  Returns the final state."""
+    x = np.array(x, np.float64, order="C", copy=True)
+    rc = lib().orc_run_subcycled(_p(pack_params(params)), float(dt_t), float(dt_d), int(nt), x.shape[1],
+                                 _p(graph.nbr), _p(_c(w, np.float64)), _p(x))
+    if rc != 0:
+        raise RuntimeError("orc_run_subcycled failed")
+    return x
+
+
 def run_states(params, dt: float, graph: OracleGraph, x: np.ndarray, nsteps: int, order: int = 0,
                w=None) -> np.ndarray:
     """All states x^0..x^nsteps as [nsteps+1][5][n]."""
@@ -300,6 +315,8 @@ def adjoint(params, dt: float, graph: OracleGraph, states: np.ndarray, seeds: np
         raise ValueError("seeds must be [nsteps+1][nseg][5]")
     lam0 = np.empty((NPOOL, n), np.float64)
     grad = np.empty(NPARAM_BASE + nreg, np.float64)
+    if getattr(params, "sequential", False):
+        raise ValueError("the adjoint follows Algorithm 1 only")
     rc = lib().orc_adjoint(_p(pack_params(params)), float(dt), int(order), n, _p(graph.nbr),
                            _p(_c(w, np.float64)), _p(_c(region, np.int32)), int(nreg), int(nsteps),
                            _p(states), graph.nseg, _p(graph.seg_off), _p(seeds),

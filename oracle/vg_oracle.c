@@ -16,10 +16,11 @@
  *   w      double [6][n]   edge weight per slot (NULL: every weight is 1)
  *   x      double [5][n]   pools MB, DOM, SOM, P4 (the paper's FOM), CO2
  *
- * Parameter vector prm[14]
+ * Parameter vector prm[15]
  *   prm[0..4] D_s (m^2/s)   prm[5] h (m)
  *   prm[6] v_DOM  prm[7] K_DOM  prm[8] rho  prm[9] mu  prm[10] beta
  *   prm[11] v_SOM prm[12] v_FOM prm[13] mortality routing (0: paper, 1: to P4)
+ *   prm[14] transformation algorithm (0: Algorithm 1, 1: Algorithm 2)
  *
  * Gradient vector g[12 + R]
  *   g[0..4] dL/dD_s, g[5] v_DOM, g[6] K_DOM, g[7] rho, g[8] mu, g[9] beta,
@@ -34,7 +35,7 @@
 #define NPARAM_BASE 12
 
 enum { P_D = 0, P_H = 5, P_VDOM = 6, P_KDOM = 7, P_RHO = 8, P_MU = 9, P_BETA = 10,
-       P_VSOM = 11, P_VFOM = 12, P_ROUTE = 13 };
+       P_VSOM = 11, P_VFOM = 12, P_ROUTE = 13, P_ALG = 14 };
 
 /* ------------------------------------------------------------------------ */
 /* Graph (Sec. II.A, Fig. 2; Sec. III): the pore voxels are the nodes, and two
@@ -157,11 +158,65 @@ static void transform_one(const double *prm, double dt, double *x1, double *x2,
     *x5 = m5 + resp;
 }
 
+/* Transformation, Appendix A Algorithm 2: the processes of a voxel update
+ * its masses one after the other, each from the masses the previous one
+ * left: uptake (MB grows on DOM), mortality (dead MB to DOM and SOM, or to
+ * pool 4), respiration (MB to CO2), then SOM and FOM turnover to DOM.  A
+ * process that would take more than its source pool holds takes all of it.
+ * As printed the algorithm tests "resp" instead of each turnover against its
+ * own pool, zeroes SOM / FOM before adding them to DOM (losing that mass)
+ * and leaves MB in place when all of it dies; those three slips are read as
+ * corrected here: each turnover is compared with its own pool, the pool is
+ * moved to DOM before it is zeroed, and MB is zeroed when it all dies.      */
+static void transform_seq_one(const double *prm, double dt, double *x1, double *x2,
+                              double *x3, double *x4, double *x5)
+{
+    double v_dom = prm[P_VDOM], k_dom = prm[P_KDOM], rho = prm[P_RHO], mu = prm[P_MU];
+    double beta = prm[P_BETA], v_som = prm[P_VSOM], v_fom = prm[P_VFOM];
+    int paper_route = prm[P_ROUTE] == 0.0;
+    double m1 = *x1, m2 = *x2, m3 = *x3, m4 = *x4, m5 = *x5;
+
+    if (m1 > 0.0) {
+        if (m2 > 0.0) {
+            double uptake = v_dom * m2 / (k_dom + m2) * m1 * dt;
+            if (uptake < m2) { m1 = m1 + uptake; m2 = m2 - uptake; }
+            else { m1 = m1 + m2; m2 = 0.0; }
+        }
+        double morta = mu * m1 * dt;
+        if (morta < m1) {
+            m1 = m1 - morta;
+            if (paper_route) { m2 = m2 + beta * morta; m3 = m3 + (1.0 - beta) * morta; }
+            else m4 = m4 + morta;
+        } else {
+            if (paper_route) { m2 = m2 + beta * m1; m3 = m3 + (1.0 - beta) * m1; }
+            else m4 = m4 + m1;
+            m1 = 0.0;
+        }
+        double resp = rho * m1 * dt;
+        if (resp < m1) { m1 = m1 - resp; m5 = m5 + resp; }
+        else { m5 = m5 + m1; m1 = 0.0; }
+    }
+    if (m3 > 0.0) {
+        double turn_som = v_som * m3 * dt;
+        if (turn_som < m3) { m3 = m3 - turn_som; m2 = m2 + turn_som; }
+        else { m2 = m2 + m3; m3 = 0.0; }
+    }
+    if (m4 > 0.0) {
+        double turn_fom = v_fom * m4 * dt;
+        if (turn_fom < m4) { m4 = m4 - turn_fom; m2 = m2 + turn_fom; }
+        else { m2 = m2 + m4; m4 = 0.0; }
+    }
+    *x1 = m1; *x2 = m2; *x3 = m3; *x4 = m4; *x5 = m5;
+}
+
 void orc_transform(const double *prm, double dt, int64_t n, double *x)
 {
+    int seq = prm[P_ALG] != 0.0;
     #pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < n; i++)
-        transform_one(prm, dt, &x[i], &x[n + i], &x[2 * n + i], &x[3 * n + i], &x[4 * n + i]);
+    for (int64_t i = 0; i < n; i++) {
+        if (seq) transform_seq_one(prm, dt, &x[i], &x[n + i], &x[2 * n + i], &x[3 * n + i], &x[4 * n + i]);
+        else transform_one(prm, dt, &x[i], &x[n + i], &x[2 * n + i], &x[3 * n + i], &x[4 * n + i]);
+    }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -275,6 +330,41 @@ int orc_run(const double *prm, double dt, int order, int64_t n, const int32_t *n
             orc_transform(prm, dt, n, x);
         }
         if (totals) orc_totals(n, x, nseg, seg_off, totals + (t + 1) * nseg * 6);
+    }
+    free(tmp);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Unequal time steps (Sec. III: the process with the smaller step is
+ * repeated).  Over [0, t_end], t_end = nt * dt_t, transformation steps of
+ * dt_t start at k dt_t (k < nt) and diffusion steps of dt_d start at k dt_d
+ * while k dt_d < t_end, the last one shortened to end at t_end.  Every step
+ * is explicit and uses the state at its start, so the steps are applied in
+ * the order of their start times, a transformation first when both start
+ * together (with dt_t = dt_d this is the paper's T-then-D step).            */
+/* ------------------------------------------------------------------------ */
+
+int orc_run_subcycled(const double *prm, double dt_t, double dt_d, int64_t nt, int64_t n,
+                      const int32_t *nbr, const double *w, double *x)
+{
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!tmp) return -1;
+    double t_end = (double)nt * dt_t;
+    int64_t kt = 0, kd = 0;
+    for (;;) {
+        double st = (double)kt * dt_t;       /* start of the next transformation step */
+        double sd = (double)kd * dt_d;       /* start of the next diffusion step */
+        int more_t = kt < nt, more_d = sd < t_end;
+        if (!more_t && !more_d) break;
+        if (more_t && (!more_d || st <= sd)) {
+            orc_transform(prm, dt_t, n, x);
+            kt++;
+        } else {
+            double len = (double)(kd + 1) * dt_d <= t_end ? dt_d : t_end - sd;
+            orc_diffuse(prm, len, n, nbr, w, x, tmp);
+            kd++;
+        }
     }
     free(tmp);
     return 0;
@@ -493,6 +583,7 @@ int orc_adjoint(const double *prm, double dt, int order, int64_t n, const int32_
                 const double *states, int nseg, const int64_t *seg_off, const double *seeds,
                 const double *lam_final, double *lam0, double *grad)
 {
+    if (prm[P_ALG] != 0.0) return -2;     /* the adjoint follows Algorithm 1 only */
     size_t nn = (size_t)(n > 0 ? n : 1);
     double *lam = lam0;
     double *u = malloc(sizeof(double) * NPOOL * nn);

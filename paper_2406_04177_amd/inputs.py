@@ -130,6 +130,7 @@ class ModelParams:
     v_som: float = 1e-7
     v_p4: float = 1e-7
     mort_to_p4: bool = False
+    sequential: bool = False       # Appendix A Algorithm 2 instead of Algorithm 1
 
     def replace(self, **kw) -> "ModelParams":
         return dataclasses.replace(self, **kw)
