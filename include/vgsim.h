@@ -68,13 +68,21 @@ extern "C" {
 /* Model parameters, SI units.  a_s = D[s] * dt / h^2 is the dimensionless
  * diffusion number of pool s (voxel units give S_ij = d_ij = 1, Sec. II.B.2).
  * mort_to_p4 = 0 routes a fraction beta of dead biomass to DOM and 1 - beta to
- * SOM (Sec. II.C); 1 routes all of it to pool 3. */
+ * SOM (Sec. II.C); 1 routes all of it to pool 3.  sequential = 0 transforms
+ * with Appendix A Algorithm 1 (every flux from the pre-step masses, clamped,
+ * then applied); 1 with Algorithm 2 (uptake, mortality, respiration, SOM and
+ * FOM turnover one after the other, each on what the previous left, a
+ * process taking at most all of its source pool; the printed algorithm's
+ * slips read as corrected: each turnover is compared with its own pool,
+ * moved to DOM before the pool is zeroed, and MB is zeroed when it all
+ * dies).  The adjoint follows Algorithm 1 only. */
 typedef struct vg_params {
     double D[VG_NPOOL];
     double h;
     double v_dom, k_dom, rho, mu, beta, v_som, v_p4;
     int32_t mort_to_p4;
     int32_t step_order;   /* VG_ORDER_TD or VG_ORDER_DT */
+    int32_t sequential;   /* 0: Algorithm 1, 1: Algorithm 2 */
 } vg_params;
 
 /* ---- errors ------------------------------------------------------------ */
@@ -206,6 +214,20 @@ int vg_init_state(vg_sim *h, void *fields_d, void *alt_d, void *work_d, size_t w
 int vg_step_explicit(vg_sim *h, int64_t nsteps, double dt, int64_t log_every,
                      double *totals_log_d, unsigned flags, void *stream);
 
+/* Unequal time steps for transformation and diffusion (Sec. III: the
+ * process with the smaller step is repeated).  Over [0, t_end] with
+ * t_end = n_t * dt_t, transformation steps of dt_t start at k dt_t
+ * (k < n_t) and Scheme 1 diffusion steps of dt_d start at k dt_d while
+ * k dt_d < t_end, the last one shortened to end at t_end.  Each step uses the
+ * state at its start, so the steps run in the order of their start times, a
+ * transformation first when both start together (dt_t == dt_d reproduces
+ * vg_step_explicit in the paper's order).  A diffusion step directly followed
+ * by a transformation step runs as one fused pass.  Returns VG_EUNSTABLE,
+ * without stepping, when dt_d is above the positivity bound (see
+ * vg_step_explicit) unless flags has VG_FORCE.  No totals are logged; on
+ * return the bound fields hold the state at t_end. */
+int vg_step_subcycled(vg_sim *h, int64_t n_t, double dt_t, double dt_d, unsigned flags, void *stream);
+
 /* One implicit step (Scheme 2): the transformation, then for each pool with
  * D_s > 0 the system (I + a_s L_w) y = x_s solved by Jacobi-preconditioned CG
  * in FP64 (start y = x_s; stop at ||x_s - B y||_2 <= rtol ||x_s||_2).
@@ -234,7 +256,9 @@ int vg_mass_totals(vg_sim *h, double *out_h, void *stream);
  *   grad_d   [VG_NGRAD] FP64, accumulated (+=):
  *            [0..4] dL/dD_s, [5] v_DOM, [6] K_DOM, [7] rho, [8] mu, [9] beta,
  *            [10] v_SOM, [11] v_P4, [12..19] dL/dc_r (zero without regions).
- * dt must equal the one used for the forward steps. */
+ * dt must equal the one used for the forward steps.  Both calls return
+ * VG_EINVAL for params.sequential = 1 (the reverse sweep differentiates
+ * Algorithm 1) and for the diffuse-first step order. */
 int vg_record(vg_sim *h, int64_t nsteps, double dt, void *states_d, void *stream);
 int vg_adjoint(vg_sim *h, int64_t nsteps, double dt, const void *states_d, const double *seeds_d,
                void *lambda_d, double *grad_d, void *stream);

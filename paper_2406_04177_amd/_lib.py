@@ -26,7 +26,7 @@ VG_ADJ_SKIP_STATIC_D = 1
 EXPORTS = ("vg_strerror", "vg_last_error", "vg_version", "vg_rank_bytes", "vg_count_pores",
            "vg_build_graph", "vg_lookup", "vg_region_codes", "vg_create", "vg_destroy",
            "vg_set_kernel", "vg_get_kernel", "vg_set_adjoint_options", "vg_set_params", "vg_set_regions", "vg_alt_elems", "vg_workspace_bytes", "vg_init_state",
-           "vg_step_explicit", "vg_solve_implicit_step", "vg_mass_totals", "vg_record", "vg_adjoint",
+           "vg_step_explicit", "vg_step_subcycled", "vg_solve_implicit_step", "vg_mass_totals", "vg_record", "vg_adjoint",
            "vg_seed_lambda")
 
 
@@ -40,7 +40,7 @@ class VgParams(ctypes.Structure):
     _fields_ = [("D", ctypes.c_double * 5), ("h", ctypes.c_double), ("v_dom", ctypes.c_double),
                 ("k_dom", ctypes.c_double), ("rho", ctypes.c_double), ("mu", ctypes.c_double),
                 ("beta", ctypes.c_double), ("v_som", ctypes.c_double), ("v_p4", ctypes.c_double),
-                ("mort_to_p4", ctypes.c_int32), ("step_order", ctypes.c_int32)]
+                ("mort_to_p4", ctypes.c_int32), ("step_order", ctypes.c_int32), ("sequential", ctypes.c_int32)]
 
 
 class VgDesc(ctypes.Structure):
@@ -87,6 +87,7 @@ def load():
             "vg_workspace_bytes": (I, [P, ctypes.POINTER(S)]),
             "vg_init_state": (I, [P, P, P, P, S, P]),
             "vg_step_explicit": (I, [P, I64, D, I64, P, U, P]),
+            "vg_step_subcycled": (I, [P, I64, D, D, U, P]),
             "vg_solve_implicit_step": (I, [P, D, D, I, P, P, P]),
             "vg_mass_totals": (I, [P, P, P]),
             "vg_record": (I, [P, I64, D, P, P]),

@@ -137,6 +137,21 @@ int check_params(const vg_sim *h, const vg_params *p) {
         set_error("step_order must be VG_ORDER_TD or VG_ORDER_DT");
         return VG_EINVAL;
     }
+    if (p->sequential != 0 && p->sequential != 1) { set_error("sequential must be 0 or 1"); return VG_EINVAL; }
+    return VG_OK;
+}
+
+double max_c(const vg_sim *h);
+
+// VG_EUNSTABLE when an explicit diffusion step of dt could make masses negative.
+int check_stable(const vg_sim *h, double dt) {
+    double dmax = 0;
+    for (int s = 0; s < VG_NPOOL; s++) dmax = h->params.D[s] > dmax ? h->params.D[s] : dmax;
+    const double worst = dmax * dt / (h->params.h * h->params.h) * 6.0 * max_c(h);
+    if (worst > 1.0) {
+        set_error("dt = %g gives max_s a_s * sum_j w_ij = %g > 1 (negative masses possible)", dt, worst);
+        return VG_EUNSTABLE;
+    }
     return VG_OK;
 }
 
@@ -341,15 +356,7 @@ extern "C" int vg_step_explicit(vg_sim *h, int64_t nsteps, double dt, int64_t lo
     const int64_t nlog = log_every > 0 ? nsteps / log_every : 0;
     if (nlog > 0 && !totals_log_d) { set_error("totals_log_d is NULL"); return VG_EINVAL; }
     if (flags & ~VG_FORCE) { set_error("unknown flags"); return VG_EINVAL; }
-    if (!(flags & VG_FORCE)) {
-        double dmax = 0;
-        for (int s = 0; s < VG_NPOOL; s++) dmax = h->params.D[s] > dmax ? h->params.D[s] : dmax;
-        const double worst = dmax * dt / (h->params.h * h->params.h) * 6.0 * max_c(h);
-        if (worst > 1.0) {
-            set_error("dt = %g gives max_s a_s * sum_j w_ij = %g > 1 (negative masses possible)", dt, worst);
-            return VG_EUNSTABLE;
-        }
-    }
+    if (!(flags & VG_FORCE) && (rc = check_stable(h, dt))) return rc;
     if ((rc = need_bound(h))) return rc;
     if (nsteps == 0 || h->n == 0) return VG_OK;
     hipStream_t s = (hipStream_t)stream;
@@ -373,6 +380,47 @@ extern "C" int vg_step_explicit(vg_sim *h, int64_t nsteps, double dt, int64_t lo
             const bool lg = logged(j);
             if ((rc = launch_pass(h, MODE_DT, lg ? TOT_OUT : TOT_NONE, dt, s))) return rc;
             if (lg && (rc = finalize(j))) return rc;
+        }
+    }
+    return restore_canonical(h, s);
+}
+
+extern "C" int vg_step_subcycled(vg_sim *h, int64_t n_t, double dt_t, double dt_d, unsigned flags, void *stream) {
+    int rc;
+    if (!h) { set_error("handle is NULL"); return VG_EINVAL; }
+    if (n_t < 0 || !(dt_t > 0) || !std::isfinite(dt_t) || !(dt_d > 0) || !std::isfinite(dt_d)) {
+        set_error("need n_t >= 0, dt_t > 0, dt_d > 0");
+        return VG_EINVAL;
+    }
+    if (flags & ~VG_FORCE) { set_error("unknown flags"); return VG_EINVAL; }
+    if (!(flags & VG_FORCE) && (rc = check_stable(h, dt_d))) return rc;
+    if ((rc = need_bound(h))) return rc;
+    if (n_t == 0 || h->n == 0) return VG_OK;
+    hipStream_t s = (hipStream_t)stream;
+    // The steps in the order of their start times (a transformation first on
+    // ties); a diffusion step followed by a transformation step is one fused
+    // pass (diffuse, then transform: exactly the two steps in that order).
+    const double t_end = (double)n_t * dt_t;
+    int64_t kt = 0, kd = 0;
+    auto next_is_t = [&]() -> int {   // 1: transformation, 0: diffusion, -1: done
+        const bool more_t = kt < n_t, more_d = (double)kd * dt_d < t_end;
+        if (!more_t && !more_d) return -1;
+        return (more_t && (!more_d || (double)kt * dt_t <= (double)kd * dt_d)) ? 1 : 0;
+    };
+    for (int e = next_is_t(); e >= 0; e = next_is_t()) {
+        if (e == 1) {
+            if ((rc = launch_pass2(h, MODE_T, TOT_NONE, dt_t, dt_d, s))) return rc;
+            kt++;
+            continue;
+        }
+        const double sd = (double)kd * dt_d;
+        const double len = (double)(kd + 1) * dt_d <= t_end ? dt_d : t_end - sd;
+        kd++;
+        if (next_is_t() == 1) {
+            if ((rc = launch_pass2(h, MODE_DT, TOT_NONE, dt_t, len, s))) return rc;
+            kt++;
+        } else {
+            if ((rc = launch_pass2(h, MODE_D, TOT_NONE, dt_t, len, s))) return rc;
         }
     }
     return restore_canonical(h, s);
@@ -431,6 +479,7 @@ extern "C" int vg_record(vg_sim *h, int64_t nsteps, double dt, void *states_d, v
     if (rc) return rc;
     if (!(h->features & VG_FEAT_ADJ)) { set_error("handle created without VG_FEAT_ADJ"); return VG_ESTATE; }
     if (h->params.step_order != VG_ORDER_TD) { set_error("the adjoint supports the paper order only"); return VG_EINVAL; }
+    if (h->params.sequential) { set_error("the adjoint follows Algorithm 1 only"); return VG_EINVAL; }
     if (nsteps < 0 || !(dt > 0) || (nsteps > 0 && h->n > 0 && !states_d)) { set_error("bad record arguments"); return VG_EINVAL; }
     return launch_record(h, nsteps, dt, states_d, (hipStream_t)stream);
 }
@@ -441,6 +490,7 @@ extern "C" int vg_adjoint(vg_sim *h, int64_t nsteps, double dt, const void *stat
     if (rc) return rc;
     if (!(h->features & VG_FEAT_ADJ)) { set_error("handle created without VG_FEAT_ADJ"); return VG_ESTATE; }
     if (h->params.step_order != VG_ORDER_TD) { set_error("the adjoint supports the paper order only"); return VG_EINVAL; }
+    if (h->params.sequential) { set_error("the adjoint follows Algorithm 1 only"); return VG_EINVAL; }
     if (nsteps < 0 || !(dt > 0)) { set_error("need nsteps >= 0 and dt > 0"); return VG_EINVAL; }
     if (nsteps > 0 && h->n > 0 && (!states_d || !seeds_d || !lambda_d || !grad_d)) {
         set_error("null pointer argument");

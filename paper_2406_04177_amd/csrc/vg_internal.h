@@ -142,6 +142,7 @@ struct Coef {
     R a[VG_NPOOL];       // D_s dt / h^2
     R v_dom, k_dom, rho, mu, beta, omb, v_som, v_p4, dt;   // omb = 1 - beta
     int route;           // 0 paper, 1 all mortality to pool 3
+    int seq;             // 0 Algorithm 1, 1 Algorithm 2
     R c[VG_NREG];        // region conductance factors
 };
 
@@ -412,6 +413,7 @@ namespace vg {
 enum { MODE_T = 0, MODE_D = 1, MODE_DT = 2, MODE_NONE = 3 };
 enum { TOT_NONE = 0, TOT_IN = 1, TOT_MID = 2, TOT_OUT = 3 };
 int launch_pass(vg_sim *h, int mode, int tot, double dt, hipStream_t s);
+int launch_pass2(vg_sim *h, int mode, int tot, double dt_t, double dt_d, hipStream_t s);
 int launch_pass_bufs(vg_sim *h, int mode, int tot, double dt, const void *const src[VG_NPOOL],
                      void *const dst[VG_NPOOL], hipStream_t s);
 int launch_totals_finalize(vg_sim *h, double *out_rows, hipStream_t s);
@@ -431,6 +433,22 @@ int launch_adjoint(vg_sim *h, int64_t nsteps, double dt, const void *states, con
                    void *lambda, double *grad, hipStream_t s);
 int launch_seed(vg_sim *h, const double *seed, void *lambda, int zero, hipStream_t s);
 
+// Coefficients of a pass whose transformation step is dt_t and whose
+// diffusion step is dt_d (equal except in sub-cycled runs).
+template <typename R>
+Coef<R> make_coef2(const vg_sim *h, double dt_t, double dt_d) {
+    Coef<R> c;
+    const vg_params &p = h->params;
+    for (int s = 0; s < VG_NPOOL; s++) c.a[s] = (R)(p.D[s] * dt_d / (p.h * p.h));
+    c.v_dom = (R)p.v_dom; c.k_dom = (R)p.k_dom; c.rho = (R)p.rho; c.mu = (R)p.mu;
+    c.beta = (R)p.beta; c.omb = (R)(1.0 - p.beta); c.v_som = (R)p.v_som; c.v_p4 = (R)p.v_p4;
+    c.dt = (R)dt_t;
+    c.route = p.mort_to_p4 ? 1 : 0;
+    c.seq = p.sequential ? 1 : 0;
+    for (int r = 0; r < VG_NREG; r++) c.c[r] = (R)h->c[r];
+    return c;
+}
+
 template <typename R>
 Coef<R> make_coef(const vg_sim *h, double dt) {
     Coef<R> c;
@@ -440,6 +458,7 @@ Coef<R> make_coef(const vg_sim *h, double dt) {
     c.beta = (R)p.beta; c.omb = (R)(1.0 - p.beta); c.v_som = (R)p.v_som; c.v_p4 = (R)p.v_p4;
     c.dt = (R)dt;
     c.route = p.mort_to_p4 ? 1 : 0;
+    c.seq = p.sequential ? 1 : 0;
     for (int r = 0; r < VG_NREG; r++) c.c[r] = (R)h->c[r];
     return c;
 }

@@ -34,10 +34,69 @@
 namespace vg {
 namespace {
 
+// Transformation of one voxel, Appendix A Algorithm 2 (sequential): uptake,
+// mortality, respiration, SOM and FOM turnover update the masses one after
+// the other, each from what the previous left; a process that would take
+// more than its source holds takes all of it.  The printed algorithm's slips
+// are read as corrected (each turnover against its own pool, the pool moved
+// to DOM before it is zeroed, MB zeroed when it all dies).
+template <typename R>
+__device__ __forceinline__ void transform_seq(const Coef<R> &C, R &m1, R &m2, R &m3, R &m4, R &m5) {
+    if (m1 > R(0)) {
+        if (m2 > R(0)) {
+            const R uptake = C.v_dom * m2 / (C.k_dom + m2) * m1 * C.dt;
+            if (uptake < m2) {
+                m1 = m1 + uptake;
+                m2 = m2 - uptake;
+            } else {
+                m1 = m1 + m2;
+                m2 = R(0);
+            }
+        }
+        const R morta = C.mu * m1 * C.dt;
+        const R dead = morta < m1 ? morta : m1;
+        m1 = morta < m1 ? m1 - morta : R(0);
+        if (C.route == 0) {
+            m2 = m2 + C.beta * dead;
+            m3 = m3 + C.omb * dead;
+        } else {
+            m4 = m4 + dead;
+        }
+        const R resp = C.rho * m1 * C.dt;
+        if (resp < m1) {
+            m1 = m1 - resp;
+            m5 = m5 + resp;
+        } else {
+            m5 = m5 + m1;
+            m1 = R(0);
+        }
+    }
+    if (m3 > R(0)) {
+        const R turn = C.v_som * m3 * C.dt;
+        if (turn < m3) {
+            m3 = m3 - turn;
+            m2 = m2 + turn;
+        } else {
+            m2 = m2 + m3;
+            m3 = R(0);
+        }
+    }
+    if (m4 > R(0)) {
+        const R turn = C.v_p4 * m4 * C.dt;
+        if (turn < m4) {
+            m4 = m4 - turn;
+            m2 = m2 + turn;
+        } else {
+            m2 = m2 + m4;
+            m4 = R(0);
+        }
+    }
+}
+
 // Transformation of one voxel, Appendix A Algorithm 1: fluxes from the
 // pre-step masses, each clamped to what its source pool holds, then applied.
 template <typename R>
-__device__ __forceinline__ void transform(const Coef<R> &C, R &m1, R &m2, R &m3, R &m4, R &m5) {
+__device__ __forceinline__ void transform_flux(const Coef<R> &C, R &m1, R &m2, R &m3, R &m4, R &m5) {
     R uptake = C.v_dom * m2 / (C.k_dom + m2) * m1 * C.dt;
     if (uptake > m2) uptake = m2;
     R resp = C.rho * m1 * C.dt;
@@ -72,6 +131,19 @@ __device__ __forceinline__ void transform(const Coef<R> &C, R &m1, R &m2, R &m3,
     m3 = n3;
     m4 = n4;
     m5 = m5 + resp;
+}
+
+// The algorithm chosen at compile time (the hot pass) or by C.seq.
+template <bool SEQ, typename R>
+__device__ __forceinline__ void transform_alg(const Coef<R> &C, R &m1, R &m2, R &m3, R &m4, R &m5) {
+    if constexpr (SEQ) transform_seq(C, m1, m2, m3, m4, m5);
+    else transform_flux(C, m1, m2, m3, m4, m5);
+}
+
+template <typename R>
+__device__ __forceinline__ void transform(const Coef<R> &C, R &m1, R &m2, R &m3, R &m4, R &m5) {
+    if (C.seq) transform_seq(C, m1, m2, m3, m4, m5);
+    else transform_flux(C, m1, m2, m3, m4, m5);
 }
 
 template <typename R>
@@ -311,7 +383,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepBufs<R> B, Coef<R> C, Piece
 // an absent neighbour has d = 0 and so reads the voxel itself, whose
 // difference x_i - x_i is exactly +0 (the absent slot's zero) for finite
 // values, so no selects are needed.  All indices are 32-bit.
-template <typename R, int MODE, int MOB, bool REG, int TOT, bool RELC>
+template <typename R, int MODE, int MOB, bool REG, int TOT, bool RELC, bool SEQ>
 __global__ __launch_bounds__(kBlock) void k_step_off(StepBufs<R> B, Coef<R> C, Pieces pc, double *__restrict__ part) {
     static_assert(MODE == MODE_D || MODE == MODE_DT, "diffusing passes only");
     __shared__ double lds[kWaves * VG_NPOOL];
@@ -389,7 +461,7 @@ __global__ __launch_bounds__(kBlock) void k_step_off(StepBufs<R> B, Coef<R> C, P
 #pragma unroll
             for (int s = 0; s < VG_NPOOL; s++) acc[v][s] = (double)x[v][s];
         }
-        if (MODE == MODE_DT) transform(C, x[v][0], x[v][1], x[v][2], x[v][3], x[v][4]);
+        if (MODE == MODE_DT) transform_alg<SEQ>(C, x[v][0], x[v][1], x[v][2], x[v][3], x[v][4]);
         if (TOT == TOT_OUT && act[v]) {
 #pragma unroll
             for (int s = 0; s < VG_NPOOL; s++) acc[v][s] = (double)x[v][s];
@@ -702,14 +774,25 @@ template <typename R, int MODE, int MOB, bool REG, int TOT>
 int launch_one(vg_sim *h, const StepBufs<R> &B, const Coef<R> &C, hipStream_t s) {
     Pieces pc{h->piece_first, h->piece_lo, h->piece_seg, h->npieces};
     if constexpr (MODE == MODE_D || MODE == MODE_DT) {
+        // the algorithm is a template argument of the packed-source pass
+        // (Algorithm 2 instances only where a transformation runs)
+        const bool seq = MODE == MODE_DT && C.seq;
         if (use_relative(h)) {
-            hipLaunchKernelGGL((k_step_off<R, MODE, MOB, REG, TOT, true>), dim3((unsigned)h->ntiles), dim3(kBlock), 0,
-                               s, B, C, pc, h->part);
+            if (seq)
+                hipLaunchKernelGGL((k_step_off<R, MODE, MOB, REG, TOT, true, MODE == MODE_DT>),
+                                   dim3((unsigned)h->ntiles), dim3(kBlock), 0, s, B, C, pc, h->part);
+            else
+                hipLaunchKernelGGL((k_step_off<R, MODE, MOB, REG, TOT, true, false>), dim3((unsigned)h->ntiles),
+                                   dim3(kBlock), 0, s, B, C, pc, h->part);
             return launch_status("k_step_off relative");
         }
         if (use_offsets(h)) {
-            hipLaunchKernelGGL((k_step_off<R, MODE, MOB, REG, TOT, false>), dim3((unsigned)h->ntiles), dim3(kBlock), 0,
-                               s, B, C, pc, h->part);
+            if (seq)
+                hipLaunchKernelGGL((k_step_off<R, MODE, MOB, REG, TOT, false, MODE == MODE_DT>),
+                                   dim3((unsigned)h->ntiles), dim3(kBlock), 0, s, B, C, pc, h->part);
+            else
+                hipLaunchKernelGGL((k_step_off<R, MODE, MOB, REG, TOT, false, false>), dim3((unsigned)h->ntiles),
+                                   dim3(kBlock), 0, s, B, C, pc, h->part);
             return launch_status("k_step_off");
         }
     }
@@ -744,8 +827,8 @@ int pick_reg(vg_sim *h, int tot, const StepBufs<R> &B, const Coef<R> &C, hipStre
 }
 
 template <typename R>
-int dispatch_bufs(vg_sim *h, int mode, int tot, double dt, const StepBufs<R> &B, hipStream_t s) {
-    const Coef<R> C = make_coef<R>(h, dt);
+int dispatch_bufs(vg_sim *h, int mode, int tot, double dt_t, double dt_d, const StepBufs<R> &B, hipStream_t s) {
+    const Coef<R> C = make_coef2<R>(h, dt_t, dt_d);
     const int mob = h->mobile_mode();
     if (mode == MODE_T) return pick_tot<R, MODE_T, 1, false>(h, tot, B, C, s);
     if (mode == MODE_NONE) return launch_one<R, MODE_NONE, 1, false, TOT_IN>(h, B, C, s);
@@ -755,7 +838,7 @@ int dispatch_bufs(vg_sim *h, int mode, int tot, double dt, const StepBufs<R> &B,
 }
 
 template <typename R>
-int dispatch(vg_sim *h, int mode, int tot, double dt, hipStream_t s) {
+int dispatch(vg_sim *h, int mode, int tot, double dt_t, double dt_d, hipStream_t s) {
     StepBufs<R> B = graph_bufs<R>(h);
     const int mob = h->mobile_mode();
     R *canon = (R *)h->fields;
@@ -771,7 +854,7 @@ int dispatch(vg_sim *h, int mode, int tot, double dt, hipStream_t s) {
         // a pass that diffuses writes mobile pools to the other buffer
         B.dst[p] = (mob_p && (mode == MODE_D || mode == MODE_DT)) ? oth : cur;
     }
-    const int rc = dispatch_bufs<R>(h, mode, tot, dt, B, s);
+    const int rc = dispatch_bufs<R>(h, mode, tot, dt_t, dt_d, B, s);
     if (rc) return rc;
     if (mode == MODE_D || mode == MODE_DT) h->cur ^= 1;
     return VG_OK;
@@ -876,10 +959,14 @@ int launch_geometry(vg_sim *h, hipStream_t s) {
     return launch_status("k_geometry");
 }
 
-int launch_pass(vg_sim *h, int mode, int tot, double dt, hipStream_t s) {
+int launch_pass2(vg_sim *h, int mode, int tot, double dt_t, double dt_d, hipStream_t s) {
     if (h->n == 0) return VG_OK;
-    if (h->prec == VG_F64) return dispatch<double>(h, mode, tot, dt, s);
-    return dispatch<float>(h, mode, tot, dt, s);
+    if (h->prec == VG_F64) return dispatch<double>(h, mode, tot, dt_t, dt_d, s);
+    return dispatch<float>(h, mode, tot, dt_t, dt_d, s);
+}
+
+int launch_pass(vg_sim *h, int mode, int tot, double dt, hipStream_t s) {
+    return launch_pass2(h, mode, tot, dt, dt, s);
 }
 
 // A pass between explicit buffers (pool s read from src[s], written to
@@ -890,11 +977,11 @@ int launch_pass_bufs(vg_sim *h, int mode, int tot, double dt, const void *const 
     if (h->prec == VG_F64) {
         StepBufs<double> B = graph_bufs<double>(h);
         for (int p = 0; p < VG_NPOOL; p++) { B.src[p] = (const double *)src[p]; B.dst[p] = (double *)dst[p]; }
-        return dispatch_bufs<double>(h, mode, tot, dt, B, s);
+        return dispatch_bufs<double>(h, mode, tot, dt, dt, B, s);
     }
     StepBufs<float> B = graph_bufs<float>(h);
     for (int p = 0; p < VG_NPOOL; p++) { B.src[p] = (const float *)src[p]; B.dst[p] = (float *)dst[p]; }
-    return dispatch_bufs<float>(h, mode, tot, dt, B, s);
+    return dispatch_bufs<float>(h, mode, tot, dt, dt, B, s);
 }
 
 int launch_totals_finalize(vg_sim *h, double *out_rows, hipStream_t s) {

@@ -28,6 +28,7 @@ def to_vg_params(p: ModelParams, step_order: int = _lib.VG_ORDER_TD) -> _lib.VgP
     vp.beta, vp.v_som, vp.v_p4 = float(p.beta), float(p.v_som), float(p.v_p4)
     vp.mort_to_p4 = 1 if p.mort_to_p4 else 0
     vp.step_order = int(step_order)
+    vp.sequential = 1 if getattr(p, "sequential", False) else 0
     return vp
 
 
@@ -134,6 +135,12 @@ class Simulation:
                                            log.data_ptr() if nlog else None,
                                            _lib.VG_FORCE if force else 0, self._sp()), "vg_step_explicit")
         return log if nlog else None
+
+    def step_subcycled(self, n_t: int, dt_t: float, dt_d: float, force: bool = False):
+        """Unequal steps: n_t transformation steps of dt_t and diffusion steps of
+        dt_d (the last shortened) over n_t * dt_t, ordered by start time."""
+        _lib.check(self.L.vg_step_subcycled(self.h, int(n_t), float(dt_t), float(dt_d),
+                                            _lib.VG_FORCE if force else 0, self._sp()), "vg_step_subcycled")
 
     def implicit_step(self, dt: float, rtol: float = 1e-10, max_iter: int = 1000, check: bool = True):
         """One implicit step (transformation + Scheme 2 by PCG).  Returns

@@ -114,6 +114,31 @@ def test_explicit_stability_bound_is_checked_before_any_device_work():
     L.vg_destroy(h)
 
 
+def test_subcycled_step_validation():
+    """Unequal steps: arguments checked, the diffusion step held to the
+    stability bound before any device work; Algorithm 2 is a parameter."""
+    from paper_2406_04177_amd.inputs import ModelParams, explicit_dt
+    from paper_2406_04177_amd.sim import to_vg_params
+    L = _lib.load()
+    rc, h, _ = make_handle()
+    p = ModelParams(sequential=True)
+    assert L.vg_set_params(h, ctypes.byref(to_vg_params(p))) == 0
+    vp = to_vg_params(p)
+    vp.sequential = 2
+    assert L.vg_set_params(h, ctypes.byref(vp)) == _lib.VG_EINVAL
+    bound = explicit_dt(p, factor=1.0)
+    assert L.vg_step_subcycled(None, 1, 1.0, bound, 0, None) == _lib.VG_EINVAL
+    assert L.vg_step_subcycled(h, -1, 1.0, bound, 0, None) == _lib.VG_EINVAL
+    assert L.vg_step_subcycled(h, 1, 0.0, bound, 0, None) == _lib.VG_EINVAL
+    assert L.vg_step_subcycled(h, 1, 1.0, float("inf"), 0, None) == _lib.VG_EINVAL
+    assert L.vg_step_subcycled(h, 1, 1.0, bound, 4, None) == _lib.VG_EINVAL          # unknown flag
+    # the transformation step may be anything; the diffusion step is bounded
+    assert L.vg_step_subcycled(h, 1, 50 * bound, bound * 1.01, 0, None) == _lib.VG_EUNSTABLE
+    assert L.vg_step_subcycled(h, 1, 50 * bound, bound * 0.99, 0, None) == _lib.VG_ESTATE
+    assert L.vg_step_subcycled(h, 1, 50 * bound, bound * 1.01, _lib.VG_FORCE, None) == _lib.VG_ESTATE
+    L.vg_destroy(h)
+
+
 def test_calls_out_of_sequence():
     L = _lib.load()
     rc, h, _ = make_handle(features=0)
