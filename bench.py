@@ -242,6 +242,35 @@ def fit_batch(epochs, steps=2000, K=100, subset=4, lr=0.01):
     return res
 
 
+def zlayer_experiment(mask):
+    """Sec. IV.B's diffusion comparison on the 512^3 volume: DOM on layers 0-1,
+    1.76 h of diffusion, explicit 0.1 s steps vs implicit 30 s steps, the DOM
+    mass per z-layer."""
+    import numpy as np
+    from paper_2406_04177_amd import diffusion_experiment as de
+    from paper_2406_04177_amd.graph import Graph
+    g = Graph.from_masks(mask)
+    ms_e, (sim_e, nsteps) = timed(lambda: de.run_explicit(mask, g, dt=0.1, precision="f32"))
+    pe = de.layer_profile(sim_e, mask)
+    del sim_e
+    ms_i, (sim_i, its) = timed(lambda: de.run_implicit(mask, g, dt=30.0, precision="f32", rtol=1e-10))
+    pi = de.layer_profile(sim_i, mask)
+    del sim_i
+    res = {"workload": "512^3, M0 = %.4f mg on layers 0-1, D = 100950 voxel^2/day, %.0f s" % (de.M0, de.T_END),
+           "explicit": {"dt_s": 0.1, "steps": nsteps, "ms": ms_e, "mass_rel_err": float(abs(pe.sum() / de.M0 - 1))},
+           "implicit": {"dt_s": 30.0, "steps": len(its), "cg_iterations": int(sum(its)), "ms": ms_i,
+                        "mass_rel_err": float(abs(pi.sum() / de.M0 - 1))},
+           "profile_max_abs_diff_rel_to_peak": float(np.abs(pe - pi).max() / pe.max()),
+           "profile_layers_0_4_explicit": [float(v) for v in pe[:5]],
+           "profile_layers_0_4_implicit": [float(v) for v in pi[:5]],
+           "layer_of_half_mass_explicit": int(np.searchsorted(np.cumsum(pe), de.M0 / 2)),
+           "layer_of_half_mass_implicit": int(np.searchsorted(np.cumsum(pi), de.M0 / 2))}
+    log("z-layer experiment: explicit %d steps %.1f s, implicit %d steps (%d CG iterations) %.1f s; "
+        "profiles differ by %.2e of the peak" % (nsteps, ms_e / 1e3, len(its), sum(its), ms_i / 1e3,
+                                                  res["profile_max_abs_diff_rel_to_peak"]))
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -254,6 +283,7 @@ def main(argv=None):
     ap.add_argument("--acc-steps", type=int, default=10000, help="steps of the 256^3 FP32-vs-FP64 row")
     ap.add_argument("--grad-steps", type=int, default=2000, help="steps of the 16 x 128^3 gradient row")
     ap.add_argument("--fit-epochs", type=int, default=30, help="epochs of the 16 x 128^3 fitting row (0: skip)")
+    ap.add_argument("--zlayer", type=int, default=1, help="run the 512^3 z-layer diffusion comparison (0: skip)")
     ap.add_argument("--kernel", choices=("auto", "table", "rank", "offset", "relative"), default="auto",
                     help="neighbour source of the explicit-step kernel")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -353,6 +383,25 @@ def main(argv=None):
                 "achieved_GBs_own": OWN_BYTES[other] * n / (mso / (K // 2) / 1e3) / 1e9}
             log("explicit FP32, %s kernel: %.4f ms/step" % (KERNEL_NAMES[other], mso / (K // 2)))
         sim.set_kernel(kernel)
+        # Algorithm 2 (sequential transformation) and unequal steps (the
+        # paper's test 3 ratio: transformation 4.3x the diffusion step)
+        sim2 = Simulation(g, params.replace(sequential=True), precision="f32", implicit=False, adjoint=False)
+        sim2.set_fields(x0)
+        sim2.step(20, dt)
+        ms2, _ = timed(lambda: sim2.step(K // 2, dt))
+        sim2.set_params(params)
+        sim2.set_fields(x0)
+        nt = max(K // 8, 10)
+        sim2.step_subcycled(5, 4.3 * dt, dt)
+        mss, _ = timed(lambda: sim2.step_subcycled(nt, 4.3 * dt, dt))
+        ndiff = int(np.ceil(nt * 4.3 - 1e-9))
+        rows["f2_algorithm2_and_subcycling"] = {
+            "algorithm2_ms_per_step": ms2 / (K // 2),
+            "subcycled": {"transformation_steps": nt, "dt_t_over_dt_d": 4.3, "diffusion_steps": ndiff,
+                          "ms_total": mss, "ms_per_diffusion_step": mss / ndiff}}
+        log("Algorithm 2: %.4f ms/step; sub-cycled (dt_t = 4.3 dt_d): %.4f ms per diffusion step"
+            % (ms2 / (K // 2), mss / ndiff))
+        del sim2
         # plain FP64 step on the same input
         sim64 = Simulation(g, params, precision="f64", implicit=True, adjoint=False)
         sim64.set_fields(x0.double())
@@ -408,6 +457,8 @@ def main(argv=None):
         log("adjoint/forward ratio %.2f (record %.2f ms, adjoint %.2f ms, forward %.2f ms); "
             "static-pool D gradients skipped: adjoint %.2f ms, ratio %.2f"
             % ((msr + msa) / msf, msr, msa, msf, msa_s, (msr + msa_s) / msf))
+        if args.zlayer:
+            rows["f3_zlayer_diffusion"] = zlayer_experiment(mask)
         rows["a6_gradient_16x128"] = gradient_batch(args.grad_steps)
         if args.fit_epochs > 0:
             rows["f1_fit_16x128"] = fit_batch(args.fit_epochs, steps=args.grad_steps)

@@ -131,6 +131,16 @@ int vg_lookup(const void *rank_d, int nx, int ny, int nz, int brick, const int64
 int vg_region_codes(const int32_t *vox_d, int64_t n, int nx, int ny, int nz, unsigned periodic,
                     uint16_t *codes_d, void *stream);
 
+/* Sums of x_d[0..n) over contiguous ranges: out_d[r] = sum of x_d[i] for
+ * offsets_d[r] <= i < offsets_d[r+1] (r < nranges), FP64, in a fixed order.
+ * x_d is float or double (precision VG_F32 / VG_F64), e.g. one pool of the
+ * fields; offsets_d holds nranges + 1 int64 on the device (clamped into
+ * [0, n]; an empty or inverted range sums to 0).  In raster order every
+ * z-layer of a volume is one range, so this gives the mass profile per layer
+ * of the diffusion comparison of Sec. IV.B. */
+int vg_range_sums(const void *x_d, int precision, int64_t n, const int64_t *offsets_d, int64_t nranges,
+                  double *out_d, void *stream);
+
 /* ---- simulation handle ------------------------------------------------- */
 typedef struct vg_sim vg_sim;
 

@@ -24,7 +24,7 @@ VG_KERNEL_AUTO, VG_KERNEL_TABLE, VG_KERNEL_RANK, VG_KERNEL_OFFSET, VG_KERNEL_REL
 VG_ADJ_SKIP_STATIC_D = 1
 
 EXPORTS = ("vg_strerror", "vg_last_error", "vg_version", "vg_rank_bytes", "vg_count_pores",
-           "vg_build_graph", "vg_lookup", "vg_region_codes", "vg_create", "vg_destroy",
+           "vg_build_graph", "vg_lookup", "vg_region_codes", "vg_range_sums", "vg_create", "vg_destroy",
            "vg_set_kernel", "vg_get_kernel", "vg_set_adjoint_options", "vg_set_params", "vg_set_regions", "vg_alt_elems", "vg_workspace_bytes", "vg_init_state",
            "vg_step_explicit", "vg_step_subcycled", "vg_solve_implicit_step", "vg_mass_totals", "vg_record", "vg_adjoint",
            "vg_seed_lambda")
@@ -76,6 +76,7 @@ def load():
             "vg_build_graph": (I, [P, I, I, I, I, U, ctypes.c_int32, I64, I64, P, P, P]),
             "vg_lookup": (I, [P, I, I, I, I, P, I64, ctypes.c_int32, P, P]),
             "vg_region_codes": (I, [P, I64, I, I, I, U, P, P]),
+            "vg_range_sums": (I, [P, I, I64, P, I64, P, P]),
             "vg_create": (I, [ctypes.POINTER(VgDesc), ctypes.POINTER(P)]),
             "vg_destroy": (I, [P]),
             "vg_set_kernel": (I, [P, I]),

@@ -113,3 +113,27 @@ class Graph:
                     raise ValueError("initial mass on a solid voxel")
                 x[s, pos] = torch.as_tensor(np.asarray(val, np.float64), device=x.device).to(dtype)
         return x
+
+
+def layer_offsets(mask: np.ndarray) -> np.ndarray:
+    """[nz + 1] start of every z-layer in the raster-ordered compacted list of
+    one volume (its pore voxels in layers < z), from the mask."""
+    counts = (np.asarray(mask).reshape(mask.shape[0], -1) != 0).sum(axis=1)
+    return np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+
+
+def range_sums(x: torch.Tensor, offsets: torch.Tensor) -> torch.Tensor:
+    """FP64 sums of a 1-D float/double CUDA tensor over contiguous ranges
+    (``offsets``: int64 CUDA tensor of nranges + 1 starts), by vg_range_sums."""
+    L = _lib.load()
+    if x.dim() != 1 or x.dtype not in (torch.float32, torch.float64) or offsets.dtype != torch.int64:
+        raise ValueError("x must be 1-D float32/float64, offsets int64")
+    x = x.contiguous()
+    offsets = offsets.contiguous()
+    nr = offsets.numel() - 1
+    out = torch.empty(max(nr, 0), dtype=torch.float64, device=x.device)
+    prec = _lib.VG_F64 if x.dtype == torch.float64 else _lib.VG_F32
+    _lib.check(L.vg_range_sums(x.data_ptr(), prec, x.numel(), offsets.data_ptr(), max(nr, 0),
+                               out.data_ptr() if nr > 0 else None, _lib.stream_ptr(None)), "vg_range_sums")
+    return out
+

@@ -188,3 +188,11 @@ def test_workspace_counts_geometry_words_of_the_rank_index():
         sizes.append(ws.value)
         L.vg_destroy(h)
     assert sizes[1] - sizes[0] >= 4 * n
+
+
+def test_range_sums_validation():
+    L = _lib.load()
+    assert L.vg_range_sums(None, 0, 10, None, 0, None, None) == 0            # nothing to do
+    assert L.vg_range_sums(None, 0, -1, None, 0, None, None) == _lib.VG_EINVAL
+    assert L.vg_range_sums(None, 7, 10, None, 0, None, None) == _lib.VG_EINVAL  # precision
+    assert L.vg_range_sums(None, 0, 10, None, 3, None, None) == _lib.VG_EINVAL  # null pointers
