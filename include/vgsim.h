@@ -141,6 +141,47 @@ int vg_region_codes(const int32_t *vox_d, int64_t n, int nx, int ny, int nz, uns
 int vg_range_sums(const void *x_d, int precision, int64_t n, const int64_t *offsets_d, int64_t nranges,
                   double *out_d, void *stream);
 
+/* ---- pore-network (PNGM) objectives on a brick partition (Sec. V) -------
+ * The primitives are the bricks of side b of the image; a primitive holds the
+ * pore voxels of its brick (v_i of them), two primitives are adjacent when a
+ * pore-voxel face joins them, with contact surface S_ij = the number of such
+ * faces and d_ij = the distance between their centres of gravity (the
+ * paper's primitives are maximal balls; its starting conductances are
+ * S_ij / d_ij, Sec. V.B). */
+
+/* Per brick k (raster order of bricks, nbx = ceil(nx / b) ...):
+ * sums_d[k][0..3] = pore voxels, sums of their x, y, z; contact_d[k][a] =
+ * pore-voxel faces shared with brick k + 1 along axis a (x, y, z).  vox_d /
+ * nbr_d as from vg_build_graph (any enumeration, no periodic axis).  Both
+ * outputs are cleared first (uint32 [nb][3], uint64 [nb][4]). */
+int vg_brick_stats(const int32_t *vox_d, const int32_t *nbr_d, int64_t n, int nx, int ny, int nz, int b,
+                   uint32_t *contact_d, unsigned long long *sums_d, void *stream);
+
+/* Objective 1 (objective = 1: residual of the explicit scheme 3,
+ * r_i = y_i - x_i + c sum_j theta_ij (x_i/v_i - x_j/v_j)) or objective 2 (the
+ * implicit scheme 4, r_i = x_i - y_i - c sum_j theta_ij (y_i/v_i - y_j/v_j)),
+ * L = mean over data pairs and primitives of r_i^2, c = D dt (voxel units),
+ * over l data pairs X_d, Y_d ([l][q] FP64 primitive masses at t and t + dt).
+ * Adjacency as CSR: row_d [q+1] int64, col_d [E] int32, theta_d [E] FP64 (one
+ * parameter per ordered pair, in row i only).  Writes loss_d[0], grad_d [E]
+ * (dL/dtheta) and rowloss_d [q] (each row's share, summed in a fixed order).
+ * The inner term is x_j / v_j and dL2/dtheta has the minus sign of the
+ * residual's derivative (the printed formulas slip on both). */
+int vg_pngm_loss_grad(const double *X_d, const double *Y_d, int64_t l, int64_t q, const double *v_d,
+                      const int64_t *row_d, const int32_t *col_d, const double *theta_d, double c, int objective,
+                      double *rowloss_d, double *loss_d, double *grad_d, void *stream);
+
+/* One explicit PNGM step (scheme 3): out_i = m_i - c sum_j theta_ij
+ * (m_i/v_i - m_j/v_j); out_d must not alias m_d. */
+int vg_pngm_step(const double *m_d, double *out_d, int64_t q, const double *v_d, const int64_t *row_d,
+                 const int32_t *col_d, const double *theta_d, double c, void *stream);
+
+/* The normalised-gradient step of Sec. V.A on count parameters:
+ * theta_e <- clamp(theta_e - lr * scale_e * sign(grad_e), lo_e, hi_e), no move
+ * for a zero derivative (FP64 device arrays). */
+int vg_sign_update(double *theta_d, const double *grad_d, int64_t count, double lr, const double *scale_d,
+                   const double *lo_d, const double *hi_d, void *stream);
+
 /* ---- simulation handle ------------------------------------------------- */
 typedef struct vg_sim vg_sim;
 

@@ -24,7 +24,8 @@ VG_KERNEL_AUTO, VG_KERNEL_TABLE, VG_KERNEL_RANK, VG_KERNEL_OFFSET, VG_KERNEL_REL
 VG_ADJ_SKIP_STATIC_D = 1
 
 EXPORTS = ("vg_strerror", "vg_last_error", "vg_version", "vg_rank_bytes", "vg_count_pores",
-           "vg_build_graph", "vg_lookup", "vg_region_codes", "vg_range_sums", "vg_create", "vg_destroy",
+           "vg_build_graph", "vg_lookup", "vg_region_codes", "vg_range_sums",
+           "vg_brick_stats", "vg_pngm_loss_grad", "vg_pngm_step", "vg_sign_update", "vg_create", "vg_destroy",
            "vg_set_kernel", "vg_get_kernel", "vg_set_adjoint_options", "vg_set_params", "vg_set_regions", "vg_alt_elems", "vg_workspace_bytes", "vg_init_state",
            "vg_step_explicit", "vg_step_subcycled", "vg_solve_implicit_step", "vg_mass_totals", "vg_record", "vg_adjoint",
            "vg_seed_lambda")
@@ -77,6 +78,10 @@ def load():
             "vg_lookup": (I, [P, I, I, I, I, P, I64, ctypes.c_int32, P, P]),
             "vg_region_codes": (I, [P, I64, I, I, I, U, P, P]),
             "vg_range_sums": (I, [P, I, I64, P, I64, P, P]),
+            "vg_brick_stats": (I, [P, P, I64, I, I, I, I, P, P, P]),
+            "vg_pngm_loss_grad": (I, [P, P, I64, I64, P, P, P, P, D, I, P, P, P, P]),
+            "vg_pngm_step": (I, [P, P, I64, P, P, P, P, D, P]),
+            "vg_sign_update": (I, [P, P, I64, D, P, P, P, P]),
             "vg_create": (I, [ctypes.POINTER(VgDesc), ctypes.POINTER(P)]),
             "vg_destroy": (I, [P]),
             "vg_set_kernel": (I, [P, I]),

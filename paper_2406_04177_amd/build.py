@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvgsim.so")
-SOURCES = ["vg_graph.hip", "vg_step.hip", "vg_cg.hip", "vg_adjoint.hip", "vg_reduce.hip", "vg_api.cpp"]
+SOURCES = ["vg_graph.hip", "vg_step.hip", "vg_cg.hip", "vg_adjoint.hip", "vg_reduce.hip", "vg_pngm.hip", "vg_api.cpp"]
 HEADERS = ["vg_internal.h"]
 
 

@@ -1,0 +1,212 @@
+// Pore-network (PNGM) objectives of Sec. V on a coarse partition of the
+// voxel graph: the primitives are the bricks of side b (pore voxels of one
+// brick), adjacent when a pore-voxel face joins them.
+//
+//   k_brick_stats    per brick: pore voxels, coordinate sums (centres of
+//                    gravity) and pore-voxel faces shared with the next
+//                    brick along +x, +y, +z (contact surface S)
+//   k_pngm_loss_grad objective L1 (explicit scheme 3 residual) or L2
+//                    (implicit scheme 4 residual) over data pairs of
+//                    primitive masses, and its gradient per directed edge
+//   k_pngm_step      one explicit PNGM step (scheme 3)
+//   k_sign_update    the normalised-gradient update of Sec. V.A
+//
+// Inner term x_j / v_j (the printed x_i / v_j is read as a slip); theta is
+// one parameter per ordered pair; dL2/dtheta carries the minus sign of
+// d r2 / d theta, which the printed formula drops.
+#include <cmath>
+
+#include "vg_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace vg {
+namespace {
+
+inline unsigned blocks_for(int64_t work) { return (unsigned)((work + kBlock - 1) / kBlock); }
+
+__global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *__restrict__ p, int64_t cnt) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < cnt) p[i] = 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_u64(unsigned long long *__restrict__ p, int64_t cnt) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < cnt) p[i] = 0ull;
+}
+
+struct BrickGeom {
+    int nx, ny, nz, b, nbx, nby, nbz;
+};
+
+__device__ __forceinline__ int64_t brick_of(const BrickGeom &G, int x, int y, int z) {
+    return ((int64_t)(z / G.b) * G.nby + y / G.b) * G.nbx + x / G.b;
+}
+
+// Integer sums (atomic adds of integers are exact and order-free, so the
+// result is deterministic).
+__global__ __launch_bounds__(kBlock) void k_brick_stats(const int32_t *__restrict__ vox,
+                                                        const int32_t *__restrict__ nbr, int64_t n, BrickGeom G,
+                                                        uint32_t *__restrict__ contact,
+                                                        unsigned long long *__restrict__ sums) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int64_t p = vox[i];
+    const int x = (int)(p % G.nx), y = (int)((p / G.nx) % G.ny), z = (int)(p / ((int64_t)G.nx * G.ny));
+    const int64_t k = brick_of(G, x, y, z);
+    atomicAdd(&sums[k * 4 + 0], 1ull);
+    atomicAdd(&sums[k * 4 + 1], (unsigned long long)x);
+    atomicAdd(&sums[k * 4 + 2], (unsigned long long)y);
+    atomicAdd(&sums[k * 4 + 3], (unsigned long long)z);
+    // +x, +y, +z slots: a face shared with the next brick along that axis
+    const int axis_coord[3] = {x, y, z};
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const int32_t j = nbr[(int64_t)(2 * a + 1) * n + i];
+        if (j >= 0 && (axis_coord[a] + 1) % G.b == 0) atomicAdd(&contact[k * 3 + a], 1u);
+    }
+}
+
+// One thread per primitive row i: for every data pair p the residual of row
+// i, then the gradient terms of the row's edges (each edge belongs to one
+// row, so no two threads write the same entry) and the row's share of the
+// loss.
+__global__ __launch_bounds__(kBlock) void k_pngm_loss_grad(const double *__restrict__ X, const double *__restrict__ Y,
+                                                           int64_t l, int64_t q, const double *__restrict__ v,
+                                                           const int64_t *__restrict__ row,
+                                                           const int32_t *__restrict__ col,
+                                                           const double *__restrict__ theta, double c, int objective,
+                                                           double *__restrict__ rowloss, double *__restrict__ grad) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= q) return;
+    const int64_t e0 = row[i], e1 = row[i + 1];
+    const double inv = 1.0 / (double)(l * q);
+    for (int64_t e = e0; e < e1; e++) grad[e] = 0.0;
+    double acc = 0.0;
+    for (int64_t p = 0; p < l; p++) {
+        const double *x = X + p * q, *y = Y + p * q;
+        const double *zz = objective == 1 ? x : y;       // the concentrations of the flux term
+        const double si = zz[i] / v[i];
+        double s = 0.0;
+        for (int64_t e = e0; e < e1; e++) {
+            const int32_t j = col[e];
+            s += theta[e] * (si - zz[j] / v[j]);
+        }
+        const double r = objective == 1 ? y[i] - x[i] + c * s : x[i] - y[i] - c * s;
+        for (int64_t e = e0; e < e1; e++) {
+            const int32_t j = col[e];
+            const double t = 2.0 * inv * r * c * (si - zz[j] / v[j]);
+            grad[e] = objective == 1 ? grad[e] + t : grad[e] - t;
+        }
+        acc += r * r * inv;
+    }
+    rowloss[i] = acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_rows(const double *__restrict__ rowloss, int64_t q,
+                                                     double *__restrict__ out) {
+    __shared__ double lds[kWaves];
+    double v[1] = {0.0};
+    for (int64_t i = threadIdx.x; i < q; i += kBlock) v[0] += rowloss[i];
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) out[0] = v[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_pngm_step(const double *__restrict__ m, double *__restrict__ out,
+                                                      int64_t q, const double *__restrict__ v,
+                                                      const int64_t *__restrict__ row,
+                                                      const int32_t *__restrict__ col,
+                                                      const double *__restrict__ theta, double c) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= q) return;
+    const double si = m[i] / v[i];
+    double s = 0.0;
+    for (int64_t e = row[i]; e < row[i + 1]; e++) {
+        const int32_t j = col[e];
+        s += theta[e] * (si - m[j] / v[j]);
+    }
+    out[i] = m[i] - c * s;
+}
+
+// theta_e <- clamp(theta_e - lr * scale_e * sign(g_e), lo_e, hi_e); a zero
+// derivative gives no move.
+__global__ __launch_bounds__(kBlock) void k_sign_update(double *__restrict__ theta, const double *__restrict__ g,
+                                                        int64_t cnt, double lr, const double *__restrict__ scale,
+                                                        const double *__restrict__ lo,
+                                                        const double *__restrict__ hi) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= cnt) return;
+    double t = theta[e];
+    if (g[e] > 0.0) t -= lr * scale[e];
+    else if (g[e] < 0.0) t += lr * scale[e];
+    t = t < lo[e] ? lo[e] : t;
+    t = t > hi[e] ? hi[e] : t;
+    theta[e] = t;
+}
+
+}  // namespace
+}  // namespace vg
+
+using namespace vg;
+
+extern "C" int vg_brick_stats(const int32_t *vox_d, const int32_t *nbr_d, int64_t n, int nx, int ny, int nz, int b,
+                              uint32_t *contact_d, unsigned long long *sums_d, void *stream) {
+    if (n < 0 || nx <= 0 || ny <= 0 || nz <= 0 || b <= 0 || !contact_d || !sums_d || (n > 0 && (!vox_d || !nbr_d))) {
+        set_error("bad brick-statistics arguments");
+        return VG_EINVAL;
+    }
+    BrickGeom G{nx, ny, nz, b, (nx + b - 1) / b, (ny + b - 1) / b, (nz + b - 1) / b};
+    const int64_t nb = (int64_t)G.nbx * G.nby * G.nbz;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(nb * 3)), dim3(kBlock), 0, s, contact_d, nb * 3);
+    int rc = launch_status("k_fill_u32");
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(nb * 4)), dim3(kBlock), 0, s, sums_d, nb * 4);
+    if ((rc = launch_status("k_fill_u64"))) return rc;
+    if (n == 0) return VG_OK;
+    hipLaunchKernelGGL(k_brick_stats, dim3(blocks_for(n)), dim3(kBlock), 0, s, vox_d, nbr_d, n, G, contact_d, sums_d);
+    return launch_status("k_brick_stats");
+}
+
+extern "C" int vg_pngm_loss_grad(const double *X_d, const double *Y_d, int64_t l, int64_t q, const double *v_d,
+                                 const int64_t *row_d, const int32_t *col_d, const double *theta_d, double c,
+                                 int objective, double *rowloss_d, double *loss_d, double *grad_d, void *stream) {
+    if (l <= 0 || q <= 0 || (objective != 1 && objective != 2) || !std::isfinite(c) || !X_d || !Y_d || !v_d ||
+        !row_d || !col_d || !theta_d || !rowloss_d || !loss_d || !grad_d) {
+        set_error("bad PNGM objective arguments");
+        return VG_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_pngm_loss_grad, dim3(blocks_for(q)), dim3(kBlock), 0, s, X_d, Y_d, l, q, v_d, row_d, col_d,
+                       theta_d, c, objective, rowloss_d, grad_d);
+    int rc = launch_status("k_pngm_loss_grad");
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(kBlock), 0, s, rowloss_d, q, loss_d);
+    return launch_status("k_sum_rows");
+}
+
+extern "C" int vg_pngm_step(const double *m_d, double *out_d, int64_t q, const double *v_d, const int64_t *row_d,
+                            const int32_t *col_d, const double *theta_d, double c, void *stream) {
+    if (q < 0 || !std::isfinite(c) || (q > 0 && (!m_d || !out_d || !v_d || !row_d || !col_d || !theta_d)) ||
+        (q > 0 && m_d == out_d)) {
+        set_error("bad PNGM step arguments");
+        return VG_EINVAL;
+    }
+    if (q == 0) return VG_OK;
+    hipLaunchKernelGGL(k_pngm_step, dim3(blocks_for(q)), dim3(kBlock), 0, (hipStream_t)stream, m_d, out_d, q, v_d,
+                       row_d, col_d, theta_d, c);
+    return launch_status("k_pngm_step");
+}
+
+extern "C" int vg_sign_update(double *theta_d, const double *grad_d, int64_t count, double lr, const double *scale_d,
+                              const double *lo_d, const double *hi_d, void *stream) {
+    if (count < 0 || !(lr >= 0) || !std::isfinite(lr) ||
+        (count > 0 && (!theta_d || !grad_d || !scale_d || !lo_d || !hi_d))) {
+        set_error("bad sign-update arguments");
+        return VG_EINVAL;
+    }
+    if (count == 0) return VG_OK;
+    hipLaunchKernelGGL(k_sign_update, dim3(blocks_for(count)), dim3(kBlock), 0, (hipStream_t)stream, theta_d, grad_d,
+                       count, lr, scale_d, lo_d, hi_d);
+    return launch_status("k_sign_update");
+}

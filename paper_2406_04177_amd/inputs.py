@@ -198,3 +198,16 @@ def epoch_subsets(nvol: int, size: int, epochs: int, seed: int = 0) -> list:
     per epoch, sorted, from default_rng(seed)."""
     rng = np.random.default_rng(seed)
     return [np.sort(rng.choice(nvol, size=size, replace=False)) for _ in range(epochs)]
+
+
+def init_scenario(mask: np.ndarray, seed: int, frac: float = 0.01, mass_range=(0.5, 1.5)) -> dict:
+    """A random DOM distribution for the pore-network data (Sec. V.B): a total
+    mass M0 ~ U(mass_range) spread over round(frac * n) random pore voxels with
+    U(0, 1) weights (``default_rng(seed + 11)``)."""
+    lin = np.flatnonzero(mask.ravel())
+    rng = np.random.default_rng(seed + 11)
+    k = max(1, min(int(round(frac * lin.size)), lin.size))
+    idx = np.sort(rng.choice(lin.size, size=k, replace=False))
+    w = rng.random(k)
+    m0 = rng.uniform(*mass_range)
+    return {DOM: (lin[idx], m0 * w / w.sum())}
