@@ -271,6 +271,81 @@ def zlayer_experiment(mask):
     return res
 
 
+def pngm_row(mask, b=16, scenarios=8, records=30, every_s=10.0, epochs=1000):
+    """Sec. V on the 512^3 volume: primitives = bricks of side b; data pairs =
+    primitive masses of voxel-method diffusion runs (D = 100950 voxel^2/day,
+    explicit 0.1 s steps) recorded every 10 s from random DOM scenarios;
+    objective L2, normalised-gradient SGD for `epochs` epochs of 4 pairs (lr 0.1
+    halved every 10 epochs) from theta = S / d; then the explicit pore-network
+    scheme with 0.1 s steps and the implicit one with 10 s steps from a held-out
+    scenario, against the voxel method (mean relative L2 error of the primitive
+    masses over the 10 s records), and objective 2 on the held-out pairs."""
+    import numpy as np
+    import torch
+    from paper_2406_04177_amd import pngm
+    from paper_2406_04177_amd.graph import Graph
+    ms_setup, (g, part) = timed(lambda: (lambda gg: (gg, pngm.partition(gg, b)))(Graph.from_masks(mask, brick=b)))
+    scen = list(range(scenarios))
+    ms_data, data = timed(lambda: pngm.generate(g, part, mask, scen + [1000], records, every_s))
+    train, held = data[:-1], data[-1]
+    X = train[:, :-1].reshape(-1, part.q)
+    Y = train[:, 1:].reshape(-1, part.q)
+    c = 100950.0 / 86400.0 * every_s
+    ms_fit, (theta, losses) = timed(lambda: pngm.fit(part, X, Y, c, epochs, batch=4, objective=2))
+    theta0 = torch.as_tensor(part.S / part.d, dtype=torch.float64, device=X.device)
+
+    # the networks run from a held-out scenario: scheme 3 at the voxel method's
+    # 0.1 s step and scheme 4 at the data spacing (the scheme objective 2
+    # encodes), from t = 0 and from t = 30 s (after the sub-brick transient)
+    c_sub = 100950.0 / 86400.0 * 0.1
+    nsub = int(round(every_s / 0.1))
+    work = torch.empty(3 * part.q + 2, dtype=torch.float64, device=X.device)
+    sweeps = []
+
+    def rollout(th, scheme, start):
+        m = held[start].clone()
+        errs = []
+        for r in range(start, records):
+            if scheme == 3:
+                for _ in range(nsub):
+                    m = pngm.step(part, m, th, c_sub)
+            else:
+                m, it, _ = pngm.implicit_step(part, m, th, c, rtol=1e-12, work=work)
+                sweeps.append(it)
+            errs.append(float(torch.linalg.norm(m - held[r + 1]) / torch.linalg.norm(held[r + 1])))
+        return float(np.mean(errs))
+    err = {}
+    for scheme in (3, 4):
+        for start in (0, 3):
+            for name, th in (("start", theta0), ("fitted", theta)):
+                err["scheme%d_from_%ds_%s_theta" % (scheme, int(start * every_s), name)] = rollout(th, scheme, start)
+    ms_r4, _ = timed(lambda: rollout(theta, 4, 0))
+    # objective 2 on the held-out pairs, one pair at a time
+    per0 = np.array([float(pngm.loss_grad(part, held[r:r + 1], held[r + 1:r + 2], theta0, c, 2)[0])
+                     for r in range(records)])
+    per1 = np.array([float(pngm.loss_grad(part, held[r:r + 1], held[r + 1:r + 2], theta, c, 2)[0])
+                     for r in range(records)])
+    full0 = float(pngm.loss_grad(part, X, Y, theta0, c, 2)[0])
+    full1 = float(pngm.loss_grad(part, X, Y, theta, c, 2)[0])
+    ratio = (theta / theta0).cpu().numpy()
+    res = {"workload": "512^3 in %d^3 bricks (q = %d primitives, %d directed edges), %d scenarios x %d pairs "
+                       "10 s apart, 1 held-out scenario" % (b, part.q, int(part.col.numel()), scenarios, records),
+           "ms_partition": ms_setup, "ms_data": ms_data, "ms_fit": ms_fit, "epochs": epochs,
+           "L2_train_start": full0, "L2_train_end": full1,
+           "L2_heldout_start": float(per0.mean()), "L2_heldout_end": float(per1.mean()),
+           "L2_heldout_pair_ratio_median": float(np.median(per1 / per0)),
+           "theta_over_theta0_percentiles_10_50_90": np.percentile(ratio, [10, 50, 90]).tolist(),
+           "rollout_mean_rel_err": err, "scheme4_sweeps_max": int(max(sweeps)),
+           "ms_scheme4_step": ms_r4 / records}
+    log("PNGM (q = %d): data %.1f s, fit %d epochs %.2f s; L2 train %.3e -> %.3e, held-out %.3e -> %.3e (median pair "
+        "ratio %.3f); mean held-out error from 30 s, scheme 3 at 0.1 s %.3f -> %.3f, scheme 4 at 10 s %.3f -> %.3f "
+        "(%.2f ms/step)" % (part.q, ms_data / 1e3, epochs, ms_fit / 1e3, full0, full1, per0.mean(), per1.mean(),
+                            np.median(per1 / per0), err["scheme3_from_30s_start_theta"],
+                            err["scheme3_from_30s_fitted_theta"], err["scheme4_from_30s_start_theta"],
+                            err["scheme4_from_30s_fitted_theta"], ms_r4 / records))
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -284,6 +359,7 @@ def main(argv=None):
     ap.add_argument("--grad-steps", type=int, default=2000, help="steps of the 16 x 128^3 gradient row")
     ap.add_argument("--fit-epochs", type=int, default=30, help="epochs of the 16 x 128^3 fitting row (0: skip)")
     ap.add_argument("--zlayer", type=int, default=1, help="run the 512^3 z-layer diffusion comparison (0: skip)")
+    ap.add_argument("--pngm", type=int, default=1, help="run the 512^3 pore-network fitting row (0: skip)")
     ap.add_argument("--kernel", choices=("auto", "table", "rank", "offset", "relative"), default="auto",
                     help="neighbour source of the explicit-step kernel")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -459,6 +535,8 @@ def main(argv=None):
             % ((msr + msa) / msf, msr, msa, msf, msa_s, (msr + msa_s) / msf))
         if args.zlayer:
             rows["f3_zlayer_diffusion"] = zlayer_experiment(mask)
+        if args.pngm:
+            rows["f4_pngm_512"] = pngm_row(mask)
         rows["a6_gradient_16x128"] = gradient_batch(args.grad_steps)
         if args.fit_epochs > 0:
             rows["f1_fit_16x128"] = fit_batch(args.fit_epochs, steps=args.grad_steps)

@@ -176,6 +176,19 @@ int vg_pngm_loss_grad(const double *X_d, const double *Y_d, int64_t l, int64_t q
 int vg_pngm_step(const double *m_d, double *out_d, int64_t q, const double *v_d, const int64_t *row_d,
                  const int32_t *col_d, const double *theta_d, double c, void *stream);
 
+/* One implicit PNGM step (scheme 4, Sec. V.A): out_d = the masses y solving
+ * y_i + c sum_j theta_ij (y_i/v_i - y_j/v_j) = m_i.  Solved by Jacobi sweeps
+ * on the concentrations y/v (each row is strictly diagonally dominant since
+ * v_i > 0, so the sweeps converge), starting from m/v, until the residual
+ * ||m - A y||_2 <= rtol ||m||_2 (checked every 8 sweeps, one host sync each).
+ * work_d: caller-owned FP64 scratch of 3 q + 2 entries.  iters_out /
+ * relres_out (host): sweeps taken and the result's relative residual.
+ * Returns VG_ENOCONV when max_iter sweeps end above rtol (out_d then holds
+ * the last checked iterate).  out_d must not alias m_d or work_d. */
+int vg_pngm_implicit_step(const double *m_d, double *out_d, int64_t q, const double *v_d, const int64_t *row_d,
+                          const int32_t *col_d, const double *theta_d, double c, double rtol, int max_iter,
+                          double *work_d, int *iters_out, double *relres_out, void *stream);
+
 /* The normalised-gradient step of Sec. V.A on count parameters:
  * theta_e <- clamp(theta_e - lr * scale_e * sign(grad_e), lo_e, hi_e), no move
  * for a zero derivative (FP64 device arrays). */

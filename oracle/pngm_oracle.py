@@ -24,6 +24,8 @@ parameter per ordered pair, as the paper's derivative treats it (it appears
 in row i only); the derivative of L2 carries a minus sign, which the printed
 formula drops (d r2_i / d theta_ij = -c (y_i/v_i - y_j/v_j)).
 Scheme 3 (explicit PNGM step): m_i <- m_i - c sum_j theta_ij (m_i/v_i - m_j/v_j).
+Scheme 4 (implicit PNGM step): the new masses y solve
+y_i + c sum_j theta_ij (y_i/v_i - y_j/v_j) = m_i (a dense solve here).
 """
 from __future__ import annotations
 
@@ -111,3 +113,16 @@ def loss_grad(part, X: np.ndarray, Y: np.ndarray, theta: np.ndarray, c: float, o
                     grad[e] -= 2.0 / (l * q) * r * c * (y[i] / v[i] - y[col[e]] / v[col[e]])
             loss += r * r / (l * q)
     return loss, grad
+
+
+def scheme4_step(part, m: np.ndarray, theta: np.ndarray, c: float) -> np.ndarray:
+    """One implicit PNGM step (scheme 4): the matrix of the linear system is
+    written out densely and solved (small partitions only)."""
+    v, row, col, q = part["v"], part["row"], part["col"], part["q"]
+    A = np.eye(q)
+    for i in range(q):
+        for e in range(row[i], row[i + 1]):
+            j = col[e]
+            A[i, i] += c * theta[e] / v[i]
+            A[i, j] -= c * theta[e] / v[j]
+    return np.linalg.solve(A, m)

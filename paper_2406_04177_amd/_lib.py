@@ -25,7 +25,7 @@ VG_ADJ_SKIP_STATIC_D = 1
 
 EXPORTS = ("vg_strerror", "vg_last_error", "vg_version", "vg_rank_bytes", "vg_count_pores",
            "vg_build_graph", "vg_lookup", "vg_region_codes", "vg_range_sums",
-           "vg_brick_stats", "vg_pngm_loss_grad", "vg_pngm_step", "vg_sign_update", "vg_create", "vg_destroy",
+           "vg_brick_stats", "vg_pngm_loss_grad", "vg_pngm_step", "vg_pngm_implicit_step", "vg_sign_update", "vg_create", "vg_destroy",
            "vg_set_kernel", "vg_get_kernel", "vg_set_adjoint_options", "vg_set_params", "vg_set_regions", "vg_alt_elems", "vg_workspace_bytes", "vg_init_state",
            "vg_step_explicit", "vg_step_subcycled", "vg_solve_implicit_step", "vg_mass_totals", "vg_record", "vg_adjoint",
            "vg_seed_lambda")
@@ -81,6 +81,7 @@ def load():
             "vg_brick_stats": (I, [P, P, I64, I, I, I, I, P, P, P]),
             "vg_pngm_loss_grad": (I, [P, P, I64, I64, P, P, P, P, D, I, P, P, P, P]),
             "vg_pngm_step": (I, [P, P, I64, P, P, P, P, D, P]),
+            "vg_pngm_implicit_step": (I, [P, P, I64, P, P, P, P, D, D, I, P, P, P, P]),
             "vg_sign_update": (I, [P, P, I64, D, P, P, P, P]),
             "vg_create": (I, [ctypes.POINTER(VgDesc), ctypes.POINTER(P)]),
             "vg_destroy": (I, [P]),

@@ -9,6 +9,8 @@
 //                    (implicit scheme 4 residual) over data pairs of
 //                    primitive masses, and its gradient per directed edge
 //   k_pngm_step      one explicit PNGM step (scheme 3)
+//   k_pngm_jacobi    one Jacobi sweep of the implicit PNGM step (scheme 4)
+//                    on the concentrations, with the row residuals
 //   k_sign_update    the normalised-gradient update of Sec. V.A
 //
 // Inner term x_j / v_j (the printed x_i / v_j is read as a slip); theta is
@@ -128,6 +130,45 @@ __global__ __launch_bounds__(kBlock) void k_pngm_step(const double *__restrict__
     out[i] = m[i] - c * s;
 }
 
+// Scheme 4 in concentrations s = m / v: (v_i + c sum_e theta_e) s_i -
+// c sum_e theta_e s_j = m_i.  Every row is strictly diagonally dominant
+// (v_i >= 1), so Jacobi converges.  One sweep writes s_out from s_in and the
+// squared residual of s_in per row (mass units) into rowres.
+__global__ __launch_bounds__(kBlock) void k_pngm_jacobi(const double *__restrict__ m,
+                                                        const double *__restrict__ s_in,
+                                                        double *__restrict__ s_out, int64_t q,
+                                                        const double *__restrict__ v,
+                                                        const int64_t *__restrict__ row,
+                                                        const int32_t *__restrict__ col,
+                                                        const double *__restrict__ theta, double c,
+                                                        double *__restrict__ rowres) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= q) return;
+    double sum_t = 0.0, sum_ts = 0.0;
+    for (int64_t e = row[i]; e < row[i + 1]; e++) {
+        sum_t += theta[e];
+        sum_ts += theta[e] * s_in[col[e]];
+    }
+    const double diag = v[i] + c * sum_t;
+    const double r = m[i] - (diag * s_in[i] - c * sum_ts);
+    s_out[i] = (m[i] + c * sum_ts) / diag;
+    rowres[i] = r * r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pngm_conc(const double *__restrict__ m, const double *__restrict__ v,
+                                                      double *__restrict__ s, double *__restrict__ msq, int64_t q) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= q) return;
+    s[i] = m[i] / v[i];
+    msq[i] = m[i] * m[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_pngm_mass(const double *__restrict__ s, const double *__restrict__ v,
+                                                      double *__restrict__ out, int64_t q) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < q) out[i] = s[i] * v[i];
+}
+
 // theta_e <- clamp(theta_e - lr * scale_e * sign(g_e), lo_e, hi_e); a zero
 // derivative gives no move.
 __global__ __launch_bounds__(kBlock) void k_sign_update(double *__restrict__ theta, const double *__restrict__ g,
@@ -196,6 +237,73 @@ extern "C" int vg_pngm_step(const double *m_d, double *out_d, int64_t q, const d
     hipLaunchKernelGGL(k_pngm_step, dim3(blocks_for(q)), dim3(kBlock), 0, (hipStream_t)stream, m_d, out_d, q, v_d,
                        row_d, col_d, theta_d, c);
     return launch_status("k_pngm_step");
+}
+
+extern "C" int vg_pngm_implicit_step(const double *m_d, double *out_d, int64_t q, const double *v_d,
+                                     const int64_t *row_d, const int32_t *col_d, const double *theta_d, double c,
+                                     double rtol, int max_iter, double *work_d, int *iters_out, double *relres_out,
+                                     void *stream) {
+    if (q < 0 || !std::isfinite(c) || c < 0 || !(rtol > 0) || max_iter < 1 || !iters_out || !relres_out ||
+        (q > 0 && (!m_d || !out_d || !v_d || !row_d || !col_d || !theta_d || !work_d || out_d == m_d ||
+                   (out_d < work_d + 3 * q + 2 && work_d < out_d + q)))) {
+        set_error("bad PNGM implicit-step arguments");
+        return VG_EINVAL;
+    }
+    *iters_out = 0;
+    *relres_out = 0.0;
+    if (q == 0) return VG_OK;
+    hipStream_t s = (hipStream_t)stream;
+    double *sa = work_d, *sb = work_d + q, *rowres = work_d + 2 * q, *scal = work_d + 3 * q;
+    const unsigned nb = blocks_for(q);
+    hipLaunchKernelGGL(k_pngm_conc, dim3(nb), dim3(kBlock), 0, s, m_d, v_d, sa, rowres, q);
+    int rc = launch_status("k_pngm_conc");
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(kBlock), 0, s, rowres, q, scal + 1);
+    if ((rc = launch_status("k_sum_rows"))) return rc;
+    double host[2] = {0.0, 0.0};
+    if (hipMemcpyAsync(&host[1], scal + 1, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        set_error("PNGM implicit step: reading the right-hand side norm failed");
+        return VG_EHIP;
+    }
+    const double bnorm = std::sqrt(host[1]);
+    if (bnorm == 0.0) {
+        hipLaunchKernelGGL(k_pngm_mass, dim3(nb), dim3(kBlock), 0, s, sa, v_d, out_d, q);
+        return launch_status("k_pngm_mass");
+    }
+    // sweeps in groups of 8; the residual read after a group is that of the
+    // last sweep's input (sb after the swap), and that input is the result,
+    // so the reported residual is the result's own
+    int it = 0;
+    double rel = INFINITY;
+    while (it < max_iter) {
+        for (int k = 0; k < 8 && it < max_iter; k++, it++) {
+            hipLaunchKernelGGL(k_pngm_jacobi, dim3(nb), dim3(kBlock), 0, s, m_d, sa, sb, q, v_d, row_d, col_d,
+                               theta_d, c, rowres);
+            if ((rc = launch_status("k_pngm_jacobi"))) return rc;
+            double *t = sa;
+            sa = sb;
+            sb = t;
+        }
+        hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(kBlock), 0, s, rowres, q, scal);
+        if ((rc = launch_status("k_sum_rows"))) return rc;
+        if (hipMemcpyAsync(&host[0], scal, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            set_error("PNGM implicit step: reading the residual failed");
+            return VG_EHIP;
+        }
+        rel = std::sqrt(host[0]) / bnorm;
+        if (rel <= rtol) break;
+    }
+    hipLaunchKernelGGL(k_pngm_mass, dim3(nb), dim3(kBlock), 0, s, sb, v_d, out_d, q);
+    if ((rc = launch_status("k_pngm_mass"))) return rc;
+    *iters_out = it;
+    *relres_out = rel;
+    if (!(rel <= rtol)) {
+        set_error("PNGM implicit step did not reach rtol within max_iter sweeps");
+        return VG_ENOCONV;
+    }
+    return VG_OK;
 }
 
 extern "C" int vg_sign_update(double *theta_d, const double *grad_d, int64_t count, double lr, const double *scale_d,

@@ -109,6 +109,22 @@ def step(part: Partition, m: torch.Tensor, theta: torch.Tensor, c: float) -> tor
     return out
 
 
+def implicit_step(part: Partition, m: torch.Tensor, theta: torch.Tensor, c: float, rtol: float = 1e-12,
+                  max_iter: int = 20000, work: torch.Tensor = None):
+    """One implicit PNGM step (scheme 4); returns (masses, sweeps, relative residual)."""
+    L = _lib.load()
+    out = torch.empty_like(m)
+    if work is None:
+        work = torch.empty(3 * part.q + 2, dtype=torch.float64, device=m.device)
+    it = ctypes.c_int(0)
+    rel = ctypes.c_double(0.0)
+    _lib.check(L.vg_pngm_implicit_step(m.data_ptr(), out.data_ptr(), part.q, part.v.data_ptr(), part.row.data_ptr(),
+                                       part.col.data_ptr(), theta.data_ptr(), float(c), float(rtol), int(max_iter),
+                                       work.data_ptr(), ctypes.byref(it), ctypes.byref(rel), _lib.stream_ptr(None)),
+               "vg_pngm_implicit_step")
+    return out, it.value, rel.value
+
+
 def sign_update(theta, grad, lr, scale, lo, hi):
     L = _lib.load()
     _lib.check(L.vg_sign_update(theta.data_ptr(), grad.data_ptr(), theta.numel(), float(lr), scale.data_ptr(),

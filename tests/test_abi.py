@@ -196,3 +196,30 @@ def test_range_sums_validation():
     assert L.vg_range_sums(None, 0, -1, None, 0, None, None) == _lib.VG_EINVAL
     assert L.vg_range_sums(None, 7, 10, None, 0, None, None) == _lib.VG_EINVAL  # precision
     assert L.vg_range_sums(None, 0, 10, None, 3, None, None) == _lib.VG_EINVAL  # null pointers
+
+
+def test_pngm_entry_points_validate_before_device_work():
+    import ctypes
+    L = _lib.load()
+    E = _lib.VG_EINVAL
+    assert L.vg_brick_stats(None, None, 10, 8, 8, 8, 4, None, None, None) == E
+    assert L.vg_brick_stats(None, None, 0, 8, 8, 0, 4, None, None, None) == E
+    assert L.vg_pngm_loss_grad(None, None, 1, 1, None, None, None, None, 1.0, 1, None, None, None, None) == E
+    assert L.vg_pngm_step(None, None, -1, None, None, None, None, 1.0, None) == E
+    assert L.vg_pngm_step(None, None, 0, None, None, None, None, 1.0, None) == 0
+    assert L.vg_sign_update(None, None, 0, -0.1, None, None, None, None) == E
+    it, rel = ctypes.c_int(-1), ctypes.c_double(-1.0)
+    ok = dict(iters_out=ctypes.byref(it), relres_out=ctypes.byref(rel))
+
+    def implicit(q, m, out, c, rtol, max_iter, work, iters_out=ok["iters_out"], relres_out=ok["relres_out"]):
+        one = 0x1000                      # never dereferenced: every call below is rejected or has q = 0
+        return L.vg_pngm_implicit_step(m, out, q, one, one, one, one, c, rtol, max_iter, work, iters_out,
+                                       relres_out, None)
+    assert implicit(0, None, None, 1.0, 1e-10, 10, None) == 0 and it.value == 0 and rel.value == 0.0
+    assert implicit(4, 0x2000, 0x2000, 1.0, 1e-10, 10, 0x9000) == E             # out aliases m
+    assert implicit(4, 0x2000, 0x9008, 1.0, 1e-10, 10, 0x9000) == E             # out inside the work area
+    assert implicit(4, 0x2000, 0x3000, 1.0, 0.0, 10, 0x9000) == E               # rtol
+    assert implicit(4, 0x2000, 0x3000, 1.0, 1e-10, 0, 0x9000) == E              # max_iter
+    assert implicit(4, 0x2000, 0x3000, -1.0, 1e-10, 10, 0x9000) == E            # c < 0
+    assert implicit(4, 0x2000, 0x3000, 1.0, 1e-10, 10, None) == E               # no work area
+    assert implicit(4, 0x2000, 0x3000, 1.0, 1e-10, 10, 0x9000, iters_out=None) == E

@@ -116,3 +116,30 @@ def test_data_and_fit_follow_the_oracle(vol):
         expect = np.clip(hist[e] - rate * t0 * np.sign(go), 0.05 * t0, 20.0 * t0)
         np.testing.assert_allclose(hist[e + 1][robust], expect[robust], rtol=1e-14)
     assert losses[-5:].mean() < losses[:5].mean()
+
+
+def test_implicit_step_equals_dense_solve(vol):
+    """Scheme 4 by Jacobi sweeps on the GPU against the oracle's dense solve,
+    at c = D * 10 s (the data spacing) with perturbed, non-symmetric theta;
+    the reported residual is the result's own; a sweep cap below what is
+    needed is reported as VG_ENOCONV."""
+    from paper_2406_04177_amd import _lib, pngm
+    mask, g, part, ref = vol
+    rng = np.random.default_rng(5)
+    m = rng.random(ref["q"]) * ref["v"]
+    theta = (ref["S"] / ref["d"]) * (1 + 0.3 * rng.random(ref["S"].size))
+    c = 100950.0 / 86400.0 * 10.0
+    expect = po.scheme4_step(ref, m, theta, c)
+    dev = "cuda"
+    th = torch.as_tensor(theta, device=dev)
+    y, it, rel = pngm.implicit_step(part, torch.as_tensor(m, device=dev), th, c, rtol=1e-13)
+    assert rel <= 1e-13 and it > 0
+    y = y.cpu().numpy()
+    np.testing.assert_allclose(y, expect, rtol=0, atol=1e-10 * np.abs(expect).max())
+    # the residual of the definition, in mass units, from the oracle's side
+    A_y = y + c * np.array([sum(theta[e] * (y[i] / ref["v"][i] - y[ref["col"][e]] / ref["v"][ref["col"][e]])
+                                for e in range(ref["row"][i], ref["row"][i + 1])) for i in range(ref["q"])])
+    assert np.linalg.norm(A_y - m) <= 2e-13 * np.linalg.norm(m)
+    with pytest.raises(_lib.VgError) as err:
+        pngm.implicit_step(part, torch.as_tensor(m, device=dev), th, c, rtol=1e-13, max_iter=3)
+    assert err.value.code == _lib.VG_ENOCONV

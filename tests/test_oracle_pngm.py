@@ -1,7 +1,8 @@
 """Pins of the PNGM oracle (oracle/pngm_oracle.py): the partition against a
-voxel-by-voxel construction, scheme 3's conservation and fixed points, the
-objectives' gradients against central differences and autograd, and zero
-loss on data the network itself generated."""
+voxel-by-voxel construction, scheme 3's and scheme 4's conservation and
+fixed points, the two-primitive closed forms of both schemes, the objectives'
+gradients against central differences and autograd, and zero loss on data
+the network itself generated."""
 import numpy as np
 import pytest
 import torch
@@ -106,3 +107,40 @@ def test_zero_loss_on_data_of_the_network_itself():
     X2 = np.stack([2 * y - po.scheme3_step(part, y, theta, c) for y in Y2])
     l2, _ = po.loss_grad(part, X2, Y2, theta, c, 2)
     assert l2 <= 1e-28 * np.mean(X ** 2)
+
+
+def test_scheme4_two_primitives_closed_form():
+    """Two primitives joined by theta both ways: the concentration difference
+    is divided by 1 + c theta (1/v1 + 1/v2) per implicit step (the explicit
+    step multiplies it by 1 - c theta (1/v1 + 1/v2)); total mass is kept."""
+    mask = np.zeros((1, 1, 6), np.uint8)
+    mask[0, 0, 1:5] = 1                       # bricks of 3: voxels {1,2} and {3,4}
+    part = po.partition(mask, 3)
+    assert part["q"] == 2 and list(part["v"]) == [2.0, 2.0] and list(part["S"]) == [1.0, 1.0]
+    theta = np.array([0.7, 0.7])
+    c = 1.3
+    m = np.array([3.0, 1.0])
+    ds = m[0] / 2 - m[1] / 2
+    k = c * 0.7 * (1 / 2 + 1 / 2)
+    y = po.scheme4_step(part, m, theta, c)
+    np.testing.assert_allclose(y[0] / 2 - y[1] / 2, ds / (1 + k), rtol=1e-14)
+    np.testing.assert_allclose(y.sum(), m.sum(), rtol=1e-15)
+    y3 = po.scheme3_step(part, m, theta, c)
+    np.testing.assert_allclose(y3[0] / 2 - y3[1] / 2, ds * (1 - k), rtol=1e-14)
+
+
+def test_scheme4_conserves_keeps_uniform_and_zeroes_L2():
+    part, theta, X = setup()
+    c = 0.8
+    y = po.scheme4_step(part, X[0], theta, c)
+    np.testing.assert_allclose(y.sum(), X[0].sum(), rtol=1e-13)        # theta symmetric
+    uni = 1.5 * part["v"]
+    np.testing.assert_allclose(po.scheme4_step(part, uni, theta, c), uni, rtol=1e-13)
+    # data the implicit network generated leaves objective 2 at zero (up to the solve's rounding)
+    Y = np.stack([po.scheme4_step(part, x, theta, c) for x in X])
+    l2, _ = po.loss_grad(part, X, Y, theta, c, 2)
+    assert l2 <= 1e-26 * np.mean(X ** 2)
+    # for small c the implicit and explicit steps agree to O(c^2)
+    e1 = np.abs(po.scheme4_step(part, X[0], theta, 1e-3) - po.scheme3_step(part, X[0], theta, 1e-3)).max()
+    e2 = np.abs(po.scheme4_step(part, X[0], theta, 5e-4) - po.scheme3_step(part, X[0], theta, 5e-4)).max()
+    assert 3.5 < e1 / e2 < 4.5
