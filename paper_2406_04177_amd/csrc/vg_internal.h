@@ -106,10 +106,73 @@ __device__ inline int64_t xcd_tile(int64_t b, int64_t nb) {
 }
 
 // ---------------------------------------------------------------- reductions
+// A double moved across lanes by a DPP control (the two 32-bit halves in
+// turn).  Only controls whose source lane lies in the same 16-lane row are
+// used, so every lane has a source.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes of a wave, the same value in every lane, in a fixed
+// order: within each 16-lane row pairs (lane ^ 1), then pairs of pairs
+// (lane ^ 2), then the row's quads by rotations of 4 and 8 lanes (DPP: no
+// LDS traffic), then the four row sums read from lanes 0, 16, 32, 48 and
+// added as (r0 + r1) + (r2 + r3).
 __device__ inline double wave_sum(double v) {
+    v += dpp_move<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_move<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_move<0x124>(v);   // row_ror:4
+    v += dpp_move<0x128>(v);   // row_ror:8
+    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
+
+// Per-tile sums of M doubles written straight to out[0..M-1] in a fixed
+// order: each 16-lane row is reduced by DPP (the first four steps of
+// wave_sum), one lane per row stores the row sums in LDS, and thread m < M
+// adds the block's kRows row sums of value m pairwise.  `lds` must hold
+// kRows * M doubles; it may be reused after the call.
+constexpr int kRows = kWaves * 4;
+
+template <int M>
+__device__ inline void tile_sum_to(double (&v)[M], double *lds, double *__restrict__ out) {
+    const int lane = threadIdx.x & 63, row = threadIdx.x >> 4;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    for (int m = 0; m < M; m++) {
+        double x = v[m];
+        x += dpp_move<0xB1>(x);
+        x += dpp_move<0x4E>(x);
+        x += dpp_move<0x124>(x);
+        x += dpp_move<0x128>(x);
+        v[m] = x;
+    }
+    if ((lane & 15) == 0) {
+#pragma unroll
+        for (int m = 0; m < M; m++) lds[row * M + m] = v[m];
+    }
+    __syncthreads();
+    if (threadIdx.x < M) {
+        const int m = threadIdx.x;
+        double r[kRows];
+#pragma unroll
+        for (int k = 0; k < kRows; k++) r[k] = lds[k * M + m];
+#pragma unroll
+        for (int w = 1; w < kRows; w <<= 1)
+#pragma unroll
+            for (int k = 0; k + w < kRows; k += 2 * w) r[k] += r[k + w];
+        out[m] = r[0];
+    }
+    __syncthreads();
 }
 
 // Sums M doubles over the block in a fixed order; the result is valid in

@@ -313,7 +313,8 @@ __device__ __forceinline__ void finish(const StepBufs<R> &B, const Coef<R> &C, c
 }
 
 // Per-piece sums of the thread's accumulators (a piece is the part of a tile
-// inside one segment), written to part[piece][pool] in a fixed order.
+// inside one segment), written to part[piece][pool] in a fixed order; `lds`
+// holds kRows * 5 doubles.
 __device__ __forceinline__ void tile_totals(const Pieces &pc, int64_t tile, const double (&acc)[kVPT][VG_NPOOL],
                                             double *__restrict__ part, double *lds) {
     const int32_t p0 = pc.piece_first[tile], p1 = pc.piece_first[tile + 1];
@@ -327,17 +328,13 @@ __device__ __forceinline__ void tile_totals(const Pieces &pc, int64_t tile, cons
 #pragma unroll
             for (int s = 0; s < VG_NPOOL; s++) v5[s] += in ? acc[v][s] : 0.0;
         }
-        block_sum<VG_NPOOL>(v5, lds);
-        if (threadIdx.x == 0) {
-#pragma unroll
-            for (int s = 0; s < VG_NPOOL; s++) part[(int64_t)p * VG_NPOOL + s] = v5[s];
-        }
+        tile_sum_to<VG_NPOOL>(v5, lds, part + (int64_t)p * VG_NPOOL);
     }
 }
 
 template <typename R, int MODE, int MOB, bool REG, int TOT>
 __global__ __launch_bounds__(kBlock) void k_step(StepBufs<R> B, Coef<R> C, Pieces pc, double *__restrict__ part) {
-    __shared__ double lds[kWaves * VG_NPOOL];
+    __shared__ double lds[kRows * VG_NPOOL];
     __shared__ R cl[VG_NREG];
     constexpr bool do_d = MODE == MODE_D || MODE == MODE_DT;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -386,7 +383,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepBufs<R> B, Coef<R> C, Piece
 template <typename R, int MODE, int MOB, bool REG, int TOT, bool RELC, bool SEQ>
 __global__ __launch_bounds__(kBlock) void k_step_off(StepBufs<R> B, Coef<R> C, Pieces pc, double *__restrict__ part) {
     static_assert(MODE == MODE_D || MODE == MODE_DT, "diffusing passes only");
-    __shared__ double lds[kWaves * VG_NPOOL];
+    __shared__ double lds[kRows * VG_NPOOL];
     __shared__ R cl[VG_NREG];
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const uint32_t n = (uint32_t)B.n;
@@ -563,7 +560,7 @@ __device__ __forceinline__ void geo_neighbours(const RGeom &G, const R *cl, cons
 template <typename R, int MODE, int MOB, bool REG, int TOT, bool RASTER>
 __global__ __launch_bounds__(kBlock) void k_step_geo(StepBufs<R> B, Coef<R> C, RGeom G,
                                                      const uint32_t *__restrict__ geo, double *__restrict__ part) {
-    __shared__ double lds[kWaves * VG_NPOOL];
+    __shared__ double lds[kRows * VG_NPOOL];
     __shared__ R cl[VG_NREG];
     constexpr bool do_d = MODE == MODE_D || MODE == MODE_DT;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -598,11 +595,7 @@ __global__ __launch_bounds__(kBlock) void k_step_geo(StepBufs<R> B, Coef<R> C, R
         for (int v = 0; v < kVPT; v++)
 #pragma unroll
             for (int s = 0; s < VG_NPOOL; s++) a5[s] += acc[v][s];
-        block_sum<VG_NPOOL>(a5, lds);
-        if (threadIdx.x == 0) {
-#pragma unroll
-            for (int s = 0; s < VG_NPOOL; s++) part[tile * VG_NPOOL + s] = a5[s];
-        }
+        tile_sum_to<VG_NPOOL>(a5, lds, part + tile * VG_NPOOL);
     }
 }
 
