@@ -43,10 +43,17 @@ BYTES_OFFSET_F32 = 5 * 4 + 5 * 4 + 8
 # relative-code kernel: the pools, one 4-byte code word per voxel and 32 B of
 # base distances per 64 voxels
 BYTES_RELATIVE_F32 = 5 * 4 + 5 * 4 + 4 + 32.0 / 64
-KERNEL_NAMES = {1: "table", 2: "rank", 3: "offset", 4: "relative"}
+# band kernel (two fused passes per launch): per voxel and pass pair the
+# first pass reads four pools and the code word of the band and its two
+# neighbour rows (band of 8 rows: 10/8 of the voxels), the second pass reads
+# four pools and the code word again and writes the five pools; per step half
+BYTES_BAND_F32 = (10.0 / 8 * (4 * 4 + 4 + 32.0 / 64) + (4 * 4 + 4 + 32.0 / 64) + 5 * 4) / 2
+KERNEL_NAMES = {1: "table", 2: "rank", 3: "offset", 4: "relative", 5: "band"}
 KERNEL_FUNCS = {1: "k_step (6-slot table)", 2: "k_step_geo (rank index)", 3: "k_step_off (packed offsets)",
-                4: "k_step_off (relative codes)"}
-OWN_BYTES = {1: BYTES_FUSED_F32, 2: BYTES_RANK_F32, 3: BYTES_OFFSET_F32, 4: BYTES_RELATIVE_F32}
+                4: "k_step_off (relative codes)",
+                5: "k_band2 (relative codes, two fused passes per launch, rows of a band marching along z)"}
+OWN_BYTES = {1: BYTES_FUSED_F32, 2: BYTES_RANK_F32, 3: BYTES_OFFSET_F32, 4: BYTES_RELATIVE_F32, 5: BYTES_BAND_F32}
+PASSES_PER_LAUNCH = {1: 1, 2: 1, 3: 1, 4: 1, 5: 2}
 
 # HBM bytes per launch of the headline kernel read from hardware counters
 # (FETCH_SIZE x 2 + WRITE_SIZE, the factors of a plain 1 GiB device copy on the
@@ -55,11 +62,11 @@ OWN_BYTES = {1: BYTES_FUSED_F32, 2: BYTES_RANK_F32, 3: BYTES_OFFSET_F32, 4: BYTE
 KERNEL_SOURCES = ("paper_2406_04177_amd/csrc/vg_step.hip", "paper_2406_04177_amd/csrc/vg_internal.h",
                   "paper_2406_04177_amd/build.py")
 MEASURED_TRAFFIC = {
-    # (neighbour source, size): (bytes per launch, sha256 of KERNEL_SOURCES);
-    # from profiles/k_step_off_relative_f32_512cube.md: FETCH_SIZE 336662.2 KiB
-    # x 2 + WRITE_SIZE 407846.4 KiB x 1 per launch
-    ("relative", 512): (336662.2 * 1024 * 2 + 407846.4 * 1024,
-                        "ed6ffa10d5d774019e4f132a988c719ff0707f1ae3e2dd49352d7a7d835f8993"),
+    # (kernel, size): (bytes per launch, sha256 of KERNEL_SOURCES); from
+    # profiles/k_band2_f32_512cube.md: FETCH_SIZE 622084.3 KiB x 2 +
+    # WRITE_SIZE 412621.0 KiB x 1 per launch (two fused passes)
+    ("band", 512): (622084.3 * 1024 * 2 + 412621.0 * 1024,
+                    "ebd2bc7f1f0971d78c630d137b86992ed70961ad5d09124d7b71e711181a7c62"),
 }
 
 
@@ -360,7 +367,7 @@ def main(argv=None):
     ap.add_argument("--fit-epochs", type=int, default=30, help="epochs of the 16 x 128^3 fitting row (0: skip)")
     ap.add_argument("--zlayer", type=int, default=1, help="run the 512^3 z-layer diffusion comparison (0: skip)")
     ap.add_argument("--pngm", type=int, default=1, help="run the 512^3 pore-network fitting row (0: skip)")
-    ap.add_argument("--kernel", choices=("auto", "table", "rank", "offset", "relative"), default="auto",
+    ap.add_argument("--kernel", choices=("auto", "table", "rank", "offset", "relative", "band"), default="auto",
                     help="neighbour source of the explicit-step kernel")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="finish with three plain 1 GiB device copies (scale for HBM byte counters)")
@@ -393,7 +400,7 @@ def main(argv=None):
     log("n = %d pore voxels; graph build %.2f ms (incl. mask upload and host sync)" % (n, ms_graph))
 
     sim = Simulation(g, params, precision="f32", implicit=False, adjoint=False)
-    sim.set_kernel({"auto": 0, "table": 1, "rank": 2, "offset": 3, "relative": 4}[args.kernel])
+    sim.set_kernel({"auto": 0, "table": 1, "rank": 2, "offset": 3, "relative": 4, "band": 5}[args.kernel])
     kernel = sim.kernel_in_use()
     x0 = g.fields_from_specs(spec, torch.float32)
     sim.set_fields(x0)
@@ -403,26 +410,29 @@ def main(argv=None):
     ms, _ = timed(lambda: sim.step(K, dt, log_every=100, totals_out=tot_log if K >= 100 else None))
     ms_step = ms / K
     vps = n * K / (ms / 1e3)
-    # the fused kernel's own average launch time: K paper steps launch a
-    # transformation-only pass, K-1 fused passes and a diffusion-only pass, one
-    # step launches the two end passes only; no totals in either
-    ms_k, _ = timed(lambda: sim.step(K, dt))
+    # the dominant kernel's own average launch time: K2 = 4 m + 1 paper steps
+    # launch a transformation-only pass, 4 m fused passes (m runs of four: 2 m
+    # band launches, or 4 m single passes) and a diffusion-only pass, one step
+    # launches the two end passes only; no totals in either
+    ppl = PASSES_PER_LAUNCH[kernel]
+    K2 = (K - 1) // 4 * 4 + 1
+    ms_k, _ = timed(lambda: sim.step(K2, dt))
     ms_1, _ = timed(lambda: sim.step(1, dt))
-    us_launch = (ms_k - ms_1) / (K - 1) * 1e3
+    us_launch = (ms_k - ms_1) / ((K2 - 1) / ppl) * 1e3
     own_bpv = OWN_BYTES[kernel]
     # the roofline counts the method's algorithmic bytes per voxel and step
     # (five pools read and written plus the 6-slot neighbour table, 64 B)
-    # whichever neighbour source the kernel uses; own_bytes_per_voxel is what
-    # the kernel's own neighbour source makes it move
+    # whichever neighbour source the kernel uses, times the passes one launch
+    # applies; own_bytes_per_voxel is what the kernel itself moves per step
     bpv = BYTES_FUSED_F32
-    achieved = bpv * n / (us_launch / 1e6) / 1e9
+    achieved = bpv * ppl * n / (us_launch / 1e6) / 1e9
     kname = KERNEL_FUNCS[kernel]
     traffic = None
     rec = MEASURED_TRAFFIC.get((KERNEL_NAMES[kernel], N))
     if rec is not None and rec[1] == sources_sha():
         traffic = rec[0]
-    log("explicit FP32: %.4f ms/step, %.3e voxel-steps/s; fused kernel %.2f us/launch, %.0f GB/s algorithmic"
-        % (ms_step, vps, us_launch, achieved))
+    log("explicit FP32: %.4f ms/step, %.3e voxel-steps/s; %s kernel %.2f us/launch (%d pass(es)), %.0f GB/s "
+        "algorithmic" % (ms_step, vps, KERNEL_NAMES[kernel], us_launch, ppl, achieved))
     out = {
         "metric": METRIC,
         "value": 5.0 * vps,
@@ -437,9 +447,9 @@ def main(argv=None):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "%s, FP32, DOM-only diffusion (fused transformation + diffusion)" % kname,
                      "neighbour_source": KERNEL_NAMES[kernel],
-                     "launch_us": us_launch, "bytes_per_voxel": bpv, "bytes_per_launch": bpv * n,
-                     "own_bytes_per_voxel": own_bpv,
-                     "own_frac": own_bpv * n / (us_launch / 1e6) / 1e9 / HBM_PEAK_GBS},
+                     "launch_us": us_launch, "passes_per_launch": ppl, "bytes_per_voxel_step": bpv,
+                     "bytes_per_launch": bpv * ppl * n, "own_bytes_per_voxel_step": own_bpv,
+                     "own_frac": own_bpv * ppl * n / (us_launch / 1e6) / 1e9 / HBM_PEAK_GBS},
     }
     del tot_log
 
@@ -447,7 +457,7 @@ def main(argv=None):
         rows = {}
         rows["a1_graph_build_ms"] = ms_graph
         # the other neighbour sources on the same state, for comparison
-        for other in (1, 2, 3, 4):
+        for other in (1, 2, 3, 4, 5):
             if other == kernel:
                 continue
             sim.set_kernel(other)

@@ -206,7 +206,7 @@ typedef struct vg_desc {
     const int32_t *nbr_d;    /* device [6][n] neighbour table                */
     const uint16_t *rcode_d; /* device [n] region codes or NULL (weights 1)  */
     int32_t mobile_all;      /* 0: only DOM may diffuse; 1: any pool may     */
-    int32_t features;        /* bit 0: implicit CG, bit 1: adjoint           */
+    int32_t features;        /* VG_FEAT_CG | VG_FEAT_ADJ | VG_FEAT_BAND      */
     /* Optional, single volume (nseg == 1) only: the rank index built by
      * vg_count_pores for the same mask, shape, brick and periodic flags as
      * nbr_d, and the compacted list vox_d.  With them (and no periodic axis,
@@ -220,8 +220,13 @@ typedef struct vg_desc {
     uint32_t periodic;       /* VG_PERIODIC_* flags the table was built with */
 } vg_desc;
 
-#define VG_FEAT_CG  1
-#define VG_FEAT_ADJ 2
+#define VG_FEAT_CG   1
+#define VG_FEAT_ADJ  2
+/* Two explicit steps per pass (VG_KERNEL_BAND): for a single raster-order
+ * volume with no periodic axis and a rank index (rank_d, vox_d), the
+ * workspace also holds a row index ((nz * ny + 1) int32) and a second set of
+ * the five fields (5 n elements of the field type). */
+#define VG_FEAT_BAND 4
 
 /* Creates a handle (host memory only) and sets default parameters. */
 int vg_create(const vg_desc *desc, vg_sim **out);
@@ -243,6 +248,16 @@ int vg_destroy(vg_sim *h);
 #define VG_KERNEL_RANK     2
 #define VG_KERNEL_OFFSET   3
 #define VG_KERNEL_RELATIVE 4
+/* VG_KERNEL_BAND: RELATIVE codes, and runs of four consecutive fused passes
+ * (steps with no totals logged) as two launches of a kernel that applies two
+ * fused passes (Scheme 1 diffusion, then Algorithm 1, twice) to bands of
+ * rows marching along z: the intermediate DOM of a band, its neighbour rows
+ * and the planes next to it stay in LDS, so a pass pair reads and writes the
+ * fields once.  Needs the workspace of VG_FEAT_BAND and the relative codes;
+ * used while only DOM diffuses, with unit edge weights (no region codes) and
+ * Algorithm 1; other passes run on RELATIVE.  Bit-identical to RELATIVE.
+ * AUTO takes BAND for FP32 fields when it is available. */
+#define VG_KERNEL_BAND     5
 int vg_set_kernel(vg_sim *h, int variant);
 int vg_get_kernel(const vg_sim *h, int *variant_in_use);
 /* Sets the model parameters (validated: h > 0, K_DOM > 0, rates >= 0,

@@ -18,9 +18,9 @@ VG_OK, VG_EINVAL, VG_EUNSTABLE, VG_ENOCONV, VG_ENONFINITE, VG_EHIP, VG_ESTATE = 
 VG_F32, VG_F64 = 0, 1
 VG_ORDER_TD, VG_ORDER_DT = 0, 1
 VG_FORCE = 1
-VG_FEAT_CG, VG_FEAT_ADJ = 1, 2
+VG_FEAT_CG, VG_FEAT_ADJ, VG_FEAT_BAND = 1, 2, 4
 VG_NPOOL, VG_NREG, VG_NGRAD = 5, 8, 20
-VG_KERNEL_AUTO, VG_KERNEL_TABLE, VG_KERNEL_RANK, VG_KERNEL_OFFSET, VG_KERNEL_RELATIVE = 0, 1, 2, 3, 4
+VG_KERNEL_AUTO, VG_KERNEL_TABLE, VG_KERNEL_RANK, VG_KERNEL_OFFSET, VG_KERNEL_RELATIVE, VG_KERNEL_BAND = 0, 1, 2, 3, 4, 5
 VG_ADJ_SKIP_STATIC_D = 1
 
 EXPORTS = ("vg_strerror", "vg_last_error", "vg_version", "vg_rank_bytes", "vg_count_pores",

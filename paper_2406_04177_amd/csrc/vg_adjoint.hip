@@ -190,7 +190,12 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces 
         lout[s] = A.lout + (int64_t)s * n;
     }
 
-    for (int64_t t = xcd_tile(blockIdx.x, gridDim.x); t < A.ntiles; t += gridDim.x)
+    for (int64_t it = 0;; it++) {
+    const int64_t t = xcd_stride_tile(blockIdx.x, gridDim.x, it, A.ntiles);
+    if (t >= A.ntiles) break;
+    // seeds of this step's totals: uniform when the tile lies in one volume
+    const int32_t pf = pc.piece_first[t], pl = pc.piece_first[t + 1];
+    const double *sd_tile = pl - pf == 1 ? A.seed + (int64_t)pc.piece_seg[pf] * VG_NPOOL : nullptr;
     for (int v = 0; v < kVPT; v++) {
         const int64_t i64 = t * kTile + v * kBlock + threadIdx.x;
         if (i64 >= n) continue;
@@ -302,12 +307,15 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces 
         }
         // adjoint of the transformation half
         transform_rev(C, x, bar, &g[5]);
-        // seeds of this step's totals
-        int32_t p = pc.piece_first[t];
-        while (p + 1 < pc.piece_first[t + 1] && i64 >= pc.piece_lo[p + 1]) p++;
-        const double *sd = A.seed + (int64_t)pc.piece_seg[p] * VG_NPOOL;
+        const double *sd = sd_tile;
+        if (!sd) {
+            int32_t p = pf;
+            while (p + 1 < pl && i64 >= pc.piece_lo[p + 1]) p++;
+            sd = A.seed + (int64_t)pc.piece_seg[p] * VG_NPOOL;
+        }
 #pragma unroll
         for (int s = 0; s < VG_NPOOL; s++) elem(lout[s], i) = (R)((double)bar[s] + sd[s]);
+    }
     }
     block_sum<kG>(g, lds);
     if (threadIdx.x == 0) {
@@ -365,10 +373,16 @@ __global__ __launch_bounds__(kBlock) void k_seed(R *__restrict__ lam, const doub
 template <typename R, int MOB, bool REG, int NS, bool DALL>
 int launch_adj_d(vg_sim *h, bool from_x, const AdjBufs<R> &A, const Coef<R> &C, hipStream_t s) {
     Pieces pc{h->piece_first, h->piece_lo, h->piece_seg, h->npieces};
-    if (from_x) hipLaunchKernelGGL((k_adj<R, MOB, REG, true, NS, DALL>), dim3(h->adj_blocks), dim3(kBlock), 0, s, A,
-                                   C, pc, h->adj_part);
-    else hipLaunchKernelGGL((k_adj<R, MOB, REG, false, NS, DALL>), dim3(h->adj_blocks), dim3(kBlock), 0, s, A, C,
-                            pc, h->adj_part);
+    // the partials buffer holds h->adj_blocks slots; fewer blocks leave zeros
+    if (from_x) {
+        const void *k = (const void *)k_adj<R, MOB, REG, true, NS, DALL>;
+        hipLaunchKernelGGL((k_adj<R, MOB, REG, true, NS, DALL>), dim3(resident_blocks(k, h->adj_blocks)),
+                           dim3(kBlock), 0, s, A, C, pc, h->adj_part);
+    } else {
+        const void *k = (const void *)k_adj<R, MOB, REG, false, NS, DALL>;
+        hipLaunchKernelGGL((k_adj<R, MOB, REG, false, NS, DALL>), dim3(resident_blocks(k, h->adj_blocks)),
+                           dim3(kBlock), 0, s, A, C, pc, h->adj_part);
+    }
     return launch_status("k_adj");
 }
 

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "vg_internal.h"
@@ -27,6 +28,36 @@ int hip_status(hipError_t e, const char *what) {
 }
 
 int launch_status(const char *what) { return hip_status(hipGetLastError(), what); }
+
+int resident_blocks(const void *kernel, int cap) {
+    struct Entry {
+        const void *kernel;
+        int dev, blocks;
+    };
+    static std::mutex mu;
+    static std::vector<Entry> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return cap;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        for (const Entry &e : cache)
+            if (e.kernel == kernel && e.dev == dev) return e.blocks < cap ? e.blocks : cap;
+    }
+    int cus = 0, per = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0) != hipSuccess || cus <= 0 ||
+        per <= 0) {
+        (void)hipGetLastError();
+        return cap;
+    }
+    int g = per * cus;
+    if (g >= kNumXcd) g -= g % kNumXcd;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        cache.push_back({kernel, dev, g});
+    }
+    return g < cap ? g : cap;
+}
 
 namespace {
 
@@ -71,6 +102,10 @@ size_t layout(vg_sim *h, char *base) {
     if (h->features & VG_FEAT_ADJ) {
         h->lam_alt = take(h->elem() * VG_NPOOL * (size_t)h->n);
         h->adj_part = (double *)take(sizeof(double) * VG_NGRAD * (size_t)h->adj_blocks);
+    }
+    if (band_geometry(h)) {
+        h->band_rs = (int32_t *)take(sizeof(int32_t) * ((size_t)h->nz * (size_t)h->ny + 1));
+        h->band_alt = take(h->elem() * VG_NPOOL * (size_t)h->n);
     }
     return off;
 }
@@ -203,7 +238,7 @@ extern "C" int vg_create(const vg_desc *d, vg_sim **out) {
     if (d->seg_off[0] != 0 || d->seg_off[d->nseg] != d->n) { set_error("seg_off must run from 0 to n"); return VG_EINVAL; }
     for (int g = 0; g < d->nseg; g++)
         if (d->seg_off[g + 1] < d->seg_off[g]) { set_error("seg_off must be non-decreasing"); return VG_EINVAL; }
-    if (d->features & ~(VG_FEAT_CG | VG_FEAT_ADJ)) { set_error("unknown feature bits"); return VG_EINVAL; }
+    if (d->features & ~(VG_FEAT_CG | VG_FEAT_ADJ | VG_FEAT_BAND)) { set_error("unknown feature bits"); return VG_EINVAL; }
     vg_sim *h = new (std::nothrow) vg_sim();
     if (!h) { set_error("out of host memory"); return VG_EINVAL; }
     h->n = d->n;
@@ -250,8 +285,9 @@ extern "C" int vg_destroy(vg_sim *h) {
 
 extern "C" int vg_set_kernel(vg_sim *h, int variant) {
     if (!h) { set_error("handle is NULL"); return VG_EINVAL; }
-    if (variant < VG_KERNEL_AUTO || variant > VG_KERNEL_RELATIVE || (variant == VG_KERNEL_RANK && !h->rank) ||
-        (variant == VG_KERNEL_OFFSET && !h->off_ok) || (variant == VG_KERNEL_RELATIVE && !h->rel_ok)) {
+    if (variant < VG_KERNEL_AUTO || variant > VG_KERNEL_BAND || (variant == VG_KERNEL_RANK && !h->rank) ||
+        (variant == VG_KERNEL_OFFSET && !h->off_ok) || (variant == VG_KERNEL_RELATIVE && !h->rel_ok) ||
+        (variant == VG_KERNEL_BAND && !(h->band_ok && h->rel_ok))) {
         set_error("kernel variant %d not available", variant);
         return VG_EINVAL;
     }
@@ -268,7 +304,8 @@ extern "C" int vg_set_adjoint_options(vg_sim *h, unsigned flags) {
 
 extern "C" int vg_get_kernel(const vg_sim *h, int *variant_in_use) {
     if (!h || !variant_in_use) { set_error("null pointer argument"); return VG_EINVAL; }
-    *variant_in_use = vg::use_relative(h) ? VG_KERNEL_RELATIVE
+    *variant_in_use = vg::use_band(h)       ? VG_KERNEL_BAND
+                      : vg::use_relative(h) ? VG_KERNEL_RELATIVE
                       : vg::use_offsets(h) ? VG_KERNEL_OFFSET
                       : vg::use_rank(h)    ? VG_KERNEL_RANK
                                            : VG_KERNEL_TABLE;
@@ -304,6 +341,7 @@ extern "C" int vg_workspace_bytes(const vg_sim *h, size_t *bytes) {
     tmp.ntiles = h->ntiles; tmp.npieces = h->npieces; tmp.cg_blocks = h->cg_blocks; tmp.adj_blocks = h->adj_blocks;
     tmp.nchunks = h->nchunks;
     tmp.rank = h->rank;   // the geometry words are part of the workspace when a rank index is used
+    tmp.vox = h->vox; tmp.nx = h->nx; tmp.ny = h->ny; tmp.nz = h->nz; tmp.brick = h->brick; tmp.periodic = h->periodic;
     *bytes = layout(&tmp, nullptr);
     return VG_OK;
 }
@@ -339,6 +377,7 @@ extern "C" int vg_init_state(vg_sim *h, void *fields_d, void *alt_d, void *work_
                                         hipMemcpyHostToDevice, s), "upload segment chunks"))) return rc;
     if ((rc = launch_geometry(h, s))) return rc;
     if ((rc = build_offsets(h, s))) return rc;
+    if ((rc = build_band(h, s))) return rc;
     // the host tables must outlive the asynchronous copies
     if ((rc = hip_status(hipStreamSynchronize(s), "synchronise"))) return rc;
     h->bound = true;
@@ -365,9 +404,23 @@ extern "C" int vg_step_explicit(vg_sim *h, int64_t nsteps, double dt, int64_t lo
     auto finalize = [&](int64_t j) -> int {
         return launch_totals_finalize(h, totals_log_d + (size_t)(j / log_every - 1) * row, s);
     };
+    // four fused passes j .. j + 3 with no totals logged run as two band
+    // launches when the band kernel applies
+    const bool band = use_band(h);
+    auto quiet4 = [&](int64_t j, int64_t last) {
+        if (!band || j + 3 > last) return false;
+        for (int64_t k = j; k < j + 4; k++)
+            if (logged(k)) return false;
+        return true;
+    };
     if (h->params.step_order == VG_ORDER_TD) {
         if ((rc = launch_pass(h, MODE_T, TOT_NONE, dt, s))) return rc;
         for (int64_t j = 1; j < nsteps; j++) {
+            if (quiet4(j, nsteps - 1)) {
+                if ((rc = launch_band_quad(h, dt, s))) return rc;
+                j += 3;
+                continue;
+            }
             const bool lg = logged(j);
             if ((rc = launch_pass(h, MODE_DT, lg ? TOT_MID : TOT_NONE, dt, s))) return rc;
             if (lg && (rc = finalize(j))) return rc;
@@ -377,6 +430,11 @@ extern "C" int vg_step_explicit(vg_sim *h, int64_t nsteps, double dt, int64_t lo
         if (lg && (rc = finalize(nsteps))) return rc;
     } else {
         for (int64_t j = 1; j <= nsteps; j++) {
+            if (quiet4(j, nsteps)) {
+                if ((rc = launch_band_quad(h, dt, s))) return rc;
+                j += 3;
+                continue;
+            }
             const bool lg = logged(j);
             if ((rc = launch_pass(h, MODE_DT, lg ? TOT_OUT : TOT_NONE, dt, s))) return rc;
             if (lg && (rc = finalize(j))) return rc;

@@ -71,7 +71,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs A, const R *__restric
     if (threadIdx.x < VG_NREG) cl[threadIdx.x] = A.c[threadIdx.x];
     __syncthreads();
     double acc[3] = {0.0, 0.0, 0.0};   // r.z, r.r, b.b
-    for (int64_t t = xcd_tile(blockIdx.x, gridDim.x); t < A.ntiles; t += gridDim.x)
+    for (int64_t it = 0;; it++) {
+    const int64_t t = xcd_stride_tile(blockIdx.x, gridDim.x, it, A.ntiles);
+    if (t >= A.ntiles) break;
     for (int v = 0; v < kVPT; v++) {
         const int64_t i = t * kTile + v * kBlock + threadIdx.x;
         if (i >= A.n) continue;
@@ -102,6 +104,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs A, const R *__restric
         acc[1] += ri * ri;
         acc[2] += b * b;
     }
+    }
     block_sum<3>(acc, lds);
     if (threadIdx.x == 0) {
         for (int q = 0; q < 3; q++) part[(int64_t)blockIdx.x * 4 + q] = acc[q];
@@ -121,7 +124,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(CgArgs A, const double *__re
     __syncthreads();
     const double beta = scal[S_BETA];
     double acc[1] = {0.0};
-    for (int64_t t = xcd_tile(blockIdx.x, gridDim.x); t < A.ntiles; t += gridDim.x)
+    for (int64_t it = 0;; it++) {
+    const int64_t t = xcd_stride_tile(blockIdx.x, gridDim.x, it, A.ntiles);
+    if (t >= A.ntiles) break;
     for (int v = 0; v < kVPT; v++) {
         const int64_t i = t * kTile + v * kBlock + threadIdx.x;
         if (i >= A.n) continue;
@@ -146,6 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(CgArgs A, const double *__re
         q[i] = qi;
         acc[0] += pi * qi;
     }
+    }
     block_sum<1>(acc, lds);
     if (threadIdx.x == 0) part[(int64_t)blockIdx.x * 4] = acc[0];
 }
@@ -159,7 +165,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, int64_t ntiles,
     __shared__ double lds[kWaves * 2];
     const double alpha = scal[S_ALPHA];
     double acc[2] = {0.0, 0.0};
-    for (int64_t t = xcd_tile(blockIdx.x, gridDim.x); t < ntiles; t += gridDim.x)
+    for (int64_t it = 0;; it++) {
+    const int64_t t = xcd_stride_tile(blockIdx.x, gridDim.x, it, ntiles);
+    if (t >= ntiles) break;
     for (int v = 0; v < kVPT; v++) {
         const int64_t i = t * kTile + v * kBlock + threadIdx.x;
         if (i >= n) continue;
@@ -170,6 +178,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, int64_t ntiles,
         z[i] = zi;
         acc[0] += ri * zi;
         acc[1] += ri * ri;
+    }
     }
     block_sum<2>(acc, lds);
     if (threadIdx.x == 0) {

@@ -105,6 +105,41 @@ __device__ inline int64_t xcd_tile(int64_t b, int64_t nb) {
 #endif
 }
 
+// Tile of iteration `it` of block b in a grid-stride kernel of nb blocks.
+// With nb a multiple of 8 the blocks of one XCD (b % 8) walk that XCD's own
+// runs of VG_XCD_RUN consecutive tiles (the runs xcd_tile deals to it), then
+// its contiguous share of the tiles after the last full round of runs, so a
+// grid-stride kernel keeps the locality of the one-tile-per-block kernels;
+// otherwise plain striding.  Returns ntiles once the block's list is done.
+__device__ inline int64_t xcd_stride_tile(int64_t b, int64_t nb, int64_t it, int64_t ntiles) {
+    if (nb % kNumXcd != 0) {
+        const int64_t t = b + it * nb;
+        return t < ntiles ? t : ntiles;
+    }
+    constexpr int64_t S = VG_XCD_RUN, R = S * kNumXcd;
+    const int64_t x = b % kNumXcd, m = it * (nb / kNumXcd) + b / kNumXcd;
+    const int64_t nfull = ntiles / R * R, own_full = nfull / kNumXcd;
+    if (m < own_full) return ((m / S) * kNumXcd + x) * S + m % S;
+    const int64_t u = m - own_full, tail = ntiles - nfull;
+    const int64_t q = tail / kNumXcd, r = tail % kNumXcd;
+    if (u >= q + (x < r ? 1 : 0)) return ntiles;
+    return nfull + x * q + (x < r ? x : r) + u;
+}
+
+// Blocks of kBlock threads of `kernel` that fit on the device at once (so a
+// grid-stride launch has no second, partial round), rounded down to a
+// multiple of the XCD count, at most cap (cached per kernel and device).
+int resident_blocks(const void *kernel, int cap);
+
+// Barrier that orders the block's LDS accesses only: global loads issued
+// before it may still be in flight after it (a full __syncthreads waits for
+// them).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ---------------------------------------------------------------- reductions
 // A double moved across lanes by a DPP control (the two 32-bit halves in
 // turn).  Only controls whose source lane lies in the same 16-lane row are
@@ -437,7 +472,7 @@ struct vg_sim {
     unsigned periodic = 0;
     const int32_t *vox = nullptr;   // compacted list (linear indices)
     uint32_t *geo = nullptr;        // [n] geometry words of the rank-index kernel
-    int kernel = 0;                 // 0 auto, 1 neighbour table, 2 rank index, 3 packed offsets
+    int kernel = 0;                 // VG_KERNEL_*
     // packed neighbour offsets (any volume or batch without periodic wrap)
     uint32_t *off_m = nullptr, *off_p = nullptr;   // [n] each
     uint32_t *off_stat = nullptr;                  // [8] max offset per axis, violation flag, code spans
@@ -448,6 +483,11 @@ struct vg_sim {
     uint32_t *rel_base = nullptr;   // [ceil(n / 64)][8]
     bool rel_ok = false;
     vg::RLayout rel_layout;
+    // two-pass band kernel (single raster volume; see vg_step.hip)
+    int32_t *band_rs = nullptr;     // [nz * ny + 1] compact index of the first voxel of each row
+    char *band_alt = nullptr;       // [5][n] field type: the pass pair's intermediate fields
+    bool band_ok = false;           // built and fits the LDS
+    int band_h = 0, band_z = 0, band_nbands = 0, band_nchunks = 0, band_cap = 0;
     std::vector<int32_t> piece_first_h, piece_seg_h, seg_first_h;
     std::vector<int64_t> piece_lo_h;
     int32_t *piece_first = nullptr, *piece_seg = nullptr, *seg_first = nullptr;
@@ -484,6 +524,10 @@ int launch_geometry(vg_sim *h, hipStream_t s);
 bool use_rank(const vg_sim *h);
 bool use_offsets(const vg_sim *h);
 bool use_relative(const vg_sim *h);
+bool band_geometry(const vg_sim *h);   // the graph and features allow the band kernel
+bool use_band(const vg_sim *h);        // the next pass pairs run on the band kernel
+int build_band(vg_sim *h, hipStream_t s);
+int launch_band_quad(vg_sim *h, double dt, hipStream_t s);
 PackedNbr packed_of(const vg_sim *h);
 int build_offsets(vg_sim *h, hipStream_t s);
 int restore_canonical(vg_sim *h, hipStream_t s);

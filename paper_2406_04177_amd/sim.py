@@ -37,7 +37,8 @@ class Simulation:
 
     def __init__(self, graph: Graph, params: ModelParams, precision: str = "f32",
                  implicit: bool = True, adjoint: bool = False, mobile_all=None,
-                 step_order: int = _lib.VG_ORDER_TD, regions=None, stream=None, rank_neighbours: bool = True):
+                 step_order: int = _lib.VG_ORDER_TD, regions=None, stream=None, rank_neighbours: bool = True,
+                 band: bool = True):
         self.L = _lib.load()
         self.graph = graph
         self.precision = precision
@@ -46,7 +47,8 @@ class Simulation:
         self.stream = stream
         if mobile_all is None:
             mobile_all = any(float(d) != 0.0 for s, d in enumerate(params.D) if s != 1)
-        features = (_lib.VG_FEAT_CG if implicit else 0) | (_lib.VG_FEAT_ADJ if adjoint else 0)
+        features = ((_lib.VG_FEAT_CG if implicit else 0) | (_lib.VG_FEAT_ADJ if adjoint else 0)
+                    | (_lib.VG_FEAT_BAND if band else 0))
         self._seg = np.ascontiguousarray(graph.seg_off, np.int64)
         use_regions = regions is not None or graph.rcode is not None
         if use_regions and graph.rcode is None:
@@ -88,11 +90,12 @@ class Simulation:
         return _lib.stream_ptr(self.stream)
 
     def set_kernel(self, variant: int):
-        """Neighbour source of the explicit step: _lib.VG_KERNEL_AUTO / TABLE / RANK / OFFSET / RELATIVE."""
+        """Neighbour source of the explicit step: _lib.VG_KERNEL_AUTO / TABLE / RANK / OFFSET / RELATIVE /
+        BAND (relative codes, pass pairs in one launch)."""
         _lib.check(self.L.vg_set_kernel(self.h, int(variant)), "vg_set_kernel")
 
     def kernel_in_use(self) -> int:
-        """The neighbour source the next explicit pass uses (TABLE, RANK, OFFSET or RELATIVE)."""
+        """The kernel the next explicit passes use (TABLE, RANK, OFFSET, RELATIVE or BAND)."""
         v = ctypes.c_int(-1)
         _lib.check(self.L.vg_get_kernel(self.h, ctypes.byref(v)), "vg_get_kernel")
         return v.value
