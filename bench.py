@@ -63,10 +63,10 @@ KERNEL_SOURCES = ("paper_2406_04177_amd/csrc/vg_step.hip", "paper_2406_04177_amd
                   "paper_2406_04177_amd/build.py")
 MEASURED_TRAFFIC = {
     # (kernel, size): (bytes per launch, sha256 of KERNEL_SOURCES); from
-    # profiles/k_band2_f32_512cube.md: FETCH_SIZE 622084.3 KiB x 2 +
-    # WRITE_SIZE 412621.0 KiB x 1 per launch (two fused passes)
-    ("band", 512): (622084.3 * 1024 * 2 + 412621.0 * 1024,
-                    "ebd2bc7f1f0971d78c630d137b86992ed70961ad5d09124d7b71e711181a7c62"),
+    # profiles/k_band2_f32_512cube.md: FETCH_SIZE 622031.8 KiB x 2 +
+    # WRITE_SIZE 412612.1 KiB x 1 per launch (two fused passes)
+    ("band", 512): (622031.8 * 1024 * 2 + 412612.1 * 1024,
+                    "e097f8f4588f4a89a3145e6fa328d50e4264721270e06c34b48f58bcc2056198"),
 }
 
 

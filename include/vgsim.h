@@ -256,7 +256,8 @@ int vg_destroy(vg_sim *h);
  * fields once.  Needs the workspace of VG_FEAT_BAND and the relative codes;
  * used while only DOM diffuses, with unit edge weights (no region codes) and
  * Algorithm 1; other passes run on RELATIVE.  Bit-identical to RELATIVE.
- * AUTO takes BAND for FP32 fields when it is available. */
+ * AUTO takes BAND for FP32 fields when it is available and the volume has
+ * enough planes for chunks of at least 20 (about 512^3 and up). */
 #define VG_KERNEL_BAND     5
 int vg_set_kernel(vg_sim *h, int variant);
 int vg_get_kernel(const vg_sim *h, int *variant_in_use);

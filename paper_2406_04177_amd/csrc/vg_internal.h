@@ -487,6 +487,7 @@ struct vg_sim {
     int32_t *band_rs = nullptr;     // [nz * ny + 1] compact index of the first voxel of each row
     char *band_alt = nullptr;       // [5][n] field type: the pass pair's intermediate fields
     bool band_ok = false;           // built and fits the LDS
+    bool band_auto = false;         // chunks long enough for AUTO to take it
     int band_h = 0, band_z = 0, band_nbands = 0, band_nchunks = 0, band_cap = 0;
     std::vector<int32_t> piece_first_h, piece_seg_h, seg_first_h;
     std::vector<int64_t> piece_lo_h;

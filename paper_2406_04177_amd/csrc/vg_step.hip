@@ -1052,11 +1052,12 @@ bool band_geometry(const vg_sim *h) {
            h->periodic == 0 && h->n > 0;
 }
 
-// AUTO takes the band kernel for FP32 fields (in FP64 its LDS budget allows
-// only narrow bands: slower than single passes).
+// AUTO takes the band kernel for FP32 fields when its chunks are long enough
+// (in FP64 its LDS budget allows only narrow bands: slower than single
+// passes).
 bool use_band(const vg_sim *h) {
     return h->band_ok && h->rel_ok &&
-           (h->kernel == VG_KERNEL_BAND || (h->kernel == VG_KERNEL_AUTO && h->prec == VG_F32)) &&
+           (h->kernel == VG_KERNEL_BAND || (h->kernel == VG_KERNEL_AUTO && h->prec == VG_F32 && h->band_auto)) &&
            !h->mobile_all && h->rcode == nullptr && h->params.sequential == 0;
 }
 
@@ -1068,6 +1069,7 @@ bool use_band(const vg_sim *h) {
 // 4 rows 23 % slower, 12 rows 3.5 % faster, 10 and 16 rows no faster.
 int build_band(vg_sim *h, hipStream_t s) {
     h->band_ok = false;
+    h->band_auto = false;
     if (!band_geometry(h) || !h->rel_ok) return VG_OK;
     const int64_t nrows = (int64_t)h->nz * h->ny;
     hipLaunchKernelGGL(k_band_rows, dim3((unsigned)((nrows + 1 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, h->vox,
@@ -1109,9 +1111,14 @@ int build_band(vg_sim *h, hipStream_t s) {
         int chunks = (int)((resident + h->band_nbands / 2) / h->band_nbands);
         if (chunks > (h->nz + 3) / 4) chunks = (h->nz + 3) / 4;
         if (chunks < 1) chunks = 1;
+
         h->band_z = (h->nz + chunks - 1) / chunks;
         h->band_nchunks = (h->nz + h->band_z - 1) / h->band_z;
         h->band_ok = true;
+        // AUTO leaves chunks of fewer than 20 planes to single passes: their
+        // two extra planes and the march's start cost more than the pass
+        // pair saves (256^3: 7-plane chunks, 47 % slower)
+        h->band_auto = h->band_z >= 20;
         return VG_OK;
     }
     return VG_OK;

@@ -76,19 +76,22 @@ def test_band_fp64_equals_oracle():
 
 
 def test_band_use_and_fallbacks():
-    """AUTO picks the band kernel for a single raster volume; regions, other
-    diffusing pools, Algorithm 2, brick order and batches run on the
-    single-pass kernels (with the same results); without the feature the
-    band kernel cannot be chosen."""
+    """AUTO leaves a volume this short in z to single passes; chosen
+    explicitly, the band kernel is used unless regions, other diffusing
+    pools or Algorithm 2 send the passes to the single-pass kernel (with the
+    same results); brick order, batches or a handle without the feature
+    cannot choose it."""
     from paper_2406_04177_amd import _lib
     from paper_2406_04177_amd.graph import Graph
     mask = inputs.synthetic_volume((32, 30, 28), porosity=0.3, seed=6)
     g = Graph.from_masks(mask)
     p = fast_params()
-    assert sim_of(g, p, "f32", 0).kernel_in_use() == BAND
-    assert sim_of(g, p, "f32", 0, regions=[1.0] * 8).kernel_in_use() == RELATIVE
-    assert sim_of(g, fast_params(sequential=True), "f32", 0).kernel_in_use() == RELATIVE
-    assert sim_of(g, fast_params(D=(1e-9, 1e-9, 0, 0, 0)), "f32", 0).kernel_in_use() == RELATIVE
+    assert sim_of(g, p, "f32", 0).kernel_in_use() == RELATIVE
+    assert sim_of(g, p, "f32", BAND).kernel_in_use() == BAND
+    # (region factors attach region codes to the graph: a graph of its own)
+    assert sim_of(Graph.from_masks(mask), p, "f32", BAND, regions=[1.0] * 8).kernel_in_use() == RELATIVE
+    assert sim_of(g, fast_params(sequential=True), "f32", BAND).kernel_in_use() == RELATIVE
+    assert sim_of(g, fast_params(D=(1e-9, 1e-9, 0, 0, 0)), "f32", BAND).kernel_in_use() == RELATIVE
     with pytest.raises(_lib.VgError):
         sim_of(g, p, "f32", BAND, band=False)
     gb = Graph.from_masks(mask, brick=4)
@@ -100,7 +103,8 @@ def test_band_use_and_fallbacks():
     # a band-capable handle whose parameters turn to Algorithm 2 steps on the single-pass kernel
     dt = inputs.explicit_dt(p, 0.9)
     spec = inputs.init_random_all(mask, 6)
-    a = sim_of(g, p, "f64", 0)
+    a = sim_of(g, p, "f64", BAND)
+    assert a.kernel_in_use() == BAND
     a.set_params(fast_params(sequential=True))
     assert a.kernel_in_use() == RELATIVE
     b = sim_of(g, fast_params(sequential=True), "f64", RELATIVE)
@@ -110,9 +114,9 @@ def test_band_use_and_fallbacks():
     assert torch.equal(a.fields, b.fields)
 
 
-def test_band_512_bitwise_and_against_oracle_samples():
-    """The 512^3 workload (20.8 M pore voxels): 9 FP32 steps through the band
-    kernel equal 9 single passes bit for bit."""
+def test_band_512_auto_and_bitwise():
+    """The 512^3 workload (20.8 M pore voxels): AUTO takes the band kernel,
+    and 9 FP32 steps through it equal 9 single passes bit for bit."""
     from paper_2406_04177_amd.graph import Graph
     mask = inputs.synthetic_volume((512, 512, 512), porosity=0.17, seed=0)
     g = Graph.from_masks(mask)
@@ -120,7 +124,8 @@ def test_band_512_bitwise_and_against_oracle_samples():
     dt = inputs.explicit_dt(p)
     spec = inputs.init_uniform(mask, 0)
     x0 = g.fields_from_specs(spec, torch.float64)
-    a = sim_of(g, p, "f32", BAND)
+    a = sim_of(g, p, "f32", 0)
+    assert a.kernel_in_use() == BAND
     a.set_fields(x0)
     a.step(9, dt)
     fa = a.fields.clone()
