@@ -16,6 +16,14 @@
 //   dL/dc_r += a_s u_s,i (lambda_j - lambda_i) (1/2 to each endpoint region),
 //   lambda^k = J_T(x)^T ubar + seed,
 // with FP64 per-thread accumulators reduced per block in a fixed order.
+//
+// CO2 neither diffuses (when only DOM does) nor feeds another pool, so its
+// adjoint is the same at every voxel of a volume whenever it starts so (the
+// seeds of the totals are per volume): then the sweep carries it as one
+// value per volume (CO2U) and reads and writes 8 bytes less per voxel and
+// step; the per-voxel array is filled once at the end.
+#include <vector>
+
 #include "vg_internal.h"
 
 #pragma clang fp contract(off)
@@ -129,6 +137,7 @@ struct AdjBufs {
     const R *lin = nullptr;      // lambda^(k+1)
     R *lout = nullptr;           // lambda^k
     const double *seed = nullptr;   // [nseg][5] for this step
+    const R *co2 = nullptr;      // [nseg] CO2 adjoint lambda^(k+1) per volume (CO2U)
     int64_t n = 0, ntiles = 0;
 };
 
@@ -169,8 +178,9 @@ __device__ __forceinline__ T &elem(T *b, int64_t i) {
 
 // DALL: dL/da_s also for the pools that do not diffuse (their adjoints'
 // neighbour differences are gathered only for that term).
-template <typename R, int MOB, bool REG, bool FROM_X, int NS, bool DALL>
+template <typename R, int MOB, bool REG, bool FROM_X, int NS, bool DALL, bool CO2U>
 __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces pc, double *__restrict__ part) {
+    static_assert(!CO2U || MOB == 1, "a uniform CO2 adjoint needs CO2 not to diffuse");
     using I = typename AdjIndex<NS>::T;
     __shared__ double lds[kWaves * kG];
     __shared__ R cl[VG_NREG];
@@ -195,7 +205,7 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces 
     if (t >= A.ntiles) break;
     // seeds of this step's totals: uniform when the tile lies in one volume
     const int32_t pf = pc.piece_first[t], pl = pc.piece_first[t + 1];
-    const double *sd_tile = pl - pf == 1 ? A.seed + (int64_t)pc.piece_seg[pf] * VG_NPOOL : nullptr;
+    const int32_t seg_tile = pl - pf == 1 ? pc.piece_seg[pf] : -1;
     for (int v = 0; v < kVPT; v++) {
         const int64_t i64 = t * kTile + v * kBlock + threadIdx.x;
         if (i64 >= n) continue;
@@ -216,8 +226,16 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces 
         R x[VG_NPOOL], li[VG_NPOOL];
 #pragma unroll
         for (int s = 0; s < VG_NPOOL; s++) x[s] = elem(st[s], i);
+        // the volume of the voxel (seeds, uniform CO2 adjoint)
+        int32_t seg = seg_tile;
+        if (seg < 0) {
+            int32_t p = pf;
+            while (p + 1 < pl && i64 >= pc.piece_lo[p + 1]) p++;
+            seg = pc.piece_seg[p];
+        }
 #pragma unroll
-        for (int s = 0; s < VG_NPOOL; s++) li[s] = elem(lin[s], i);
+        for (int s = 0; s < VG_NPOOL - 1; s++) li[s] = elem(lin[s], i);
+        li[4] = CO2U ? A.co2[seg] : elem(lin[4], i);
         if constexpr (NS != NS_TABLE) {
             uint32_t jp[6];
             packed_decode<NS == NS_REL>(A.pk, (uint32_t)i, W, jp);
@@ -261,7 +279,8 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces 
         double own_c = 0.0, cross_c[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int s = 0; s < VG_NPOOL; s++) {
-            if (!DALL && !mobile<MOB>(s)) {
+            if ((!DALL && !mobile<MOB>(s)) || (CO2U && s == 4)) {
+                // (a uniform CO2 adjoint has no neighbour differences: its dL/dD term is 0)
                 bar[s] = li[s];
                 continue;
             }
@@ -307,14 +326,10 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces 
         }
         // adjoint of the transformation half
         transform_rev(C, x, bar, &g[5]);
-        const double *sd = sd_tile;
-        if (!sd) {
-            int32_t p = pf;
-            while (p + 1 < pl && i64 >= pc.piece_lo[p + 1]) p++;
-            sd = A.seed + (int64_t)pc.piece_seg[p] * VG_NPOOL;
-        }
+        const double *sd = A.seed + (int64_t)seg * VG_NPOOL;
 #pragma unroll
-        for (int s = 0; s < VG_NPOOL; s++) elem(lout[s], i) = (R)((double)bar[s] + sd[s]);
+        for (int s = 0; s < VG_NPOOL - 1; s++) elem(lout[s], i) = (R)((double)bar[s] + sd[s]);
+        if (!CO2U) elem(lout[4], i) = (R)((double)bar[4] + sd[4]);
     }
     }
     block_sum<kG>(g, lds);
@@ -370,20 +385,75 @@ __global__ __launch_bounds__(kBlock) void k_seed(R *__restrict__ lam, const doub
     }
 }
 
-template <typename R, int MOB, bool REG, int NS, bool DALL>
-int launch_adj_d(vg_sim *h, bool from_x, const AdjBufs<R> &A, const Coef<R> &C, hipStream_t s) {
+// The volume of voxel i from the reduction pieces of its tile.
+__device__ __forceinline__ int32_t seg_of(const Pieces &pc, int64_t i) {
+    const int64_t t = i / kTile;
+    int32_t p = pc.piece_first[t];
+    while (p + 1 < pc.piece_first[t + 1] && i >= pc.piece_lo[p + 1]) p++;
+    return pc.piece_seg[p];
+}
+
+// flag[g] = 1 where the CO2 adjoint differs from the volume's first voxel's
+// (flag cleared before; NaN counts as different).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_co2_check(const R *__restrict__ lam4, int64_t n, Pieces pc,
+                                                      const int32_t *__restrict__ seg_first,
+                                                      int32_t *__restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int32_t g = seg_of(pc, i);
+    const R first = lam4[pc.piece_lo[seg_first[g]]];
+    if (!(lam4[i] == first)) atomicOr(&flag[g], 1);
+}
+
+// co2[g] = the CO2 adjoint of volume g (its first voxel's; 0 for an empty volume).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_co2_init(const R *__restrict__ lam4, int nseg, Pieces pc,
+                                                     const int32_t *__restrict__ seg_first, R *__restrict__ co2) {
+    const int g = (int)(blockIdx.x * kBlock + threadIdx.x);
+    if (g >= nseg) return;
+    const int32_t p = seg_first[g];
+    co2[g] = p < pc.npieces && pc.piece_seg[p] == g ? lam4[pc.piece_lo[p]] : R(0);
+}
+
+// One reverse step of the uniform CO2 adjoint: the same rounding as the
+// per-voxel update, (R)((double)lambda + seed).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_co2_step(R *__restrict__ co2, int nseg, const double *__restrict__ seed) {
+    const int g = (int)(blockIdx.x * kBlock + threadIdx.x);
+    if (g < nseg) co2[g] = (R)((double)co2[g] + seed[(int64_t)g * VG_NPOOL + 4]);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_co2_expand(R *__restrict__ lam4, int64_t n, Pieces pc,
+                                                       const R *__restrict__ co2) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) lam4[i] = co2[seg_of(pc, i)];
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *__restrict__ p, int64_t cnt) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < cnt) p[i] = 0;
+}
+
+template <typename R, int MOB, bool REG, bool FROM_X, int NS, bool DALL, bool CO2U>
+int launch_adj_k(vg_sim *h, const AdjBufs<R> &A, const Coef<R> &C, hipStream_t s) {
     Pieces pc{h->piece_first, h->piece_lo, h->piece_seg, h->npieces};
     // the partials buffer holds h->adj_blocks slots; fewer blocks leave zeros
-    if (from_x) {
-        const void *k = (const void *)k_adj<R, MOB, REG, true, NS, DALL>;
-        hipLaunchKernelGGL((k_adj<R, MOB, REG, true, NS, DALL>), dim3(resident_blocks(k, h->adj_blocks)),
-                           dim3(kBlock), 0, s, A, C, pc, h->adj_part);
-    } else {
-        const void *k = (const void *)k_adj<R, MOB, REG, false, NS, DALL>;
-        hipLaunchKernelGGL((k_adj<R, MOB, REG, false, NS, DALL>), dim3(resident_blocks(k, h->adj_blocks)),
-                           dim3(kBlock), 0, s, A, C, pc, h->adj_part);
-    }
+    const void *k = (const void *)k_adj<R, MOB, REG, FROM_X, NS, DALL, CO2U>;
+    hipLaunchKernelGGL((k_adj<R, MOB, REG, FROM_X, NS, DALL, CO2U>), dim3(resident_blocks(k, h->adj_blocks)),
+                       dim3(kBlock), 0, s, A, C, pc, h->adj_part);
     return launch_status("k_adj");
+}
+
+template <typename R, int MOB, bool REG, int NS, bool DALL>
+int launch_adj_d(vg_sim *h, bool from_x, const AdjBufs<R> &A, const Coef<R> &C, hipStream_t s) {
+    if constexpr (MOB == 1) {
+        if (A.co2) return from_x ? launch_adj_k<R, MOB, REG, true, NS, DALL, true>(h, A, C, s)
+                                 : launch_adj_k<R, MOB, REG, false, NS, DALL, true>(h, A, C, s);
+    }
+    return from_x ? launch_adj_k<R, MOB, REG, true, NS, DALL, false>(h, A, C, s)
+                  : launch_adj_k<R, MOB, REG, false, NS, DALL, false>(h, A, C, s);
 }
 
 template <typename R, int MOB, bool REG, int NS>
@@ -415,6 +485,28 @@ int adjoint_sweep(vg_sim *h, int64_t nsteps, double dt, const void *states, cons
     R *bufs[2] = {(R *)lambda, (R *)h->lam_alt};
     int cur = 0;
     const bool reg = h->rcode != nullptr;
+    Pieces pc{h->piece_first, h->piece_lo, h->piece_seg, h->npieces};
+    const unsigned nb_n = (unsigned)((n + kBlock - 1) / kBlock), nb_g = (unsigned)((h->nseg + kBlock - 1) / kBlock);
+    R *co2 = (R *)h->adj_co2;
+    R *lam4 = (R *)lambda + 4 * n;
+    // a CO2 adjoint uniform over each volume travels as one value per volume
+    bool co2u = false;
+    if (!h->mobile_all && n > 0) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(nb_g), dim3(kBlock), 0, s, h->adj_flag, (int64_t)h->nseg);
+        if ((rc = launch_status("k_fill_i32"))) return rc;
+        hipLaunchKernelGGL(k_co2_check<R>, dim3(nb_n), dim3(kBlock), 0, s, lam4, n, pc, h->seg_first, h->adj_flag);
+        if ((rc = launch_status("k_co2_check"))) return rc;
+        std::vector<int32_t> flag((size_t)h->nseg);
+        if ((rc = hip_status(hipMemcpyAsync(flag.data(), h->adj_flag, sizeof(int32_t) * flag.size(),
+                                            hipMemcpyDeviceToHost, s), "adjoint CO2 check"))) return rc;
+        if ((rc = hip_status(hipStreamSynchronize(s), "adjoint CO2 check"))) return rc;
+        co2u = true;
+        for (int32_t f : flag) co2u = co2u && f == 0;
+        if (co2u) {
+            hipLaunchKernelGGL(k_co2_init<R>, dim3(nb_g), dim3(kBlock), 0, s, lam4, h->nseg, pc, h->seg_first, co2);
+            if ((rc = launch_status("k_co2_init"))) return rc;
+        }
+    }
     for (int64_t jstep = nsteps - 1; jstep >= 0; jstep--) {
         AdjBufs<R> A;
         A.nbr = h->nbr;
@@ -424,17 +516,28 @@ int adjoint_sweep(vg_sim *h, int64_t nsteps, double dt, const void *states, cons
         A.lin = bufs[cur];
         A.lout = bufs[cur ^ 1];
         A.seed = seeds + jstep * (int64_t)h->nseg * VG_NPOOL;
+        A.co2 = co2u ? co2 : nullptr;
         A.n = n;
         A.ntiles = h->ntiles;
         const bool fx = jstep == 0;
         if (h->mobile_all) rc = reg ? launch_adj_step<R, 2, true>(h, fx, A, C, s) : launch_adj_step<R, 2, false>(h, fx, A, C, s);
         else rc = reg ? launch_adj_step<R, 1, true>(h, fx, A, C, s) : launch_adj_step<R, 1, false>(h, fx, A, C, s);
         if (rc) return rc;
+        if (co2u) {
+            hipLaunchKernelGGL(k_co2_step<R>, dim3(nb_g), dim3(kBlock), 0, s, co2, h->nseg, A.seed);
+            if ((rc = launch_status("k_co2_step"))) return rc;
+        }
         cur ^= 1;
     }
     if (cur) {
-        if ((rc = hip_status(hipMemcpyAsync(lambda, h->lam_alt, sizeof(R) * VG_NPOOL * (size_t)n,
+        // (the CO2 rows are filled below in the uniform case)
+        const size_t pools = co2u ? VG_NPOOL - 1 : VG_NPOOL;
+        if ((rc = hip_status(hipMemcpyAsync(lambda, h->lam_alt, sizeof(R) * pools * (size_t)n,
                                             hipMemcpyDeviceToDevice, s), "lambda copy"))) return rc;
+    }
+    if (co2u) {
+        hipLaunchKernelGGL(k_co2_expand<R>, dim3(nb_n), dim3(kBlock), 0, s, lam4, n, pc, (const R *)co2);
+        if ((rc = launch_status("k_co2_expand"))) return rc;
     }
     const double scale_d = dt / (h->params.h * h->params.h);
     // pools whose dL/dD_s the sweep skipped: all but DOM, when asked and not every pool diffuses

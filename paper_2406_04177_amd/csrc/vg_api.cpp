@@ -102,6 +102,8 @@ size_t layout(vg_sim *h, char *base) {
     if (h->features & VG_FEAT_ADJ) {
         h->lam_alt = take(h->elem() * VG_NPOOL * (size_t)h->n);
         h->adj_part = (double *)take(sizeof(double) * VG_NGRAD * (size_t)h->adj_blocks);
+        h->adj_co2 = take(h->elem() * (size_t)h->nseg);
+        h->adj_flag = (int32_t *)take(sizeof(int32_t) * (size_t)h->nseg);
     }
     if (band_geometry(h)) {
         h->band_rs = (int32_t *)take(sizeof(int32_t) * ((size_t)h->nz * (size_t)h->ny + 1));

@@ -252,3 +252,49 @@ def test_skip_static_d_leaves_other_gradients_unchanged(precision):
     keep = [1] + list(range(5, 20))
     np.testing.assert_array_equal(g_skip[keep], g_all[keep])
     np.testing.assert_array_equal(l_skip, l_all)
+
+
+@pytest.mark.parametrize("uniform_co2", [True, False], ids=["uniform", "varying"])
+def test_reverse_sweep_with_given_final_adjoint(uniform_co2):
+    """vg_adjoint from a given dL/dx at the segment's end (FP64, 12 steps)
+    against the oracle's adjoint with the same final adjoint: with a CO2
+    adjoint uniform over each volume (the sweep then carries it as one value
+    per volume) and with one that varies from voxel to voxel (per-voxel
+    sweep)."""
+    from paper_2406_04177_amd.graph import Graph
+    from paper_2406_04177_amd.sim import Simulation
+    masks, specs = batch(seed=7)
+    p = rates()
+    c = [0.8, 0.9, 1.0, 0.85, 0.95, 0.75, 0.9, 1.0]
+    dt = inputs.explicit_dt(p, 0.8)
+    nsteps = 12
+    g = Graph.from_masks(masks, regions=True)
+    og = orc.build_batch(masks)
+    rng = np.random.default_rng(3)
+    lam_end = rng.standard_normal((5, og.n))
+    if uniform_co2:
+        for k in range(og.nseg):
+            lam_end[4, og.seg_off[k]:og.seg_off[k + 1]] = 0.3 + k
+    seeds = rng.standard_normal((nsteps, og.nseg, 5))
+    sim = Simulation(g, p, precision="f64", implicit=False, adjoint=True, regions=c)
+    sim.set_fields(g.fields_from_specs(specs, torch.float64))
+    states = torch.empty((nsteps, 5, og.n), dtype=torch.float64, device="cuda")
+    sim.record(nsteps, dt, states)
+    lam = torch.as_tensor(lam_end, device="cuda").contiguous()
+    grad = torch.zeros(20, dtype=torch.float64, device="cuda")
+    sim.adjoint(nsteps, dt, states, torch.as_tensor(seeds, device="cuda").contiguous(), lam, grad)
+    reg = orc.octant_regions(og)
+    w = orc.edge_weights(og, reg, c)
+    ostates = orc.run_states(p, dt, og, orc.fields_from_spec(og, specs), nsteps, w=w)
+    oseeds = np.concatenate([seeds, np.zeros((1, og.nseg, 5))])
+    lam_or, g_or = orc.adjoint(p, dt, og, ostates, oseeds, w=w, region=reg, nreg=8, lam_final=lam_end)
+    got = lam.cpu().numpy()
+    np.testing.assert_allclose(got, lam_or, rtol=1e-11, atol=1e-12 * np.abs(lam_or).max())
+    if uniform_co2:
+        for k in range(og.nseg):
+            seg = got[4, og.seg_off[k]:og.seg_off[k + 1]]
+            assert np.all(seg == seg[0])
+    gg = grad.cpu().numpy()
+    scale = np.abs(g_or).max()
+    for q in range(5, 12):   # the kinetic rates (well conditioned)
+        assert abs(gg[q] - g_or[q]) <= 1e-9 * abs(g_or[q]) + 1e-12 * scale, (q, gg[q], g_or[q])
