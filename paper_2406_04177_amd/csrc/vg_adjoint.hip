@@ -225,7 +225,11 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces 
         // forward state of this step and lambda^(k+1) of the voxel
         R x[VG_NPOOL], li[VG_NPOOL];
 #pragma unroll
-        for (int s = 0; s < VG_NPOOL; s++) x[s] = elem(st[s], i);
+        for (int s = 0; s < VG_NPOOL - 1; s++) x[s] = elem(st[s], i);
+        // the CO2 state enters only dL/dD_CO2 (the transformation's
+        // derivative does not depend on it): not read when that term is not
+        // computed
+        x[4] = (MOB == 1 && (CO2U || !DALL)) ? R(0) : elem(st[4], i);
         // the volume of the voxel (seeds, uniform CO2 adjoint)
         int32_t seg = seg_tile;
         if (seg < 0) {
