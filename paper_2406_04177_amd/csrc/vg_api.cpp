@@ -149,6 +149,11 @@ void make_pieces(vg_sim *h) {
         for (int32_t p = h->seg_first_h[gg]; p < h->seg_first_h[gg + 1]; p += kChunk) h->chunk_first_h.push_back(p);
     }
     h->nchunks = (int32_t)h->chunk_first_h.size();
+    h->max_seg_pieces = 0;
+    for (int gg = 0; gg < h->nseg; gg++) {
+        const int32_t np = h->seg_first_h[gg + 1] - h->seg_first_h[gg];
+        if (np > h->max_seg_pieces) h->max_seg_pieces = np;
+    }
     h->seg_chunk_h[h->nseg] = h->nchunks;
     h->chunk_first_h.push_back(h->npieces);
     const int64_t cap = 2048;

@@ -463,6 +463,7 @@ struct vg_sim {
     int64_t ntiles = 0;
     int32_t npieces = 0;
     int32_t nchunks = 0;
+    int32_t max_seg_pieces = 0;  // most pieces in one segment (one-stage totals up to 4096)
     std::vector<int32_t> chunk_first_h, seg_chunk_h;
     int32_t *chunk_first = nullptr, *seg_chunk = nullptr;
     double *chunk_part = nullptr;   // [nchunks][5]

@@ -747,6 +747,30 @@ __global__ __launch_bounds__(kBlock) void k_tot_segments(const double *__restric
     }
 }
 
+// Totals in one stage, for segments of at most kDirectPieces pieces: one
+// block per segment sums its pieces (thread t: pieces t, t + 256, ... in
+// order, then the block in a fixed order), then the five pool totals into
+// total carbon.
+constexpr int32_t kDirectPieces = 4096;
+
+__global__ __launch_bounds__(kBlock) void k_tot_direct(const double *__restrict__ part,
+                                                       const int32_t *__restrict__ seg_first,
+                                                       double *__restrict__ out) {
+    __shared__ double lds[kWaves * VG_NPOOL];
+    const int g = blockIdx.x;
+    double v[VG_NPOOL] = {0, 0, 0, 0, 0};
+    for (int32_t p = seg_first[g] + (int32_t)threadIdx.x; p < seg_first[g + 1]; p += kBlock) {
+#pragma unroll
+        for (int s = 0; s < VG_NPOOL; s++) v[s] += part[(int64_t)p * VG_NPOOL + s];
+    }
+    block_sum<VG_NPOOL>(v, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int s = 0; s < VG_NPOOL; s++) out[g * 6 + s] = v[s];
+        out[g * 6 + 5] = ((v[0] + v[1]) + (v[2] + v[3])) + v[4];
+    }
+}
+
 RGeom make_rgeom(const vg_sim *h) {
     RGeom G;
     make_geom(h->nx, h->ny, h->nz, h->brick, &G.g);
@@ -1263,6 +1287,11 @@ int launch_pass_bufs(vg_sim *h, int mode, int tot, double dt, const void *const 
 
 int launch_totals_finalize(vg_sim *h, double *out_rows, hipStream_t s) {
     if (h->nseg == 0 || h->n == 0) return VG_OK;
+    if (h->max_seg_pieces <= kDirectPieces) {
+        hipLaunchKernelGGL(k_tot_direct, dim3((unsigned)h->nseg), dim3(kBlock), 0, s, h->part, h->seg_first,
+                           out_rows);
+        return launch_status("k_tot_direct");
+    }
     hipLaunchKernelGGL(k_tot_chunks, dim3((unsigned)h->nchunks), dim3(kBlock), 0, s, h->part, h->chunk_first,
                        h->chunk_part);
     int rc = launch_status("k_tot_chunks");
