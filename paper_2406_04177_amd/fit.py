@@ -5,14 +5,15 @@ The gradient of the loss comes from the library's discrete adjoint
 stochastic gradient descent with a normalised gradient (Sec. V.A): each
 fitted parameter moves by the learning rate against the sign of its own
 derivative, the learning rate starting at 0.1 and halved every 10 epochs
-(Sec. V.B).  The step is taken in units of the parameter's starting value,
+(Sec. V.B), applied on the device by ``vg_sign_update``.  The step is taken
+in units of the parameter's starting value,
 so factors that start at 1 (the region conductances) move exactly as in the
 paper, while diffusion coefficients and rates move by the same fraction of
 themselves; a derivative of exactly zero gives no move.  After each update a
 fitted parameter is held inside ``box`` times its starting value (default
 [0.5, 1.5]), so that a fixed time step chosen for the box stays below the
 explicit stability bound.  ``method="adam"`` runs Adam on the same scaled
-coordinates instead.
+coordinates instead (torch's optimiser: an option outside the paper).
 
 The loss is the mean over (step, volume) of the squared difference between
 the per-volume CO2 total and the target curve; an epoch uses every volume, or
@@ -24,6 +25,7 @@ import numpy as np
 import torch
 
 from .autograd import simulate_totals
+from .pngm import sign_update
 
 
 def epoch_loss(sim, theta, x0, target, nsteps, dt, checkpoint_every, vols=None):
@@ -43,6 +45,8 @@ def fit(sim, x0, target, theta0, nsteps, dt, which, epochs=30, checkpoint_every=
     lo = scale * box[0]
     hi = scale * box[1]
     which = list(which)
+    dev = x0.device
+    scale_d, lo_d, hi_d = scale.to(dev), lo.to(dev), hi.to(dev)
     hist, losses = [theta.clone()], []
     u = torch.ones(len(which), dtype=torch.float64, requires_grad=True)   # Adam's coordinates
     opt = torch.optim.Adam([u], lr=lr) if method == "adam" else None
@@ -55,11 +59,12 @@ def fit(sim, x0, target, theta0, nsteps, dt, which, epochs=30, checkpoint_every=
         g = th.grad.detach()
         losses.append(float(loss.detach()))
         if method == "sign":
-            for q in which:
-                if g[q] > 0:
-                    theta[q] -= rate * scale[q]
-                elif g[q] < 0:
-                    theta[q] += rate * scale[q]
+            # the parameters not fitted get a zero derivative: no move
+            g_fit = torch.zeros_like(g)
+            g_fit[which] = g[which]
+            theta_d = theta.to(dev)
+            sign_update(theta_d, g_fit.to(dev).contiguous(), rate, scale_d, lo_d, hi_d)
+            theta = theta_d.cpu()
         elif method == "adam":
             for group in opt.param_groups:
                 group["lr"] = rate
@@ -71,9 +76,9 @@ def fit(sim, x0, target, theta0, nsteps, dt, which, epochs=30, checkpoint_every=
                     theta[q] = scale[q] * u[k].detach()
         else:
             raise ValueError("method must be 'sign' or 'adam'")
-        for q in which:
-            theta[q] = min(max(float(theta[q]), float(lo[q])), float(hi[q]))
         if method == "adam":
+            for q in which:
+                theta[q] = min(max(float(theta[q]), float(lo[q])), float(hi[q]))
             with torch.no_grad():
                 for k, q in enumerate(which):
                     u[k] = theta[q] / scale[q]
