@@ -360,7 +360,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--quick", action="store_true", help="headline only (no extra rows, no CPU baseline)")
-    ap.add_argument("--cpu-steps", type=int, default=400,
+    ap.add_argument("--cpu-steps", type=int, default=450,
                     help="steps of the oracle CPU baseline (about 10-15 s on 16 cores)")
     ap.add_argument("--acc-steps", type=int, default=10000, help="steps of the 256^3 FP32-vs-FP64 row")
     ap.add_argument("--grad-steps", type=int, default=2000, help="steps of the 16 x 128^3 gradient row")

@@ -223,3 +223,40 @@ def test_pngm_entry_points_validate_before_device_work():
     assert implicit(4, 0x2000, 0x3000, -1.0, 1e-10, 10, 0x9000) == E            # c < 0
     assert implicit(4, 0x2000, 0x3000, 1.0, 1e-10, 10, None) == E               # no work area
     assert implicit(4, 0x2000, 0x3000, 1.0, 1e-10, 10, 0x9000, iters_out=None) == E
+
+
+def test_band_feature_workspace():
+    """VG_FEAT_BAND is accepted (unknown bits are not) and, for a single raster
+    volume with a rank index and no periodic axis, adds the row index
+    ((nz * ny + 1) int32) and a second set of the five fields to the
+    workspace; brick order, periodic axes or no rank index add nothing."""
+    L = _lib.load()
+    rc, h, _ = make_handle(features=_lib.VG_FEAT_BAND)
+    assert rc == 0
+    L.vg_destroy(h)
+    rc, h, _ = make_handle(features=8)
+    assert rc == _lib.VG_EINVAL
+    n = 1 << 20
+
+    def ws(features, rank=True, brick=0, periodic=0):
+        seg = np.array([0, n], np.int64)
+        desc = _lib.VgDesc()
+        desc.n, desc.nseg, desc.precision = n, 1, _lib.VG_F32
+        desc.seg_off = seg.ctypes.data
+        desc.nbr_d = 0x1000
+        desc.features = features
+        if rank:
+            desc.rank_d, desc.vox_d = 0x2000, 0x3000    # never dereferenced here
+            desc.nx = desc.ny = desc.nz = 128
+            desc.brick, desc.periodic = brick, periodic
+        h = ctypes.c_void_p()
+        assert L.vg_create(ctypes.byref(desc), ctypes.byref(h)) == 0
+        out = ctypes.c_size_t(0)
+        assert L.vg_workspace_bytes(h, ctypes.byref(out)) == 0
+        L.vg_destroy(h)
+        return out.value
+    base = ws(0)
+    assert ws(_lib.VG_FEAT_BAND) - base >= 5 * 4 * n + 4 * (128 * 128 + 1)
+    assert ws(_lib.VG_FEAT_BAND, brick=8) == ws(0, brick=8)
+    assert ws(_lib.VG_FEAT_BAND, periodic=1) == ws(0, periodic=1)
+    assert ws(_lib.VG_FEAT_BAND, rank=False) == ws(0, rank=False)
