@@ -562,6 +562,14 @@ def main(argv=None):
         cb = cpu_baseline(mask, spec, params, dt, args.cpu_steps)
         out["cpu_baseline"] = cb
         log("cpu baseline: %.3e species updates/s on %d cores" % (cb["value"], cb["cores"]))
+    # the paper's own timing, other hardware (context only, not a target):
+    # Table 1 test 2, explicit 0.1 s steps for 5 days on the 512^3 image
+    # (about 0.17 x 512^3 pore voxels) in 7.9 days on a laptop CPU
+    paper_vps = 5 * 86400 / 0.1 * 0.17 * 512 ** 3 / (7.9 * 86400)
+    out["paper_context"] = {"value": 5.0 * paper_vps, "unit": "pore-voxel species updates/s",
+                            "hardware": "AMD Ryzen 7 PRO 6850H laptop CPU (the paper's C code)",
+                            "source": "Table 1, test 2 (explicit 0.1 s, 5 simulated days, 7.9 days wall time)",
+                            "gpu_over_paper": 5.0 * vps / (5.0 * paper_vps)}
     print(json.dumps(out), flush=True)
     if args.calibrate_copy:
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
