@@ -144,3 +144,34 @@ def test_scheme4_conserves_keeps_uniform_and_zeroes_L2():
     e1 = np.abs(po.scheme4_step(part, X[0], theta, 1e-3) - po.scheme3_step(part, X[0], theta, 1e-3)).max()
     e2 = np.abs(po.scheme4_step(part, X[0], theta, 5e-4) - po.scheme3_step(part, X[0], theta, 5e-4)).max()
     assert 3.5 < e1 / e2 < 4.5
+
+
+def test_normalised_gradient_descent_recovers_known_conductances():
+    """Data made by scheme 4 with known conductances theta* (0.5-2x the
+    starting S/d, symmetric): the normalised-gradient descent of Sec. V.A on
+    objective 2, started from S/d, lowers the loss by more than 100x and
+    moves theta towards theta*."""
+    from oracle import fit_oracle as fo
+    part, theta0, X = setup(seed=5)
+    rng = np.random.default_rng(11)
+    # one factor per unordered pair: theta* symmetric like the truth it stands for
+    fac = {}
+    theta_true = theta0.copy()
+    for i in range(part["q"]):
+        for e in range(part["row"][i], part["row"][i + 1]):
+            key = (min(i, part["col"][e]), max(i, part["col"][e]))
+            fac.setdefault(key, rng.uniform(0.5, 2.0))
+            theta_true[e] *= fac[key]
+    c = 0.8
+    Xs = rng.random((6, part["q"])) * part["v"]
+    Ys = np.stack([po.scheme4_step(part, x, theta_true, c) for x in Xs])
+
+    def grad_fn(theta, epoch):
+        return po.loss_grad(part, Xs, Ys, theta, c, 2)
+    which = range(theta0.size)
+    hist, losses = fo.sign_sgd(theta0, grad_fn, 60, which, lr=0.1, halve_every=10, box=(0.05, 20.0))
+    final_loss = grad_fn(hist[-1], 0)[0]
+    assert final_loss < 1e-2 * losses[0]
+    err0 = np.mean(np.abs(theta0 - theta_true) / theta_true)
+    err1 = np.mean(np.abs(hist[-1] - theta_true) / theta_true)
+    assert err1 < 0.5 * err0, (err0, err1)
