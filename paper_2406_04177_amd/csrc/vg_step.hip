@@ -22,6 +22,13 @@
 //          by axis (48 B per voxel and pass, and the neighbour loads depend on
 //          one load only).  Any volume or batch without periodic wrap whose
 //          largest distances fit the packing.
+//   relative  one 32-bit word per voxel of per-slot codes relative to base
+//          distances shared by each group of 64 voxels (one wave): 44.5 B per
+//          voxel and pass.  The default where it fits.
+//
+// The band kernel (k_band2, below) applies two fused passes per launch to
+// bands of rows marching along z, keeping the first pass's DOM in LDS, for a
+// single raster volume with relative codes.
 //
 // The paper's step is T then D.  The pass computes K = T o D (diffuse, then
 // transform), so n paper steps run as T, K^(n-1), D.  Inside a K pass the
