@@ -110,6 +110,54 @@ def cpu_baseline(mask, spec, params, dt, steps):
             "sample": "%d explicit steps of the same 512^3 workload (n = %d), FP64, %.1f s" % (steps, og.n, sec)}
 
 
+def step_1024(steps=101):
+    """The 1024^3 volume at 17 % porosity (about 1.7e8 pore voxels): FP32 step
+    time with the relative-code single passes and with the band kernel
+    (totals every 100 steps), and the kernel AUTO takes."""
+    import torch
+    from paper_2406_04177_amd import inputs
+    from paper_2406_04177_amd.graph import Graph
+    from paper_2406_04177_amd.sim import Simulation
+    t0 = time.perf_counter()
+    mask = inputs.synthetic_volume((1024, 1024, 1024), porosity=0.17, seed=0)
+    spec = inputs.init_uniform(mask, seed=0)
+    g = Graph.from_masks(mask)
+    del mask
+    log("1024^3 volume and graph in %.1f s (n = %d)" % (time.perf_counter() - t0, g.n))
+    p = inputs.ModelParams()
+    dt = inputs.explicit_dt(p, 0.9)
+    x0 = g.fields_from_specs(spec, torch.float32)
+    sim = Simulation(g, p, precision="f32", implicit=False)
+    res = {"workload": "1024^3 17% porosity explicit step, FP32 fields, FP64 totals every 100 steps",
+           "n_pore_voxels": g.n}
+    for kern, name in ((4, "relative"), (5, "band")):
+        sim.set_kernel(kern)
+        sim.set_fields(x0)
+        sim.step(9, dt)
+        sim.set_fields(x0)
+        ms, _ = timed(lambda: sim.step(steps, dt, log_every=100))
+        res["ms_per_step_" + name] = ms / steps
+        res["achieved_GBs_64B_" + name] = BYTES_FUSED_F32 * g.n / (ms / steps / 1e3) / 1e9
+    sim.set_kernel(0)
+    res["auto_kernel"] = KERNEL_NAMES[sim.kernel_in_use()]
+    log("1024^3: %.3f ms/step single passes, %.3f ms/step band kernel"
+        % (res["ms_per_step_relative"], res["ms_per_step_band"]))
+    del sim, x0, g
+    torch.cuda.empty_cache()
+    return res
+
+
+def copy_1gib():
+    """A plain 1 GiB device-to-device copy (the HIP runtime's copy kernel):
+    bytes read + written per second, a reference for the attainable rate."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ms, _ = timed(lambda: [b.copy_(a) for _ in range(10)])
+    return {"bytes_per_copy": 2 * 4 * (1 << 28), "GBs": 2 * 4 * (1 << 28) * 10 / (ms / 1e3) / 1e9}
+
+
 def accuracy_256(steps, N=256):
     import numpy as np
     import torch
@@ -367,6 +415,7 @@ def main(argv=None):
     ap.add_argument("--fit-epochs", type=int, default=30, help="epochs of the 16 x 128^3 fitting row (0: skip)")
     ap.add_argument("--zlayer", type=int, default=1, help="run the 512^3 z-layer diffusion comparison (0: skip)")
     ap.add_argument("--pngm", type=int, default=1, help="run the 512^3 pore-network fitting row (0: skip)")
+    ap.add_argument("--big", type=int, default=1, help="run the 1024^3 explicit-step row (0: skip)")
     ap.add_argument("--kernel", choices=("auto", "table", "rank", "offset", "relative", "band"), default="auto",
                     help="neighbour source of the explicit-step kernel")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -445,6 +494,7 @@ def main(argv=None):
                    "voxel_steps_per_s": vps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_GBs": None if traffic is None else traffic / (us_launch / 1e6) / 1e9,
                      "kernel": "%s, FP32, DOM-only diffusion (fused transformation + diffusion)" % kname,
                      "neighbour_source": KERNEL_NAMES[kernel],
                      "launch_us": us_launch, "passes_per_launch": ppl, "bytes_per_voxel_step": bpv,
@@ -558,6 +608,10 @@ def main(argv=None):
         # workload: 10^4 steps, totals every 100, error per species (fields,
         # relative to each pool's max) and per totals curve (relative per point)
         rows["fp32_vs_fp64_256"] = accuracy_256(args.acc_steps)
+        rows["copy_1GiB"] = copy_1gib()
+        log("plain 1 GiB device copy: %.0f GB/s (read + written)" % rows["copy_1GiB"]["GBs"])
+        if args.big:
+            rows["explicit_1024"] = step_1024()
         # CPU baseline: the oracle on the host cores
         cb = cpu_baseline(mask, spec, params, dt, args.cpu_steps)
         out["cpu_baseline"] = cb
