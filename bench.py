@@ -63,10 +63,10 @@ KERNEL_SOURCES = ("paper_2406_04177_amd/csrc/vg_step.hip", "paper_2406_04177_amd
                   "paper_2406_04177_amd/build.py")
 MEASURED_TRAFFIC = {
     # (kernel, size): (bytes per launch, sha256 of KERNEL_SOURCES); from
-    # profiles/k_band2_f32_512cube.md: FETCH_SIZE 622049.8 KiB x 2 +
-    # WRITE_SIZE 412614.6 KiB x 1 per launch (two fused passes)
-    ("band", 512): (622049.8 * 1024 * 2 + 412614.6 * 1024,
-                    "e975bcc4c3c6f8e66e9d8604f861e6a2105c2994077f63b7829eaea3ee54fbb9"),
+    # profiles/k_band2_f32_512cube.md: FETCH_SIZE 621838.1 KiB x 2 +
+    # WRITE_SIZE 412609.0 KiB x 1 per launch (two fused passes)
+    ("band", 512): (621838.1 * 1024 * 2 + 412609.0 * 1024,
+                    "7c69f60597cb36d531b41e4c44e8d71e7e9d260a351813cf0525769d8671a668"),
 }
 
 
