@@ -5,11 +5,18 @@
 // neighbour source: table or packed).  Vectors,
 // dot products and scalars are FP64 whatever the field type.
 //
-// Per iteration two streaming kernels (p/q update with the SpMV and p.q
-// partials; x/r/z update with r.z and r.r partials), each followed by a
-// one-block kernel that reduces the per-block partials in a fixed order and
-// updates the scalars on the device.  The host reads the scalars only every
-// few iterations; kernels launched after convergence return at once.
+// Per iteration two streaming kernels, each followed by a one-block kernel
+// that reduces the per-block partials in a fixed order and updates the
+// scalars on the device:
+//  - SpMV: the new direction p = z + beta p_old, q = B p and p.q partials;
+//    also x += alpha p_old, the previous iteration's x update, done here
+//    where p_old is read anyway (the last one is added on write-back);
+//  - update: r -= alpha q, z = M^-1 r, r.z and r.r partials.
+// q = B p is formed as B z + beta q_old (linearity), so the SpMV gathers one
+// vector instead of two; this adds rounding to the gap between the recursive
+// and the true residual, orders of magnitude below the tolerances in use.
+// The host reads the scalars only every few iterations; kernels launched
+// after convergence return at once.
 #include "vg_internal.h"
 
 namespace vg {
@@ -65,7 +72,8 @@ template <typename R, bool REG, int NS>
 __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs A, const R *__restrict__ field,
                                                     double *__restrict__ y, double *__restrict__ r,
                                                     double *__restrict__ z, double *__restrict__ p,
-                                                    double *__restrict__ m, double *__restrict__ part) {
+                                                    double *__restrict__ m, double *__restrict__ part,
+                                                    double *__restrict__ q) {
     __shared__ double lds[kWaves * 3];
     __shared__ double cl[VG_NREG];
     if (threadIdx.x < VG_NREG) cl[threadIdx.x] = A.c[threadIdx.x];
@@ -100,6 +108,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs A, const R *__restric
         z[i] = zi;
         p[i] = zi;
         m[i] = mi;
+        q[i] = 0.0;    // B p of no direction: the first q is B z alone (beta = 0)
         acc[0] += ri * zi;
         acc[1] += ri * ri;
         acc[2] += b * b;
@@ -107,14 +116,17 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs A, const R *__restric
     }
     block_sum<3>(acc, lds);
     if (threadIdx.x == 0) {
-        for (int q = 0; q < 3; q++) part[(int64_t)blockIdx.x * 4 + q] = acc[q];
+        for (int u = 0; u < 3; u++) part[(int64_t)blockIdx.x * 4 + u] = acc[u];
     }
 }
 
-// q = B p' with p' = z + beta p (the new search direction, also written out)
+// p' = z + beta p (the new search direction, written out) and q' = B p',
+// formed as B z + beta q by linearity so that only z is gathered (q holds
+// B p from the previous iteration and 0 before the first, where beta = 0)
 template <bool REG, int NS>
 __global__ __launch_bounds__(kBlock) void k_cg_spmv(CgArgs A, const double *__restrict__ z,
                                                     const double *__restrict__ pold, double *__restrict__ pnew,
+                                                    double *__restrict__ y,
                                                     double *__restrict__ q, const double *__restrict__ scal,
                                                     double *__restrict__ part) {
     if (scal[S_DONE] != 0.0) return;
@@ -122,7 +134,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(CgArgs A, const double *__re
     __shared__ double cl[VG_NREG];
     if (threadIdx.x < VG_NREG) cl[threadIdx.x] = A.c[threadIdx.x];
     __syncthreads();
-    const double beta = scal[S_BETA];
+    const double beta = scal[S_BETA], alpha = scal[S_ALPHA];
     double acc[1] = {0.0};
     for (int64_t it = 0;; it++) {
     const int64_t t = xcd_stride_tile(blockIdx.x, gridDim.x, it, A.ntiles);
@@ -130,23 +142,22 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(CgArgs A, const double *__re
     for (int v = 0; v < kVPT; v++) {
         const int64_t i = t * kTile + v * kBlock + threadIdx.x;
         if (i >= A.n) continue;
-        const double pi = z[i] + beta * pold[i];
+        const double zi = z[i], po = pold[i];
+        y[i] += alpha * po;   // the previous iteration's x update (alpha = 0 before the first)
+        const double pi = zi + beta * po;
         int64_t j[6];
         bool pres[6];
         cg_neighbours<NS>(A, i, j, pres);
-        double zj[6], pj[6];
+        double zj[6];
 #pragma unroll
-        for (int k = 0; k < 6; k++) {
-            zj[k] = z[j[k]];
-            pj[k] = pold[j[k]];
-        }
+        for (int k = 0; k < 6; k++) zj[k] = z[j[k]];
         double s = 0.0;
 #pragma unroll
         for (int k = 0; k < 6; k++) {
             if (!pres[k]) continue;
-            s += weight(A.rcode, cl, i, k, REG) * (pi - (zj[k] + beta * pj[k]));
+            s += weight(A.rcode, cl, i, k, REG) * (zi - zj[k]);
         }
-        const double qi = pi + A.a * s;
+        const double qi = (zi + A.a * s) + beta * q[i];
         pnew[i] = pi;
         q[i] = qi;
         acc[0] += pi * qi;
@@ -156,9 +167,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(CgArgs A, const double *__re
     if (threadIdx.x == 0) part[(int64_t)blockIdx.x * 4] = acc[0];
 }
 
-__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, int64_t ntiles, const double *__restrict__ p,
+__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, int64_t ntiles,
                                                       const double *__restrict__ q, const double *__restrict__ m,
-                                                      double *__restrict__ y, double *__restrict__ r,
+                                                      double *__restrict__ r,
                                                       double *__restrict__ z, const double *__restrict__ scal,
                                                       double *__restrict__ part) {
     if (scal[S_DONE] != 0.0) return;
@@ -171,7 +182,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, int64_t ntiles,
     for (int v = 0; v < kVPT; v++) {
         const int64_t i = t * kTile + v * kBlock + threadIdx.x;
         if (i >= n) continue;
-        y[i] += alpha * p[i];
         const double ri = r[i] - alpha * q[i];
         const double zi = m[i] * ri;
         r[i] = ri;
@@ -218,11 +228,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_scalars(const double *__restrict_
     }
 }
 
+// the solution with the last direction's update still to add
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_cg_writeback(int64_t n, const double *__restrict__ y,
-                                                         R *__restrict__ field) {
+                                                         const double *__restrict__ p,
+                                                         const double *__restrict__ scal, R *__restrict__ field) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) field[i] = (R)y[i];
+    if (i < n) field[i] = (R)(y[i] + scal[S_ALPHA] * p[i]);
 }
 
 template <typename R, int NS>
@@ -245,9 +257,9 @@ int cg_solve_ns(vg_sim *h, int pool, double a, double rtol, int max_iter, int *i
     if ((rc = hip_status(hipMemcpyAsync(h->cg_scal, host_scal, sizeof(host_scal), hipMemcpyHostToDevice, s),
                          "cg scalars"))) return rc;
     if (reg) hipLaunchKernelGGL((k_cg_init<R, true, NS>), dim3(G), dim3(kBlock), 0, s, A, field, h->cg_y, h->cg_r,
-                                h->cg_z, h->cg_p[0], h->cg_m, h->cg_part);
+                                h->cg_z, h->cg_p[0], h->cg_m, h->cg_part, h->cg_q);
     else hipLaunchKernelGGL((k_cg_init<R, false, NS>), dim3(G), dim3(kBlock), 0, s, A, field, h->cg_y, h->cg_r,
-                            h->cg_z, h->cg_p[0], h->cg_m, h->cg_part);
+                            h->cg_z, h->cg_p[0], h->cg_m, h->cg_part, h->cg_q);
     if ((rc = launch_status("k_cg_init"))) return rc;
     hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kBlock), 0, s, h->cg_part, G, 0, h->cg_scal);
     if ((rc = launch_status("k_cg_scalars"))) return rc;
@@ -263,23 +275,23 @@ int cg_solve_ns(vg_sim *h, int pool, double a, double rtol, int max_iter, int *i
         const int todo = (max_iter - launched) < chunk ? (max_iter - launched) : chunk;
         for (int it = 0; it < todo; it++) {
             if (reg) hipLaunchKernelGGL((k_cg_spmv<true, NS>), dim3(G), dim3(kBlock), 0, s, A, h->cg_z, h->cg_p[cur],
-                                        h->cg_p[cur ^ 1], h->cg_q, h->cg_scal, h->cg_part);
+                                        h->cg_p[cur ^ 1], h->cg_y, h->cg_q, h->cg_scal, h->cg_part);
             else hipLaunchKernelGGL((k_cg_spmv<false, NS>), dim3(G), dim3(kBlock), 0, s, A, h->cg_z, h->cg_p[cur],
-                                    h->cg_p[cur ^ 1], h->cg_q, h->cg_scal, h->cg_part);
+                                    h->cg_p[cur ^ 1], h->cg_y, h->cg_q, h->cg_scal, h->cg_part);
             if ((rc = launch_status("k_cg_spmv"))) return rc;
             hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kBlock), 0, s, h->cg_part, G, 1, h->cg_scal);
             if ((rc = launch_status("k_cg_scalars"))) return rc;
-            hipLaunchKernelGGL(k_cg_update, dim3(G), dim3(kBlock), 0, s, h->n, h->ntiles, h->cg_p[cur ^ 1],
-                               h->cg_q, h->cg_m, h->cg_y, h->cg_r, h->cg_z, h->cg_scal, h->cg_part);
+            hipLaunchKernelGGL(k_cg_update, dim3(G), dim3(kBlock), 0, s, h->n, h->ntiles, h->cg_q, h->cg_m,
+                               h->cg_r, h->cg_z, h->cg_scal, h->cg_part);
             if ((rc = launch_status("k_cg_update"))) return rc;
             hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kBlock), 0, s, h->cg_part, G, 2, h->cg_scal);
             if ((rc = launch_status("k_cg_scalars"))) return rc;
-            cur ^= 1;   // p ping-pong; after convergence the kernels return early
+            cur ^= 1;   // p ping-pong (iteration k writes p[k & 1]); after convergence the kernels return early
         }
         launched += todo;
     }
     hipLaunchKernelGGL((k_cg_writeback<R>), dim3((unsigned)((h->n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                       h->n, h->cg_y, field);
+                       h->n, h->cg_y, h->cg_p[(int)back[S_ITER] & 1], h->cg_scal, field);
     if ((rc = launch_status("k_cg_writeback"))) return rc;
     if (iters) *iters = (int)back[S_ITER];
     if (relres) *relres = back[S_BB] > 0.0 ? __builtin_sqrt(back[S_RR] / back[S_BB]) : 0.0;
