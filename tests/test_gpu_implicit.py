@@ -81,6 +81,27 @@ def test_implicit_reports_nonconvergence():
     assert rc == _lib.VG_ENOCONV and its[1] == 3 and rel[1] > 1e-12
 
 
+@pytest.mark.parametrize("k", [1, 2, 3, 7, 20])
+def test_implicit_iterate_after_k_iterations(k):
+    """Stopped at max_iter = k (VG_ENOCONV), the state holds the k-th PCG
+    iterate: the oracle's PCG stopped after k iterations, up to rounding.
+    (The GPU applies each iteration's solution update one kernel later and
+    the last one on write-back; a lost or doubled update is off by ~|alpha p|.)"""
+    from paper_2406_04177_amd import _lib
+    sim, og, x0, p = make()
+    dt = 20 * inputs.explicit_dt(p, 1.0)
+    a = p.D[1] * dt / p.h ** 2
+    its, rel, rc = sim.implicit_step(dt, rtol=1e-30, max_iter=k, check=False)
+    assert rc == _lib.VG_ENOCONV and its[1] == k
+    b = orc.transform(p, dt, x0)[1]
+    y, oits, orel, conv = orc.pcg(a, og, b, rtol=1e-30, max_iter=k)
+    assert oits == k and not conv
+    got = sim.fields.cpu().numpy()[1]
+    err = np.abs(got - y).max() / np.abs(y).max()
+    assert err <= 1e-11, (k, err)
+    assert abs(rel[1] - orel) <= 1e-9 * orel, (rel[1], orel)
+
+
 def test_implicit_fourier_mode_periodic_channel():
     """Closed form: the channel mode decays by 1 / (1 + a lambda) per step."""
     from paper_2406_04177_amd.graph import Graph
