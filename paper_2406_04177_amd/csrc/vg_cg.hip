@@ -11,7 +11,9 @@
 //  - SpMV: the new direction p = z + beta p_old, q = B p and p.q partials;
 //    also x += alpha p_old, the previous iteration's x update, done here
 //    where p_old is read anyway (the last one is added on write-back);
-//  - update: r -= alpha q, z = M^-1 r, r.z and r.r partials.
+//  - update: r -= alpha q, z = M^-1 r, r.z and r.r partials (without region
+//    weights M^-1 comes from a table indexed by the voxel's neighbour count,
+//    1 byte per voxel instead of an FP64 vector).
 // q = B p is formed as B z + beta q_old (linearity), so the SpMV gathers one
 // vector instead of two; this adds rounding to the gap between the recursive
 // and the true residual, orders of magnitude below the tolerances in use.
@@ -107,7 +109,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs A, const R *__restric
         r[i] = ri;
         z[i] = zi;
         p[i] = zi;
-        m[i] = mi;
+        if (REG) m[i] = mi;
+        else ((uint8_t *)m)[i] = (uint8_t)deg;   // 1/diag is then one of 7 values
         q[i] = 0.0;    // B p of no direction: the first q is B z alone (beta = 0)
         acc[0] += ri * zi;
         acc[1] += ri * ri;
@@ -167,13 +170,22 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(CgArgs A, const double *__re
     if (threadIdx.x == 0) part[(int64_t)blockIdx.x * 4] = acc[0];
 }
 
-__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, int64_t ntiles,
+// m: 1/diag per voxel with region weights; without them the number of
+// neighbours per voxel (uint8), and 1/diag = 1 / (1 + a deg) from a table
+// (the same division as in the init kernel, so the same values)
+template <bool REG>
+__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, int64_t ntiles, double a,
                                                       const double *__restrict__ q, const double *__restrict__ m,
                                                       double *__restrict__ r,
                                                       double *__restrict__ z, const double *__restrict__ scal,
                                                       double *__restrict__ part) {
     if (scal[S_DONE] != 0.0) return;
     __shared__ double lds[kWaves * 2];
+    __shared__ double mtab[8];
+    if (!REG) {
+        if (threadIdx.x < 7) mtab[threadIdx.x] = 1.0 / (1.0 + a * (double)threadIdx.x);
+        __syncthreads();
+    }
     const double alpha = scal[S_ALPHA];
     double acc[2] = {0.0, 0.0};
     for (int64_t it = 0;; it++) {
@@ -183,7 +195,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, int64_t ntiles,
         const int64_t i = t * kTile + v * kBlock + threadIdx.x;
         if (i >= n) continue;
         const double ri = r[i] - alpha * q[i];
-        const double zi = m[i] * ri;
+        const double zi = (REG ? m[i] : mtab[((const uint8_t *)m)[i]]) * ri;
         r[i] = ri;
         z[i] = zi;
         acc[0] += ri * zi;
@@ -281,8 +293,10 @@ int cg_solve_ns(vg_sim *h, int pool, double a, double rtol, int max_iter, int *i
             if ((rc = launch_status("k_cg_spmv"))) return rc;
             hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kBlock), 0, s, h->cg_part, G, 1, h->cg_scal);
             if ((rc = launch_status("k_cg_scalars"))) return rc;
-            hipLaunchKernelGGL(k_cg_update, dim3(G), dim3(kBlock), 0, s, h->n, h->ntiles, h->cg_q, h->cg_m,
-                               h->cg_r, h->cg_z, h->cg_scal, h->cg_part);
+            if (reg) hipLaunchKernelGGL(k_cg_update<true>, dim3(G), dim3(kBlock), 0, s, h->n, h->ntiles, a, h->cg_q,
+                                        h->cg_m, h->cg_r, h->cg_z, h->cg_scal, h->cg_part);
+            else hipLaunchKernelGGL(k_cg_update<false>, dim3(G), dim3(kBlock), 0, s, h->n, h->ntiles, a, h->cg_q,
+                                    h->cg_m, h->cg_r, h->cg_z, h->cg_scal, h->cg_part);
             if ((rc = launch_status("k_cg_update"))) return rc;
             hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kBlock), 0, s, h->cg_part, G, 2, h->cg_scal);
             if ((rc = launch_status("k_cg_scalars"))) return rc;
