@@ -102,6 +102,45 @@ def test_implicit_iterate_after_k_iterations(k):
     assert abs(rel[1] - orel) <= 1e-9 * orel, (rel[1], orel)
 
 
+@pytest.mark.parametrize("shape", [(3, 4, 5), (11, 13, 17), (24, 40, 40)])
+@KERNELS
+def test_implicit_unfiltered_masks(shape, kernel):
+    """Raw random masks (isolated voxels, every neighbour count 0-6, one to
+    hundreds of tiles): converged answer by the oracle's matrix, the 5-th
+    iterate against the oracle's, isolated voxels unchanged by the solve."""
+    from paper_2406_04177_amd import _lib
+    from paper_2406_04177_amd.graph import Graph
+    from paper_2406_04177_amd.sim import Simulation
+    mask = (np.random.default_rng(sum(shape)).random(shape) < 0.45).astype(np.uint8)
+    spec = inputs.init_random_all(mask, 3)
+    g = Graph.from_masks(mask)
+    og = orc.build_graph(mask)
+    p = inputs.ModelParams(mu=1e-4, rho=5e-5)
+    dt = 20 * inputs.explicit_dt(p, 1.0)
+    a = p.D[1] * dt / p.h ** 2
+    deg = (og.nbr >= 0).sum(axis=0)
+    assert deg.min() == 0 and deg.max() == 6 or shape == (3, 4, 5)
+    b = orc.transform(p, dt, orc.fields_from_spec(og, spec))[1]
+    results = {}
+    for max_iter, rtol in ((5, 1e-30), (1000, 1e-12)):
+        sim = Simulation(g, p, precision="f64", implicit=True)
+        sim.set_kernel(kernel)
+        sim.set_fields(g.fields_from_specs(spec, torch.float64))
+        its, rel, rc = sim.implicit_step(dt, rtol=rtol, max_iter=max_iter, check=False)
+        results[max_iter] = (sim.fields.cpu().numpy()[1], its[1], rc)
+    got5, its5, rc5 = results[5]
+    y5, oits5, _, _ = orc.pcg(a, og, b, rtol=1e-30, max_iter=5)
+    if oits5 == 5:
+        assert rc5 == _lib.VG_ENOCONV and its5 == 5
+    np.testing.assert_allclose(got5, y5, rtol=0, atol=1e-11 * np.abs(y5).max())
+    got, its, rc = results[1000]
+    assert rc == 0
+    true_res = np.linalg.norm(b - orc.apply_B(a, og, got)) / np.linalg.norm(b)
+    assert true_res <= 2e-12, true_res
+    iso = deg == 0
+    np.testing.assert_array_equal(got[iso], b[iso])
+
+
 def test_implicit_fourier_mode_periodic_channel():
     """Closed form: the channel mode decays by 1 / (1 + a lambda) per step."""
     from paper_2406_04177_amd.graph import Graph
