@@ -58,6 +58,43 @@ def test_band_bitwise_equals_single_passes(shape, por, seed, precision, order):
             assert torch.equal(la, lb), (steps, log_every)
 
 
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_band_raw_mask_with_empty_rows_and_planes(precision):
+    """Unfiltered random mask with empty planes, an empty row in every plane
+    and an empty x range (isolated voxels, bands and planes with no voxel):
+    band kernel = single passes bit for bit; FP64 = the oracle."""
+    from paper_2406_04177_amd.graph import Graph
+    shape = (40, 33, 29)
+    mask = (np.random.default_rng(17).random(shape) < 0.35).astype(np.uint8)
+    mask[5:7] = 0
+    mask[30] = 0
+    mask[:, 3] = 0
+    mask[:, 16:24] = 0
+    mask[:, :, :4] = 0
+    g = Graph.from_masks(mask)
+    p = fast_params()
+    dt = inputs.explicit_dt(p, 0.9)
+    spec = inputs.init_random_all(mask, 8)
+    a = sim_of(g, p, precision, BAND)
+    b = sim_of(g, p, precision, RELATIVE)
+    assert a.kernel_in_use() == BAND
+    for steps, log_every in ((1, 0), (2, 0), (7, 0), (30, 0), (17, 4)):
+        x0 = g.fields_from_specs(spec, torch.float64)
+        a.set_fields(x0)
+        b.set_fields(x0)
+        la = a.step(steps, dt, log_every=log_every)
+        lb = b.step(steps, dt, log_every=log_every)
+        assert torch.equal(a.fields, b.fields), (steps, log_every)
+        if log_every:
+            assert torch.equal(la, lb)
+    if precision == "f64":
+        og = orc.build_graph(mask)
+        ref, _ = orc.run(p, dt, og, orc.fields_from_spec(og, spec), 30, with_totals=False)
+        a.set_fields(g.fields_from_specs(spec, torch.float64))
+        a.step(30, dt)
+        assert np.array_equal(a.fields.cpu().numpy(), ref)
+
+
 def test_band_fp64_equals_oracle():
     """FP64 through the band kernel is the oracle bit for bit (200 steps, the
     48^3 workload's generator at 35 % porosity)."""
