@@ -74,3 +74,38 @@ def test_fp32_steps_512(full):
         outs.append(got)
     for o in outs[1:]:
         np.testing.assert_array_equal(outs[0], o)     # the neighbour sources agree bit for bit
+
+
+def test_implicit_step_512(full):
+    """The implicit step of the benchmark (FP64 fields, dt = 20x the explicit
+    bound, rtol 1e-10) at full size, with the CG kernels' full grid: the
+    transformation half bit for bit, the true residual of the result by the
+    oracle's matrix, and the iterate after 3 PCG iterations against the
+    oracle's (its whole solve takes minutes on the host)."""
+    from paper_2406_04177_amd import _lib
+    from paper_2406_04177_amd.sim import Simulation
+    mask, spec, g, og = full
+    p = inputs.ModelParams()
+    dt = 20 * inputs.explicit_dt(p, 1.0)
+    a = p.D[1] * dt / p.h ** 2
+    rtol = 1e-10
+    x0 = orc.fields_from_spec(og, spec)
+    xt = orc.transform(p, dt, x0)
+    sim = Simulation(g, p, precision="f64", implicit=True)
+    sim.set_fields(g.fields_from_specs(spec, torch.float64))
+    its, rel, rc = sim.implicit_step(dt, rtol=rtol)
+    assert rc == 0 and rel[1] <= rtol
+    got = sim.fields.cpu().numpy()
+    for s in (0, 2, 3, 4):
+        np.testing.assert_array_equal(got[s], xt[s])
+    b = xt[1]
+    true_res = np.linalg.norm(b - orc.apply_B(a, og, got[1])) / np.linalg.norm(b)
+    assert true_res <= 2 * rtol, true_res
+    sim.set_fields(g.fields_from_specs(spec, torch.float64))
+    its3, _, rc3 = sim.implicit_step(dt, rtol=1e-30, max_iter=3, check=False)
+    assert rc3 == _lib.VG_ENOCONV and its3[1] == 3
+    y3, oits, _, _ = orc.pcg(a, og, b, rtol=1e-30, max_iter=3)
+    assert oits == 3
+    got3 = sim.fields[1].cpu().numpy()
+    err = np.abs(got3 - y3).max() / np.abs(y3).max()
+    assert err <= 1e-11, err
