@@ -113,7 +113,9 @@ def cpu_baseline(mask, spec, params, dt, steps):
 def step_1024(steps=101):
     """The 1024^3 volume at 17 % porosity (about 1.7e8 pore voxels): FP32 step
     time with the relative-code single passes and with the band kernel
-    (totals every 100 steps), and the kernel AUTO takes."""
+    (totals every 100 steps), and the kernel AUTO takes; the same for one
+    z-slab of eight (1024 x 1024 x 128)."""
+    import numpy as np
     import torch
     from paper_2406_04177_amd import inputs
     from paper_2406_04177_amd.graph import Graph
@@ -122,6 +124,7 @@ def step_1024(steps=101):
     mask = inputs.synthetic_volume((1024, 1024, 1024), porosity=0.17, seed=0)
     spec = inputs.init_uniform(mask, seed=0)
     g = Graph.from_masks(mask)
+    slab = np.ascontiguousarray(mask[:128])
     del mask
     log("1024^3 volume and graph in %.1f s (n = %d)" % (time.perf_counter() - t0, g.n))
     p = inputs.ModelParams()
@@ -142,6 +145,29 @@ def step_1024(steps=101):
     res["auto_kernel"] = KERNEL_NAMES[sim.kernel_in_use()]
     log("1024^3: %.3f ms/step single passes, %.3f ms/step band kernel"
         % (res["ms_per_step_relative"], res["ms_per_step_band"]))
+    del sim, x0, g
+    torch.cuda.empty_cache()
+    # one GPU's share of the 1024^3 volume split into 8 z-slabs: its first 128
+    # planes as a volume of their own (closed faces: no halo exchange)
+    spec = inputs.init_uniform(slab, seed=0)
+    g = Graph.from_masks(slab)
+    x0 = g.fields_from_specs(spec, torch.float32)
+    sim = Simulation(g, p, precision="f32", implicit=False)
+    sl = {"workload": "1024x1024x128 slab (first 128 planes of the 1024^3 volume), one of 8 z-slabs; no halo",
+          "n_pore_voxels": g.n}
+    for kern, name in ((4, "relative"), (5, "band")):
+        sim.set_kernel(kern)
+        sim.set_fields(x0)
+        sim.step(9, dt)
+        sim.set_fields(x0)
+        ms, _ = timed(lambda: sim.step(steps, dt, log_every=100))
+        sl["ms_per_step_" + name] = ms / steps
+        sl["achieved_GBs_64B_" + name] = BYTES_FUSED_F32 * g.n / (ms / steps / 1e3) / 1e9
+    sim.set_kernel(0)
+    sl["auto_kernel"] = KERNEL_NAMES[sim.kernel_in_use()]
+    res["slab_of_8"] = sl
+    log("1024x1024x128 slab (n = %d): %.4f ms/step single passes, %.4f ms/step band kernel, AUTO %s"
+        % (g.n, sl["ms_per_step_relative"], sl["ms_per_step_band"], sl["auto_kernel"]))
     del sim, x0, g
     torch.cuda.empty_cache()
     return res
