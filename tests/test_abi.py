@@ -23,6 +23,24 @@ def test_header_declares_the_binding_exports():
     assert declared_functions() == sorted(_lib.EXPORTS)
 
 
+def declared_arity():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    out = {}
+    for m in re.finditer(r"^\s*(?:const\s+)?\w+\s*\*?\s*(vg_\w+)\s*\(([^)]*)\)\s*;", text, flags=re.M):
+        params = m.group(2).strip()
+        out[m.group(1)] = 0 if params in ("", "void") else len(params.split(","))
+    return out
+
+
+def test_binding_argument_counts_match_the_header():
+    L = _lib.load()
+    arity = declared_arity()
+    assert sorted(arity) == declared_functions()
+    for name, count in arity.items():
+        assert len(getattr(L, name).argtypes) == count, name
+
+
 def test_every_declared_symbol_is_exported():
     L = _lib.load()
     for name in declared_functions():
