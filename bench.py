@@ -63,10 +63,10 @@ KERNEL_SOURCES = ("paper_2406_04177_amd/csrc/vg_step.hip", "paper_2406_04177_amd
                   "paper_2406_04177_amd/build.py")
 MEASURED_TRAFFIC = {
     # (kernel, size): (bytes per launch, sha256 of KERNEL_SOURCES); from
-    # profiles/k_band2_f32_512cube.md: FETCH_SIZE 621838.1 KiB x 2 +
-    # WRITE_SIZE 412609.0 KiB x 1 per launch (two fused passes)
-    ("band", 512): (621838.1 * 1024 * 2 + 412609.0 * 1024,
-                    "7c69f60597cb36d531b41e4c44e8d71e7e9d260a351813cf0525769d8671a668"),
+    # profiles/k_band2_f32_512cube.md: FETCH_SIZE 621774.1 KiB x 2 +
+    # WRITE_SIZE 412620.9 KiB x 1 per launch (two fused passes)
+    ("band", 512): (621774.1 * 1024 * 2 + 412620.9 * 1024,
+                    "8ebb14eaadd22eb8d491bb5ddea7b3682c508e61672ab4fdcf3356910ae09e9e"),
 }
 
 
