@@ -59,6 +59,7 @@ class _TotalsFn(torch.autograd.Function):
             sim.step(k, dt, log_every=1, totals_out=tot[k0 + 1:k0 + 1 + k])
             k0 += k
         ctx.sim, ctx.dt, ctx.ckpts, ctx.nsteps = sim, dt, ckpts, nsteps
+        ctx.params, ctx.regions = p, c       # the backward differentiates at this forward's theta
         ctx.theta_device = theta.device
         ctx.x0_dtype = x0.dtype
         return tot[:, :, :5].clone()
@@ -66,6 +67,11 @@ class _TotalsFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gout):
         sim, dt = ctx.sim, ctx.dt
+        # another forward on the same simulation may have changed its
+        # parameters since: re-record at this forward's, restore afterwards
+        prev_p, prev_c = sim.params, getattr(sim, "regions", None)
+        sim.set_params(ctx.params)
+        sim.set_regions(ctx.regions)
         dev = sim.fields.device
         n = sim.graph.n
         seeds = gout.detach().to(device=dev, dtype=torch.float64).contiguous()
@@ -78,6 +84,9 @@ class _TotalsFn(torch.autograd.Function):
             sim.set_fields(ck)
             sim.record(k, dt, states)
             sim.adjoint(k, dt, states, seeds[k0:k0 + k], lam, grad)
+        sim.set_params(prev_p)
+        if prev_c is not None:
+            sim.set_regions(prev_c)
         return (grad.to(ctx.theta_device), lam.to(ctx.x0_dtype), None, None, None, None)
 
 

@@ -71,43 +71,31 @@ struct RankWord {
 };
 
 // ---------------------------------------------------------------- mapping
-// Block index -> tile index (blocks are dealt round-robin to the 8 XCDs,
-// each with its own L2).  VG_XCD_MAP 0: identity, all XCDs sweep the voxels
-// together in address order.  1: each XCD works on one contiguous eighth.
-// 2 (default): runs of VG_XCD_RUN consecutive tiles go to the XCDs in turn
-// and each XCD works through its run in order, so the +-x / +-y neighbours
-// of a tile mostly sit in its own L2 while the whole chip still sweeps
-// memory in one front; the remainder is split as with 1.  Measured on the
-// 512^3 step: 2 with runs of 64 tiles ~1 % faster than 0, 1 ~5 % slower.
-#ifndef VG_XCD_MAP
-#define VG_XCD_MAP 2
-#endif
-#ifndef VG_XCD_RUN
-#define VG_XCD_RUN 64
-#endif
+// Block index -> tile index.  Blocks are dealt round-robin to the 8 XCDs,
+// each with its own L2; runs of kXcdRun consecutive tiles go to the XCDs in
+// turn and each XCD works through its run in order, so the +-x / +-y
+// neighbours of a tile mostly sit in its own L2 while the whole chip still
+// sweeps memory in one front; the tiles after the last full round of runs
+// are split into one contiguous share per XCD.  (Measured on the 512^3 step:
+// ~1 % faster than the identity map; one contiguous eighth per XCD ~5 %
+// slower.)
+constexpr int64_t kXcdRun = 64;
 __device__ inline int64_t xcd_split(int64_t b, int64_t nb) {
     const int64_t q = nb / kNumXcd, r = nb % kNumXcd;
     const int64_t x = b % kNumXcd, k = b / kNumXcd;
     return x * q + (x < r ? x : r) + k;
 }
 __device__ inline int64_t xcd_tile(int64_t b, int64_t nb) {
-#if VG_XCD_MAP == 1
-    return xcd_split(b, nb);
-#elif VG_XCD_MAP == 2
-    constexpr int64_t S = VG_XCD_RUN, R = S * kNumXcd;
+    constexpr int64_t S = kXcdRun, R = S * kNumXcd;
     const int64_t full = nb / R * R;
     if (b >= full) return full + xcd_split(b - full, nb - full);
     const int64_t x = b % kNumXcd, k = b / kNumXcd;
     return ((k / S) * kNumXcd + x) * S + k % S;
-#else
-    (void)nb;
-    return b;
-#endif
 }
 
 // Tile of iteration `it` of block b in a grid-stride kernel of nb blocks.
 // With nb a multiple of 8 the blocks of one XCD (b % 8) walk that XCD's own
-// runs of VG_XCD_RUN consecutive tiles (the runs xcd_tile deals to it), then
+// runs of kXcdRun consecutive tiles (the runs xcd_tile deals to it), then
 // its contiguous share of the tiles after the last full round of runs, so a
 // grid-stride kernel keeps the locality of the one-tile-per-block kernels;
 // otherwise plain striding.  Returns ntiles once the block's list is done.
@@ -116,7 +104,7 @@ __device__ inline int64_t xcd_stride_tile(int64_t b, int64_t nb, int64_t it, int
         const int64_t t = b + it * nb;
         return t < ntiles ? t : ntiles;
     }
-    constexpr int64_t S = VG_XCD_RUN, R = S * kNumXcd;
+    constexpr int64_t S = kXcdRun, R = S * kNumXcd;
     const int64_t x = b % kNumXcd, m = it * (nb / kNumXcd) + b / kNumXcd;
     const int64_t nfull = ntiles / R * R, own_full = nfull / kNumXcd;
     if (m < own_full) return ((m / S) * kNumXcd + x) * S + m % S;
@@ -254,11 +242,7 @@ struct Pieces {
     int32_t npieces;
 };
 
-#ifndef VG_VPT
-#define VG_VPT 1
-#endif
-
-constexpr int kVPT = VG_VPT;            // voxels per thread in a tile
+constexpr int kVPT = 1;                 // voxels per thread in a tile
 constexpr int kTile = kBlock * kVPT;    // voxels per tile (one tile per block)
 constexpr int kChunk = 256;             // pieces per first-stage totals chunk
 

@@ -176,27 +176,15 @@ StepBufs<R> graph_bufs(const vg_sim *h) {
 }
 
 
-#ifndef VG_NT
-#define VG_NT 0
-#endif
 // Loads and stores of data used once per pass (the neighbour table, the
-// immobile pools) may bypass cache allocation so that the gathered pools stay
-// resident.
+// immobile pools); plain accesses (nontemporal ones measured no faster).
 template <typename T>
 __device__ __forceinline__ T ld_once(const T *p) {
-#if VG_NT
-    return __builtin_nontemporal_load(p);
-#else
     return *p;
-#endif
 }
 template <typename T>
 __device__ __forceinline__ void st_once(T *p, T v) {
-#if VG_NT
-    __builtin_nontemporal_store(v, p);
-#else
     *p = v;
-#endif
 }
 
 // MOB: 1 = only DOM diffuses, 2 = every pool diffuses (a_s may be 0).
