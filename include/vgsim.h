@@ -51,6 +51,19 @@ extern "C" {
 /* ---- enumerations ------------------------------------------------------ */
 #define VG_F32 0           /* fields stored and stepped in float32           */
 #define VG_F64 1           /* fields stored and stepped in float64           */
+/* Compensated float32: every pool value is held as the float hi nearest to
+ * it (the bound fields, readable as plain float32) plus a 16-bit word
+ * lo = (x - hi) / ulp(hi) * 2^15 rounded to an integer (|lo| <= 2^14, kept in
+ * the workspace), i.e. a 39-bit significand in 6 bytes; the arithmetic of a
+ * step runs in FP64 and each stored value rounds by at most 2^-39 relative
+ * instead of 2^-24.  Over k steps the drift of plain float32 (slow pools
+ * such as MB, SOM and CO2 change by ~1e-7 of themselves per step, about one
+ * float32 rounding, Sec. II.C eq. (3)) is thereby cut by 2^15.  Covers the
+ * explicit and sub-cycled steps, the totals and the implicit step; no
+ * adjoint (VG_FEAT_ADJ), no rank-index or band kernel (the table or a packed
+ * neighbour source is used).  Set a state with more than float32 precision
+ * with vg_load_state, read it with vg_store_state. */
+#define VG_F32C 2
 
 #define VG_PERIODIC_X 1u   /* wrap-around neighbours (tests); default no-flux */
 #define VG_PERIODIC_Y 2u
@@ -201,7 +214,7 @@ typedef struct vg_sim vg_sim;
 typedef struct vg_desc {
     int64_t n;               /* pore voxels over all volumes                 */
     int32_t nseg;            /* volumes (segments of the compact list)       */
-    int32_t precision;       /* VG_F32 or VG_F64                             */
+    int32_t precision;       /* VG_F32, VG_F64 or VG_F32C                    */
     const int64_t *seg_off;  /* host [nseg + 1], seg_off[0] = 0, [nseg] = n  */
     const int32_t *nbr_d;    /* device [6][n] neighbour table                */
     const uint16_t *rcode_d; /* device [n] region codes or NULL (weights 1)  */
@@ -268,7 +281,8 @@ int vg_set_params(vg_sim *h, const vg_params *p);
 int vg_set_regions(vg_sim *h, const double *c);
 
 /* Device memory the caller binds with vg_init_state:
- *   fields  [5][n] elements of the field type (float or double)
+ *   fields  [5][n] elements of the field type (float or double; float for
+ *           VG_F32C, whose compensation words live in the workspace)
  *   alt     alt_elems elements of the field type (ping-pong of mobile pools)
  *   work    workspace_bytes bytes (reduction partials, packed neighbour
  *           offsets and codes (12.5 B per voxel), geometry words with a rank
@@ -320,6 +334,19 @@ int vg_solve_implicit_step(vg_sim *h, double dt, double rtol, int max_iter, int 
 /* Totals of the bound state: out_h[g][0..5] (host), FP64, fixed summation
  * order.  Returns VG_ENONFINITE if any total is not finite.  Synchronises. */
 int vg_mass_totals(vg_sim *h, double *out_h, void *stream);
+
+/* Copies a state into the bound fields, converting to the handle's
+ * precision: x_d [5][n] of x_precision (VG_F32 or VG_F64) on the device.
+ * Float32 fields take the nearest float; compensated fields (VG_F32C) take
+ * the nearest float and its compensation word (a VG_F32 source gives zero
+ * words).  x_d may be the bound fields themselves (after writing them
+ * directly, this clears the compensation words).  Asynchronous. */
+int vg_load_state(vg_sim *h, const void *x_d, int x_precision, void *stream);
+
+/* Writes the bound state to x_d [5][n] in x_precision (VG_F32: the float
+ * part of compensated fields; VG_F64: the value, for VG_F32C hi + lo ulp(hi)
+ * 2^-15, exact).  x_d must not overlap the bound buffers.  Asynchronous. */
+int vg_store_state(vg_sim *h, void *x_d, int x_precision, void *stream);
 
 /* ---- discrete adjoint of the explicit loop (paper order only) -----------
  * vg_record advances nsteps steps from the bound state x^k0 and writes what

@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("VGSIM_LIB") or os.path.join(_HERE, "libvgsim.so")
 
 VG_OK, VG_EINVAL, VG_EUNSTABLE, VG_ENOCONV, VG_ENONFINITE, VG_EHIP, VG_ESTATE = 0, -1, -2, -3, -4, -5, -6
-VG_F32, VG_F64 = 0, 1
+VG_F32, VG_F64, VG_F32C = 0, 1, 2
 VG_ORDER_TD, VG_ORDER_DT = 0, 1
 VG_FORCE = 1
 VG_FEAT_CG, VG_FEAT_ADJ, VG_FEAT_BAND = 1, 2, 4
@@ -28,7 +28,7 @@ EXPORTS = ("vg_strerror", "vg_last_error", "vg_version", "vg_rank_bytes", "vg_co
            "vg_brick_stats", "vg_pngm_loss_grad", "vg_pngm_step", "vg_pngm_implicit_step", "vg_sign_update", "vg_create", "vg_destroy",
            "vg_set_kernel", "vg_get_kernel", "vg_set_adjoint_options", "vg_set_params", "vg_set_regions", "vg_alt_elems", "vg_workspace_bytes", "vg_init_state",
            "vg_step_explicit", "vg_step_subcycled", "vg_solve_implicit_step", "vg_mass_totals", "vg_record", "vg_adjoint",
-           "vg_seed_lambda")
+           "vg_seed_lambda", "vg_load_state", "vg_store_state")
 
 
 class VgError(RuntimeError):
@@ -100,6 +100,8 @@ def load():
             "vg_record": (I, [P, I64, D, P, P]),
             "vg_adjoint": (I, [P, I64, D, P, P, P, P, P]),
             "vg_seed_lambda": (I, [P, P, P, I, P]),
+            "vg_load_state": (I, [P, P, I, P]),
+            "vg_store_state": (I, [P, P, I, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)

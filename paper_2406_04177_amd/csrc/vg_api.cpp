@@ -109,6 +109,10 @@ size_t layout(vg_sim *h, char *base) {
         h->band_rs = (int32_t *)take(sizeof(int32_t) * ((size_t)h->nz * (size_t)h->ny + 1));
         h->band_alt = take(h->elem() * VG_NPOOL * (size_t)h->n);
     }
+    if (h->prec == VG_F32C) {
+        h->lo = (int16_t *)take(sizeof(int16_t) * VG_NPOOL * (size_t)h->n);
+        h->lo_alt = (int16_t *)take(sizeof(int16_t) * (h->mobile_all ? VG_NPOOL : 1) * (size_t)h->n);
+    }
     return off;
 }
 
@@ -241,7 +245,14 @@ extern "C" int vg_create(const vg_desc *d, vg_sim **out) {
         set_error("bad graph descriptor (n, nseg, seg_off, nbr)");
         return VG_EINVAL;
     }
-    if (d->precision != VG_F32 && d->precision != VG_F64) { set_error("precision must be VG_F32 or VG_F64"); return VG_EINVAL; }
+    if (d->precision != VG_F32 && d->precision != VG_F64 && d->precision != VG_F32C) {
+        set_error("precision must be VG_F32, VG_F64 or VG_F32C");
+        return VG_EINVAL;
+    }
+    if (d->precision == VG_F32C && (d->features & VG_FEAT_ADJ)) {
+        set_error("the adjoint needs VG_F32 or VG_F64 fields");
+        return VG_EINVAL;
+    }
     if (d->seg_off[0] != 0 || d->seg_off[d->nseg] != d->n) { set_error("seg_off must run from 0 to n"); return VG_EINVAL; }
     for (int g = 0; g < d->nseg; g++)
         if (d->seg_off[g + 1] < d->seg_off[g]) { set_error("seg_off must be non-decreasing"); return VG_EINVAL; }
@@ -292,7 +303,9 @@ extern "C" int vg_destroy(vg_sim *h) {
 
 extern "C" int vg_set_kernel(vg_sim *h, int variant) {
     if (!h) { set_error("handle is NULL"); return VG_EINVAL; }
-    if (variant < VG_KERNEL_AUTO || variant > VG_KERNEL_BAND || (variant == VG_KERNEL_RANK && !h->rank) ||
+    const bool comp = h->prec == VG_F32C;   // compensated fields: table or packed sources only
+    if (variant < VG_KERNEL_AUTO || variant > VG_KERNEL_BAND || (variant == VG_KERNEL_RANK && (!h->rank || comp)) ||
+        (variant == VG_KERNEL_BAND && comp) ||
         (variant == VG_KERNEL_OFFSET && !h->off_ok) || (variant == VG_KERNEL_RELATIVE && !h->rel_ok) ||
         (variant == VG_KERNEL_BAND && !(h->band_ok && h->rel_ok))) {
         set_error("kernel variant %d not available", variant);
@@ -344,7 +357,7 @@ extern "C" int vg_alt_elems(const vg_sim *h, int64_t *elems) {
 extern "C" int vg_workspace_bytes(const vg_sim *h, size_t *bytes) {
     if (!h || !bytes) { set_error("null pointer argument"); return VG_EINVAL; }
     vg_sim tmp;
-    tmp.n = h->n; tmp.nseg = h->nseg; tmp.prec = h->prec; tmp.features = h->features;
+    tmp.n = h->n; tmp.nseg = h->nseg; tmp.prec = h->prec; tmp.features = h->features; tmp.mobile_all = h->mobile_all;
     tmp.ntiles = h->ntiles; tmp.npieces = h->npieces; tmp.cg_blocks = h->cg_blocks; tmp.adj_blocks = h->adj_blocks;
     tmp.nchunks = h->nchunks;
     tmp.rank = h->rank;   // the geometry words are part of the workspace when a rank index is used
@@ -382,6 +395,13 @@ extern "C" int vg_init_state(vg_sim *h, void *fields_d, void *alt_d, void *work_
                                         hipMemcpyHostToDevice, s), "upload chunks"))) return rc;
     if ((rc = hip_status(hipMemcpyAsync(h->seg_chunk, h->seg_chunk_h.data(), sizeof(int32_t) * h->seg_chunk_h.size(),
                                         hipMemcpyHostToDevice, s), "upload segment chunks"))) return rc;
+    if (h->prec == VG_F32C && h->n > 0) {   // the fields hold the initial state exactly
+        if ((rc = hip_status(hipMemsetAsync(h->lo, 0, sizeof(int16_t) * VG_NPOOL * (size_t)h->n, s), "clear words")))
+            return rc;
+        if ((rc = hip_status(hipMemsetAsync(h->lo_alt, 0, sizeof(int16_t) * (h->mobile_all ? VG_NPOOL : 1) * (size_t)h->n, s),
+                             "clear words")))
+            return rc;
+    }
     if ((rc = launch_geometry(h, s))) return rc;
     if ((rc = build_offsets(h, s))) return rc;
     if ((rc = build_band(h, s))) return rc;
@@ -569,4 +589,20 @@ extern "C" int vg_seed_lambda(vg_sim *h, const double *seed_d, void *lambda_d, i
     if (rc) return rc;
     if (h->n > 0 && (!seed_d || !lambda_d)) { set_error("null pointer argument"); return VG_EINVAL; }
     return launch_seed(h, seed_d, lambda_d, zero, (hipStream_t)stream);
+}
+
+extern "C" int vg_load_state(vg_sim *h, const void *x_d, int x_precision, void *stream) {
+    int rc = need_bound(h);
+    if (rc) return rc;
+    if (x_precision != VG_F32 && x_precision != VG_F64) { set_error("x_precision must be VG_F32 or VG_F64"); return VG_EINVAL; }
+    if (h->n > 0 && !x_d) { set_error("x_d is NULL"); return VG_EINVAL; }
+    return launch_load_state(h, x_d, x_precision, (hipStream_t)stream);
+}
+
+extern "C" int vg_store_state(vg_sim *h, void *x_d, int x_precision, void *stream) {
+    int rc = need_bound(h);
+    if (rc) return rc;
+    if (x_precision != VG_F32 && x_precision != VG_F64) { set_error("x_precision must be VG_F32 or VG_F64"); return VG_EINVAL; }
+    if (h->n > 0 && !x_d) { set_error("x_d is NULL"); return VG_EINVAL; }
+    return launch_store_state(h, x_d, x_precision, (hipStream_t)stream);
 }

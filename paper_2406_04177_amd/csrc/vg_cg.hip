@@ -70,8 +70,8 @@ __device__ __forceinline__ void cg_neighbours(const CgArgs &A, int64_t i, int64_
     }
 }
 
-template <typename R, bool REG, int NS>
-__global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs A, const R *__restrict__ field,
+template <typename F, bool REG, int NS>
+__global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs A, F field,
                                                     double *__restrict__ y, double *__restrict__ r,
                                                     double *__restrict__ z, double *__restrict__ p,
                                                     double *__restrict__ m, double *__restrict__ part,
@@ -87,13 +87,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs A, const R *__restric
     for (int v = 0; v < kVPT; v++) {
         const int64_t i = t * kTile + v * kBlock + threadIdx.x;
         if (i >= A.n) continue;
-        const double b = (double)field[i];
+        const double b = field.get(i);
         int64_t j[6];
         bool pres[6];
         cg_neighbours<NS>(A, i, j, pres);
         double fj[6];
 #pragma unroll
-        for (int k = 0; k < 6; k++) fj[k] = (double)field[j[k]];
+        for (int k = 0; k < 6; k++) fj[k] = field.get(j[k]);
         double s = 0.0, deg = 0.0;
 #pragma unroll
         for (int k = 0; k < 6; k++) {
@@ -240,16 +240,33 @@ __global__ __launch_bounds__(kBlock) void k_cg_scalars(const double *__restrict_
     }
 }
 
-// the solution with the last direction's update still to add
-template <typename R>
+// the solution with the last direction's update still to add, rounded to the
+// field storage
+template <typename F>
 __global__ __launch_bounds__(kBlock) void k_cg_writeback(int64_t n, const double *__restrict__ y,
                                                          const double *__restrict__ p,
-                                                         const double *__restrict__ scal, R *__restrict__ field) {
+                                                         const double *__restrict__ scal, F field) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) field[i] = (R)(y[i] + scal[S_ALPHA] * p[i]);
+    if (i < n) field.put(i, y[i] + scal[S_ALPHA] * p[i]);
 }
 
-template <typename R, int NS>
+// storage of one pool of the bound fields
+template <typename F>
+F pool_acc(vg_sim *h, int pool);
+template <>
+PlainAcc<float> pool_acc<PlainAcc<float>>(vg_sim *h, int pool) {
+    return PlainAcc<float>{(float *)h->fields + (int64_t)pool * h->n};
+}
+template <>
+PlainAcc<double> pool_acc<PlainAcc<double>>(vg_sim *h, int pool) {
+    return PlainAcc<double>{(double *)h->fields + (int64_t)pool * h->n};
+}
+template <>
+CompAcc pool_acc<CompAcc>(vg_sim *h, int pool) {
+    return CompAcc{(float *)h->fields + (int64_t)pool * h->n, h->lo + (int64_t)pool * h->n};
+}
+
+template <typename F, int NS>
 int cg_solve_ns(vg_sim *h, int pool, double a, double rtol, int max_iter, int *iters, double *relres,
                 hipStream_t s) {
     CgArgs A;
@@ -262,15 +279,15 @@ int cg_solve_ns(vg_sim *h, int pool, double a, double rtol, int max_iter, int *i
     for (int k = 0; k < VG_NREG; k++) A.c[k] = h->c[k];
     const bool reg = h->rcode != nullptr;
     const int G = h->cg_blocks;
-    R *field = (R *)h->fields + (int64_t)pool * h->n;
+    const F field = pool_acc<F>(h, pool);
     int rc;
     // squared tolerance (compared with squared norms; rtol^2 is exact enough)
     double host_scal[S_NSCAL] = {0, 0, 0, 0, 0, 0, 0, rtol * rtol};
     if ((rc = hip_status(hipMemcpyAsync(h->cg_scal, host_scal, sizeof(host_scal), hipMemcpyHostToDevice, s),
                          "cg scalars"))) return rc;
-    if (reg) hipLaunchKernelGGL((k_cg_init<R, true, NS>), dim3(G), dim3(kBlock), 0, s, A, field, h->cg_y, h->cg_r,
+    if (reg) hipLaunchKernelGGL((k_cg_init<F, true, NS>), dim3(G), dim3(kBlock), 0, s, A, field, h->cg_y, h->cg_r,
                                 h->cg_z, h->cg_p[0], h->cg_m, h->cg_part, h->cg_q);
-    else hipLaunchKernelGGL((k_cg_init<R, false, NS>), dim3(G), dim3(kBlock), 0, s, A, field, h->cg_y, h->cg_r,
+    else hipLaunchKernelGGL((k_cg_init<F, false, NS>), dim3(G), dim3(kBlock), 0, s, A, field, h->cg_y, h->cg_r,
                             h->cg_z, h->cg_p[0], h->cg_m, h->cg_part, h->cg_q);
     if ((rc = launch_status("k_cg_init"))) return rc;
     hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kBlock), 0, s, h->cg_part, G, 0, h->cg_scal);
@@ -304,7 +321,7 @@ int cg_solve_ns(vg_sim *h, int pool, double a, double rtol, int max_iter, int *i
         }
         launched += todo;
     }
-    hipLaunchKernelGGL((k_cg_writeback<R>), dim3((unsigned)((h->n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL((k_cg_writeback<F>), dim3((unsigned)((h->n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
                        h->n, h->cg_y, h->cg_p[(int)back[S_ITER] & 1], h->cg_scal, field);
     if ((rc = launch_status("k_cg_writeback"))) return rc;
     if (iters) *iters = (int)back[S_ITER];
@@ -313,12 +330,12 @@ int cg_solve_ns(vg_sim *h, int pool, double a, double rtol, int max_iter, int *i
 }
 
 // the explicit step's neighbour source
-template <typename R>
+template <typename F>
 int cg_solve(vg_sim *h, int pool, double a, double rtol, int max_iter, int *iters, double *relres,
              hipStream_t s) {
-    if (use_relative(h)) return cg_solve_ns<R, NS_REL>(h, pool, a, rtol, max_iter, iters, relres, s);
-    if (use_offsets(h)) return cg_solve_ns<R, NS_OFF>(h, pool, a, rtol, max_iter, iters, relres, s);
-    return cg_solve_ns<R, NS_TABLE>(h, pool, a, rtol, max_iter, iters, relres, s);
+    if (use_relative(h)) return cg_solve_ns<F, NS_REL>(h, pool, a, rtol, max_iter, iters, relres, s);
+    if (use_offsets(h)) return cg_solve_ns<F, NS_OFF>(h, pool, a, rtol, max_iter, iters, relres, s);
+    return cg_solve_ns<F, NS_TABLE>(h, pool, a, rtol, max_iter, iters, relres, s);
 }
 
 }  // namespace
@@ -330,8 +347,9 @@ int run_cg(vg_sim *h, int pool, double a, double rtol, int max_iter, int *iters,
         if (relres) *relres = 0.0;
         return VG_OK;
     }
-    if (h->prec == VG_F64) return cg_solve<double>(h, pool, a, rtol, max_iter, iters, relres, s);
-    return cg_solve<float>(h, pool, a, rtol, max_iter, iters, relres, s);
+    if (h->prec == VG_F32C) return cg_solve<CompAcc>(h, pool, a, rtol, max_iter, iters, relres, s);
+    if (h->prec == VG_F64) return cg_solve<PlainAcc<double>>(h, pool, a, rtol, max_iter, iters, relres, s);
+    return cg_solve<PlainAcc<float>>(h, pool, a, rtol, max_iter, iters, relres, s);
 }
 
 }  // namespace vg

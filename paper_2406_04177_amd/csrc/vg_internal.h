@@ -221,6 +221,51 @@ __device__ inline void block_sum(double (&v)[M], double *lds) {
     __syncthreads();
 }
 
+// ---------------------------------------------------------------- storage
+// Compensated float32 (VG_F32C): a value x is stored as hi = the float nearest
+// to x and lo = (x - hi) / ulp(hi) * 2^15 rounded to an int16.  |x - hi| is at
+// most half an ulp of hi, so |lo| <= 2^14, and x - hi is exact in FP64
+// (Sterbenz), as is the scaling by a power of two: the only rounding is lo's,
+// at most ulp(hi) * 2^-16, i.e. 2^-39 relative.  ulp(hi) = 2^(e - 150) for the
+// biased exponent e of hi, with e taken as 1 for zero and subnormal hi (their
+// ulp is 2^-149), so ulp(hi) * 2^-15 = 2^(e - 165), a normal double.
+__device__ __forceinline__ double comp_get(float hi, int16_t lo) {
+    uint32_t e = (__float_as_uint(hi) >> 23) & 0xffu;
+    e = e < 1u ? 1u : e;
+    const double scale = __longlong_as_double((long long)((uint64_t)(e + 858u) << 52));   // 2^(e - 165)
+    return (double)hi + (double)lo * scale;
+}
+
+__device__ __forceinline__ void comp_put(double x, float &hi, int16_t &lo) {
+    const float h = (float)x;
+    uint32_t e = (__float_as_uint(h) >> 23) & 0xffu;
+    e = e < 1u ? 1u : e;
+    const double inv = __longlong_as_double((long long)((uint64_t)(1188u - e) << 52));    // 2^(165 - e)
+    hi = h;
+    lo = (int16_t)__double2int_rn((x - (double)h) * inv);
+}
+
+// One pool's storage as the kernels that work in FP64 see it (the implicit
+// solve, state conversions): plain R, or compensated float32.
+template <typename R>
+struct PlainAcc {
+    R *p;
+    __device__ __forceinline__ double get(int64_t i) const { return (double)p[i]; }
+    __device__ __forceinline__ void put(int64_t i, double v) const { p[i] = (R)v; }
+};
+struct CompAcc {
+    float *hi;
+    int16_t *lo;
+    __device__ __forceinline__ double get(int64_t i) const { return comp_get(hi[i], lo[i]); }
+    __device__ __forceinline__ void put(int64_t i, double v) const {
+        float h;
+        int16_t l;
+        comp_put(v, h, l);
+        hi[i] = h;
+        lo[i] = l;
+    }
+};
+
 // ---------------------------------------------------------------- kernels
 // Coefficients of one step, rounded once to the field type R.
 template <typename R>
@@ -443,6 +488,8 @@ struct vg_sim {
     char *alt = nullptr;
     char *work = nullptr;
     int cur = 0;                 // mobile pools live in fields (0) or alt (1)
+    int16_t *lo = nullptr;       // VG_F32C: [5][n] compensation words of the fields
+    int16_t *lo_alt = nullptr;   // VG_F32C: compensation words of alt
     // reduction tiles and pieces (host copies and device views)
     int64_t ntiles = 0;
     int32_t npieces = 0;
@@ -494,7 +541,7 @@ struct vg_sim {
     int32_t *adj_flag = nullptr; // [nseg] nonzero: the CO2 adjoint of the volume is not uniform
     int adj_blocks = 0;
 
-    size_t elem() const { return prec == VG_F64 ? sizeof(double) : sizeof(float); }
+    size_t elem() const { return prec == VG_F64 ? sizeof(double) : sizeof(float); }   // float for VG_F32C
     int mobile_mode() const { return mobile_all ? 2 : 1; }
 };
 
@@ -527,6 +574,8 @@ int launch_record(vg_sim *h, int64_t nsteps, double dt, void *states, hipStream_
 int launch_adjoint(vg_sim *h, int64_t nsteps, double dt, const void *states, const double *seeds,
                    void *lambda, double *grad, hipStream_t s);
 int launch_seed(vg_sim *h, const double *seed, void *lambda, int zero, hipStream_t s);
+int launch_load_state(vg_sim *h, const void *x, int xprec, hipStream_t s);
+int launch_store_state(vg_sim *h, void *x, int xprec, hipStream_t s);
 
 // Coefficients of a pass whose transformation step is dt_t and whose
 // diffusion step is dt_d (equal except in sub-cycled runs).

@@ -474,6 +474,122 @@ __global__ __launch_bounds__(kBlock) void k_step_off(StepBufs<R> B, Coef<R> C, P
     }
 }
 
+// Compensated float32 fields (VG_F32C): every pool is a float hi and an
+// int16 compensation word lo (6 B per value, a 39-bit significand, see
+// comp_get / comp_put).  The pass decodes to FP64, diffuses and transforms in
+// FP64 with the operations of the FP64 pass in the same order, and rounds
+// each value once on the way out.  Neighbours come from the table or a packed
+// source, chosen at run time (uniform branch); region weights and the
+// algorithm likewise.
+struct CompBufs {
+    const int32_t *nbr = nullptr;       // [6][n]
+    const uint16_t *rcode = nullptr;    // [n] or null
+    PackedNbr pk;
+    int ns = 0;                         // 0 table, 1 relative codes, 2 packed offsets
+    const float *src[VG_NPOOL] = {};
+    const int16_t *slo[VG_NPOOL] = {};
+    float *dst[VG_NPOOL] = {};
+    int16_t *dlo[VG_NPOOL] = {};
+    int64_t n = 0;
+};
+
+__device__ __forceinline__ double comp_at(const float *hi, const int16_t *lo, uint32_t i) {
+    return comp_get(at(hi, i), at(lo, i));
+}
+
+template <int MODE, int MOB, int TOT>
+__global__ __launch_bounds__(kBlock) void k_step_c(CompBufs B, Coef<double> C, Pieces pc,
+                                                   double *__restrict__ part) {
+    __shared__ double lds[kRows * VG_NPOOL];
+    __shared__ double cl[VG_NREG];
+    constexpr bool do_d = MODE == MODE_D || MODE == MODE_DT;
+    constexpr bool do_t = MODE == MODE_T || MODE == MODE_DT;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t n = (uint32_t)B.n;
+    const bool reg = B.rcode != nullptr;
+    if (reg) {   // uniform over the block
+        if (threadIdx.x < VG_NREG) cl[threadIdx.x] = C.c[threadIdx.x];
+        __syncthreads();
+    }
+    const uint32_t i0 = (uint32_t)tile * (uint32_t)kBlock + threadIdx.x;
+    const bool act = i0 < n;
+    const uint32_t i = act ? i0 : n - 1;
+    // neighbours: an absent one is the voxel itself (its difference is +0)
+    uint32_t j[6];
+    bool pres[6];
+    if (do_d) {
+        if (B.ns == 0) {
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                const int32_t jk = B.nbr[(int64_t)k * B.n + i];
+                pres[k] = jk >= 0;
+                j[k] = pres[k] ? (uint32_t)jk : i;
+            }
+        } else {
+            const bool relc = B.ns == 1;
+            const PackedWords W = relc ? packed_words<true>(B.pk, i) : packed_words<false>(B.pk, i);
+            if (relc) packed_decode<true>(B.pk, i, W, j);
+            else packed_decode<false>(B.pk, i, W, j);
+#pragma unroll
+            for (int k = 0; k < 6; k++) pres[k] = j[k] != i;   // no periodic wrap in packed sources
+        }
+    }
+    double x[VG_NPOOL];
+#pragma unroll
+    for (int s = 0; s < VG_NPOOL; s++)
+        x[s] = reads<MODE, MOB, TOT>(s) ? comp_at(B.src[s], B.slo[s], i) : 0.0;
+    double acc[1][VG_NPOOL];
+#pragma unroll
+    for (int s = 0; s < VG_NPOOL; s++) acc[0][s] = (TOT == TOT_IN && act) ? x[s] : 0.0;
+    if (do_d) {
+        double w[6] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.0};
+        if (reg) {
+            const uint32_t code = at(B.rcode, i);
+            const uint32_t own = code & 7u;
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                const uint32_t other = own ^ (((code >> (3 + k)) & 1u) << (k >> 1));
+                w[k] = 0.5 * (cl[own] + cl[other]);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < VG_NPOOL; s++) {
+            if (!mobile<MOB>(s)) continue;
+            const double xi = x[s];
+            double v[6];
+#pragma unroll
+            for (int k = 0; k < 6; k++) v[k] = comp_at(B.src[s], B.slo[s], j[k]);
+            double d[6];
+#pragma unroll
+            for (int k = 0; k < 6; k++) d[k] = pres[k] ? (reg ? w[k] * (v[k] - xi) : v[k] - xi) : 0.0;
+            const double sum = ((d[0] + d[1]) + (d[2] + d[3])) + (d[4] + d[5]);
+            x[s] = xi + C.a[s] * sum;
+        }
+    }
+    if (TOT == TOT_MID && act) {
+#pragma unroll
+        for (int s = 0; s < VG_NPOOL; s++) acc[0][s] = x[s];
+    }
+    if (do_t) transform(C, x[0], x[1], x[2], x[3], x[4]);
+    if (TOT == TOT_OUT && act) {
+#pragma unroll
+        for (int s = 0; s < VG_NPOOL; s++) acc[0][s] = x[s];
+    }
+    if (MODE != MODE_NONE && act) {
+#pragma unroll
+        for (int s = 0; s < VG_NPOOL; s++) {
+            if (mobile<MOB>(s) || MODE != MODE_D) {
+                float hi;
+                int16_t lo;
+                comp_put(x[s], hi, lo);
+                at(B.dst[s], i) = hi;
+                at(B.dlo[s], i) = lo;
+            }
+        }
+    }
+    if constexpr (TOT != TOT_NONE) tile_totals(pc, tile, acc, part, lds);
+}
+
 // Rank-index variant (single volume: one piece per tile).  Each voxel has a
 // 32-bit geometry word (x | y << 10 | z << 20, and in raster order whether
 // its -x / +x neighbours are pore in bits 30 / 31: their compact indices are
@@ -1043,6 +1159,83 @@ __global__ __launch_bounds__(kBlock) void k_band2(StepBufs<R> B, Coef<R> C, Band
     }
 }
 
+template <int MODE, int MOB, int TOT>
+int launch_c(vg_sim *h, const CompBufs &B, const Coef<double> &C, hipStream_t s) {
+    Pieces pc{h->piece_first, h->piece_lo, h->piece_seg, h->npieces};
+    hipLaunchKernelGGL((k_step_c<MODE, MOB, TOT>), dim3((unsigned)h->ntiles), dim3(kBlock), 0, s, B, C, pc, h->part);
+    return launch_status("k_step_c");
+}
+
+template <int MODE, int MOB>
+int pick_tot_c(vg_sim *h, int tot, const CompBufs &B, const Coef<double> &C, hipStream_t s) {
+    switch (tot) {
+        case TOT_NONE: return launch_c<MODE, MOB, TOT_NONE>(h, B, C, s);
+        case TOT_IN: return launch_c<MODE, MOB, TOT_IN>(h, B, C, s);
+        case TOT_MID: return launch_c<MODE, MOB, TOT_MID>(h, B, C, s);
+        default: return launch_c<MODE, MOB, TOT_OUT>(h, B, C, s);
+    }
+}
+
+// A pass on compensated fields: the same buffer rotation as dispatch<R>, for
+// the float parts and the compensation words alike.
+int dispatch_c(vg_sim *h, int mode, int tot, double dt_t, double dt_d, hipStream_t s) {
+    CompBufs B;
+    B.nbr = h->nbr;
+    B.rcode = h->rcode;
+    B.pk = packed_of(h);
+    B.ns = use_relative(h) ? 1 : (use_offsets(h) ? 2 : 0);
+    B.n = h->n;
+    const int mob = h->mobile_mode();
+    for (int p = 0; p < VG_NPOOL; p++) {
+        const bool mob_p = mob == 2 || p == 1;
+        const int64_t off = (int64_t)p * h->n;
+        float *here = (float *)h->fields + off;
+        int16_t *here_lo = h->lo + off;
+        float *there = nullptr;
+        int16_t *there_lo = nullptr;
+        if (mob_p) {
+            there = (float *)h->alt + (mob == 2 ? off : 0);
+            there_lo = h->lo_alt + (mob == 2 ? off : 0);
+        }
+        const bool flip = mob_p && h->cur;
+        float *cur = flip ? there : here, *oth = flip ? here : there;
+        int16_t *cur_lo = flip ? there_lo : here_lo, *oth_lo = flip ? here_lo : there_lo;
+        const bool moves = mob_p && (mode == MODE_D || mode == MODE_DT);
+        B.src[p] = cur;
+        B.slo[p] = cur_lo;
+        B.dst[p] = moves ? oth : cur;
+        B.dlo[p] = moves ? oth_lo : cur_lo;
+    }
+    const Coef<double> C = make_coef2<double>(h, dt_t, dt_d);
+    int rc;
+    if (mode == MODE_T) rc = pick_tot_c<MODE_T, 1>(h, tot, B, C, s);
+    else if (mode == MODE_NONE) rc = launch_c<MODE_NONE, 1, TOT_IN>(h, B, C, s);
+    else if (mode == MODE_D) rc = mob == 2 ? pick_tot_c<MODE_D, 2>(h, tot, B, C, s) : pick_tot_c<MODE_D, 1>(h, tot, B, C, s);
+    else rc = mob == 2 ? pick_tot_c<MODE_DT, 2>(h, tot, B, C, s) : pick_tot_c<MODE_DT, 1>(h, tot, B, C, s);
+    if (rc) return rc;
+    if (mode == MODE_D || mode == MODE_DT) h->cur ^= 1;
+    return VG_OK;
+}
+
+// State conversions: x [5][n] of type X into the bound fields, or back.
+template <typename X, typename F>
+__global__ __launch_bounds__(kBlock) void k_load_state(const X *__restrict__ x, int64_t m, F f) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < m) f.put(i, (double)x[i]);
+}
+
+template <typename X, typename F>
+__global__ __launch_bounds__(kBlock) void k_store_state(X *__restrict__ x, int64_t m, F f) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < m) x[i] = (X)f.get(i);
+}
+
+// float parts of compensated fields as float (the exact values, no rounding)
+__global__ __launch_bounds__(kBlock) void k_store_hi(float *__restrict__ x, int64_t m, const float *__restrict__ hi) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < m) x[i] = hi[i];
+}
+
 template <typename R>
 int dispatch(vg_sim *h, int mode, int tot, double dt_t, double dt_d, hipStream_t s) {
     StepBufs<R> B = graph_bufs<R>(h);
@@ -1088,14 +1281,14 @@ bool use_relative(const vg_sim *h) {
 
 bool band_geometry(const vg_sim *h) {
     return (h->features & VG_FEAT_BAND) && h->nseg == 1 && h->vox != nullptr && h->brick == 0 &&
-           h->periodic == 0 && h->n > 0;
+           h->periodic == 0 && h->n > 0 && h->prec != VG_F32C;
 }
 
 // AUTO takes the band kernel for FP32 fields when its chunks are long enough
 // (in FP64 its LDS budget allows only narrow bands: slower than single
 // passes).
 bool use_band(const vg_sim *h) {
-    return h->band_ok && h->rel_ok &&
+    return h->band_ok && h->rel_ok && h->prec != VG_F32C &&
            (h->kernel == VG_KERNEL_BAND || (h->kernel == VG_KERNEL_AUTO && h->prec == VG_F32 && h->band_auto)) &&
            !h->mobile_all && h->rcode == nullptr && h->params.sequential == 0;
 }
@@ -1201,7 +1394,7 @@ bool use_offsets(const vg_sim *h) {
 }
 
 bool use_rank(const vg_sim *h) {
-    const bool ok = h->rank != nullptr && h->geo != nullptr && h->nseg == 1;
+    const bool ok = h->rank != nullptr && h->geo != nullptr && h->nseg == 1 && h->prec != VG_F32C;
     if (h->kernel == VG_KERNEL_RANK) return ok;
     return ok && h->kernel == VG_KERNEL_AUTO && !h->off_ok && !h->rel_ok;
 }
@@ -1277,6 +1470,7 @@ int launch_geometry(vg_sim *h, hipStream_t s) {
 
 int launch_pass2(vg_sim *h, int mode, int tot, double dt_t, double dt_d, hipStream_t s) {
     if (h->n == 0) return VG_OK;
+    if (h->prec == VG_F32C) return dispatch_c(h, mode, tot, dt_t, dt_d, s);
     if (h->prec == VG_F64) return dispatch<double>(h, mode, tot, dt_t, dt_d, s);
     return dispatch<float>(h, mode, tot, dt_t, dt_d, s);
 }
@@ -1316,6 +1510,46 @@ int launch_totals_finalize(vg_sim *h, double *out_rows, hipStream_t s) {
     return launch_status("k_tot_segments");
 }
 
+int launch_load_state(vg_sim *h, const void *x, int xprec, hipStream_t s) {
+    const int64_t m = (int64_t)VG_NPOOL * h->n;
+    if (m == 0) return VG_OK;
+    const dim3 grid((unsigned)((m + kBlock - 1) / kBlock));
+    if (h->prec == VG_F32C) {
+        const CompAcc f{(float *)h->fields, h->lo};
+        if (xprec == VG_F64) hipLaunchKernelGGL((k_load_state<double, CompAcc>), grid, dim3(kBlock), 0, s, (const double *)x, m, f);
+        else hipLaunchKernelGGL((k_load_state<float, CompAcc>), grid, dim3(kBlock), 0, s, (const float *)x, m, f);
+    } else if (h->prec == VG_F64) {
+        const PlainAcc<double> f{(double *)h->fields};
+        if (xprec == VG_F64) hipLaunchKernelGGL((k_load_state<double, PlainAcc<double>>), grid, dim3(kBlock), 0, s, (const double *)x, m, f);
+        else hipLaunchKernelGGL((k_load_state<float, PlainAcc<double>>), grid, dim3(kBlock), 0, s, (const float *)x, m, f);
+    } else {
+        const PlainAcc<float> f{(float *)h->fields};
+        if (xprec == VG_F64) hipLaunchKernelGGL((k_load_state<double, PlainAcc<float>>), grid, dim3(kBlock), 0, s, (const double *)x, m, f);
+        else hipLaunchKernelGGL((k_load_state<float, PlainAcc<float>>), grid, dim3(kBlock), 0, s, (const float *)x, m, f);
+    }
+    return launch_status("k_load_state");
+}
+
+int launch_store_state(vg_sim *h, void *x, int xprec, hipStream_t s) {
+    const int64_t m = (int64_t)VG_NPOOL * h->n;
+    if (m == 0) return VG_OK;
+    const dim3 grid((unsigned)((m + kBlock - 1) / kBlock));
+    if (h->prec == VG_F32C) {
+        const CompAcc f{(float *)h->fields, h->lo};
+        if (xprec == VG_F64) hipLaunchKernelGGL((k_store_state<double, CompAcc>), grid, dim3(kBlock), 0, s, (double *)x, m, f);
+        else hipLaunchKernelGGL(k_store_hi, grid, dim3(kBlock), 0, s, (float *)x, m, (const float *)h->fields);
+    } else if (h->prec == VG_F64) {
+        const PlainAcc<double> f{(double *)h->fields};
+        if (xprec == VG_F64) hipLaunchKernelGGL((k_store_state<double, PlainAcc<double>>), grid, dim3(kBlock), 0, s, (double *)x, m, f);
+        else hipLaunchKernelGGL((k_store_state<float, PlainAcc<double>>), grid, dim3(kBlock), 0, s, (float *)x, m, f);
+    } else {
+        const PlainAcc<float> f{(float *)h->fields};
+        if (xprec == VG_F64) hipLaunchKernelGGL((k_store_state<double, PlainAcc<float>>), grid, dim3(kBlock), 0, s, (double *)x, m, f);
+        else hipLaunchKernelGGL((k_store_state<float, PlainAcc<float>>), grid, dim3(kBlock), 0, s, (float *)x, m, f);
+    }
+    return launch_status("k_store_state");
+}
+
 // Mobile pools that currently live in the alt buffer are copied back to the
 // caller's field buffer, so the fields hold the state between calls.
 int restore_canonical(vg_sim *h, hipStream_t s) {
@@ -1323,6 +1557,13 @@ int restore_canonical(vg_sim *h, hipStream_t s) {
     const size_t e = h->elem();
     const int mob = h->mobile_mode();
     int rc;
+    if (h->prec == VG_F32C) {
+        const size_t cnt = (mob == 2 ? VG_NPOOL : 1) * (size_t)h->n;
+        const size_t at0 = mob == 2 ? 0 : (size_t)h->n;
+        if ((rc = hip_status(hipMemcpyAsync(h->lo + at0, h->lo_alt, sizeof(int16_t) * cnt, hipMemcpyDeviceToDevice, s),
+                             "restore compensation words")))
+            return rc;
+    }
     if (mob == 2) {
         rc = hip_status(hipMemcpyAsync(h->fields, h->alt, e * VG_NPOOL * (size_t)h->n, hipMemcpyDeviceToDevice, s),
                         "restore fields");

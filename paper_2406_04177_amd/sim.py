@@ -17,7 +17,8 @@ from . import _lib
 from .graph import Graph
 from .inputs import ModelParams
 
-_DTYPES = {"f32": torch.float32, "f64": torch.float64}
+_DTYPES = {"f32": torch.float32, "f64": torch.float64, "f32c": torch.float32}
+_PREC = {"f32": _lib.VG_F32, "f64": _lib.VG_F64, "f32c": _lib.VG_F32C}
 
 
 def to_vg_params(p: ModelParams, step_order: int = _lib.VG_ORDER_TD) -> _lib.VgParams:
@@ -56,7 +57,7 @@ class Simulation:
         desc = _lib.VgDesc()
         desc.n = graph.n
         desc.nseg = graph.nseg
-        desc.precision = _lib.VG_F64 if precision == "f64" else _lib.VG_F32
+        desc.precision = _PREC[precision]
         desc.seg_off = self._seg.ctypes.data
         desc.nbr_d = graph.nbr.data_ptr() if graph.n else None
         desc.rcode_d = graph.rcode.data_ptr() if (use_regions and graph.n) else None
@@ -111,8 +112,27 @@ class Simulation:
         self.regions = list(map(float, c))
 
     def set_fields(self, x: torch.Tensor):
-        """Copy a [5, n] tensor into the bound fields."""
+        """Copy a [5, n] tensor into the bound fields.  Compensated fields
+        ("f32c") take a float64 state at their full precision (vg_load_state)."""
+        if self.precision == "f32c":
+            src = x.to(device=self.fields.device)
+            if src.dtype != torch.float32:
+                src = src.to(torch.float64)
+            src = src.contiguous()
+            prec = _lib.VG_F64 if src.dtype == torch.float64 else _lib.VG_F32
+            _lib.check(self.L.vg_load_state(self.h, src.data_ptr(), prec, self._sp()), "vg_load_state")
+            if self.stream is not None:     # src belongs to the current stream
+                self.stream.synchronize()
+            return
         self.fields.copy_(x.to(device=self.fields.device, dtype=self.dtype))
+
+    def state(self, dtype=torch.float64) -> torch.Tensor:
+        """The bound state as a new [5, n] tensor (float64: for compensated
+        fields the full-precision value, vg_store_state)."""
+        out = torch.empty((5, self.graph.n), dtype=dtype, device=self.fields.device)
+        prec = _lib.VG_F64 if dtype == torch.float64 else _lib.VG_F32
+        _lib.check(self.L.vg_store_state(self.h, out.data_ptr(), prec, self._sp()), "vg_store_state")
+        return out
 
     def close(self):
         if getattr(self, "h", None) is not None:
