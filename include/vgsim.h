@@ -202,6 +202,20 @@ int vg_pngm_implicit_step(const double *m_d, double *out_d, int64_t q, const dou
                           const int32_t *col_d, const double *theta_d, double c, double rtol, int max_iter,
                           double *work_d, int *iters_out, double *relres_out, void *stream);
 
+/* For callers that cannot allocate device memory (or hand the library a
+ * scratch buffer): vg_pngm_implicit_step with its 3 q + 2 FP64 scratch
+ * entries in a static device array of the library instead of work_d, so the
+ * call allocates nothing.  Same kernels, same results.  q is at most
+ * VG_PNGM_NOALLOC_MAX_Q (larger q returns VG_EINVAL); the array
+ * (3 * 65536 + 2 doubles, 1.5 MiB) exists once per GPU and is held until the
+ * process ends.  All calls on one GPU share it: calls that overlap on one GPU
+ * (other streams or host threads) race.  Nothing in it needs to start at
+ * zero: every entry is written before it is read. */
+#define VG_PNGM_NOALLOC_MAX_Q 65536
+int vg_pngm_implicit_step_noalloc(const double *m_d, double *out_d, int64_t q, const double *v_d,
+                                  const int64_t *row_d, const int32_t *col_d, const double *theta_d, double c,
+                                  double rtol, int max_iter, int *iters_out, double *relres_out, void *stream);
+
 /* The normalised-gradient step of Sec. V.A on count parameters:
  * theta_e <- clamp(theta_e - lr * scale_e * sign(grad_e), lo_e, hi_e), no move
  * for a zero derivative (FP64 device arrays). */

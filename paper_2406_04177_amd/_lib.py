@@ -22,10 +22,12 @@ VG_FEAT_CG, VG_FEAT_ADJ, VG_FEAT_BAND = 1, 2, 4
 VG_NPOOL, VG_NREG, VG_NGRAD = 5, 8, 20
 VG_KERNEL_AUTO, VG_KERNEL_TABLE, VG_KERNEL_RANK, VG_KERNEL_OFFSET, VG_KERNEL_RELATIVE, VG_KERNEL_BAND = 0, 1, 2, 3, 4, 5
 VG_ADJ_SKIP_STATIC_D = 1
+VG_PNGM_NOALLOC_MAX_Q = 65536
 
 EXPORTS = ("vg_strerror", "vg_last_error", "vg_version", "vg_rank_bytes", "vg_count_pores",
            "vg_build_graph", "vg_lookup", "vg_region_codes", "vg_range_sums",
-           "vg_brick_stats", "vg_pngm_loss_grad", "vg_pngm_step", "vg_pngm_implicit_step", "vg_sign_update", "vg_create", "vg_destroy",
+           "vg_brick_stats", "vg_pngm_loss_grad", "vg_pngm_step", "vg_pngm_implicit_step",
+           "vg_pngm_implicit_step_noalloc", "vg_sign_update", "vg_create", "vg_destroy",
            "vg_set_kernel", "vg_get_kernel", "vg_set_adjoint_options", "vg_set_params", "vg_set_regions", "vg_alt_elems", "vg_workspace_bytes", "vg_init_state",
            "vg_step_explicit", "vg_step_subcycled", "vg_solve_implicit_step", "vg_mass_totals", "vg_record", "vg_adjoint",
            "vg_seed_lambda", "vg_load_state", "vg_store_state")
@@ -82,6 +84,7 @@ def load():
             "vg_pngm_loss_grad": (I, [P, P, I64, I64, P, P, P, P, D, I, P, P, P, P]),
             "vg_pngm_step": (I, [P, P, I64, P, P, P, P, D, P]),
             "vg_pngm_implicit_step": (I, [P, P, I64, P, P, P, P, D, D, I, P, P, P, P]),
+            "vg_pngm_implicit_step_noalloc": (I, [P, P, I64, P, P, P, P, D, D, I, P, P, P]),
             "vg_sign_update": (I, [P, P, I64, D, P, P, P, P]),
             "vg_create": (I, [ctypes.POINTER(VgDesc), ctypes.POINTER(P)]),
             "vg_destroy": (I, [P]),

@@ -17,6 +17,7 @@
 // one parameter per ordered pair; dL2/dtheta carries the minus sign of
 // d r2 / d theta, which the printed formula drops.
 #include <cmath>
+#include <mutex>
 
 #include "vg_internal.h"
 
@@ -239,16 +240,15 @@ extern "C" int vg_pngm_step(const double *m_d, double *out_d, int64_t q, const d
     return launch_status("k_pngm_step");
 }
 
-extern "C" int vg_pngm_implicit_step(const double *m_d, double *out_d, int64_t q, const double *v_d,
-                                     const int64_t *row_d, const int32_t *col_d, const double *theta_d, double c,
-                                     double rtol, int max_iter, double *work_d, int *iters_out, double *relres_out,
-                                     void *stream) {
-    if (q < 0 || !std::isfinite(c) || c < 0 || !(rtol > 0) || max_iter < 1 || !iters_out || !relres_out ||
-        (q > 0 && (!m_d || !out_d || !v_d || !row_d || !col_d || !theta_d || !work_d || out_d == m_d ||
-                   (out_d < work_d + 3 * q + 2 && work_d < out_d + q)))) {
-        set_error("bad PNGM implicit-step arguments");
-        return VG_EINVAL;
-    }
+namespace {
+
+// The implicit PNGM step with its 3 q + 2 FP64 scratch entries at work_d
+// (arguments already checked): sa, sb (concentration iterates), the row
+// residuals and two scalars.  Every entry is written before it is read, so
+// the scratch needs no clearing.
+int pngm_implicit(const double *m_d, double *out_d, int64_t q, const double *v_d, const int64_t *row_d,
+                  const int32_t *col_d, const double *theta_d, double c, double rtol, int max_iter, double *work_d,
+                  int *iters_out, double *relres_out, void *stream) {
     *iters_out = 0;
     *relres_out = 0.0;
     if (q == 0) return VG_OK;
@@ -304,6 +304,80 @@ extern "C" int vg_pngm_implicit_step(const double *m_d, double *out_d, int64_t q
         return VG_ENOCONV;
     }
     return VG_OK;
+}
+
+bool pngm_implicit_args_ok(const double *m_d, const double *out_d, int64_t q, const double *v_d,
+                           const int64_t *row_d, const int32_t *col_d, const double *theta_d, double c, double rtol,
+                           int max_iter, const int *iters_out, const double *relres_out) {
+    return !(q < 0 || !std::isfinite(c) || c < 0 || !(rtol > 0) || max_iter < 1 || !iters_out || !relres_out ||
+             (q > 0 && (!m_d || !out_d || !v_d || !row_d || !col_d || !theta_d || out_d == m_d)));
+}
+
+// Scratch of vg_pngm_implicit_step_noalloc: a file-scope device array, one
+// copy per GPU the library runs on, held until the process ends.  In host
+// code its name is only a stand-in; the device address of each GPU's copy is
+// looked up once per device (that device current) and kept.
+static __device__ __align__(256) double scratch[3 * VG_PNGM_NOALLOC_MAX_Q + 2];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_of_current_device(double **out) {
+    int dev = -1;
+    int rc = hip_status(hipGetDevice(&dev), "hipGetDevice");
+    if (rc) return rc;
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device %d beyond the %d devices the static scratch tracks", dev, kMaxDevices);
+        return VG_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        double *p = nullptr;
+        rc = hip_status(hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (rc) return rc;
+        if (!p) {
+            set_error("hipGetSymbolAddress(scratch) returned a null address");
+            return VG_EHIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return VG_OK;
+}
+
+}  // namespace
+
+extern "C" int vg_pngm_implicit_step(const double *m_d, double *out_d, int64_t q, const double *v_d,
+                                     const int64_t *row_d, const int32_t *col_d, const double *theta_d, double c,
+                                     double rtol, int max_iter, double *work_d, int *iters_out, double *relres_out,
+                                     void *stream) {
+    if (!pngm_implicit_args_ok(m_d, out_d, q, v_d, row_d, col_d, theta_d, c, rtol, max_iter, iters_out, relres_out) ||
+        (q > 0 && (!work_d || (out_d < work_d + 3 * q + 2 && work_d < out_d + q)))) {
+        set_error("bad PNGM implicit-step arguments");
+        return VG_EINVAL;
+    }
+    return pngm_implicit(m_d, out_d, q, v_d, row_d, col_d, theta_d, c, rtol, max_iter, work_d, iters_out, relres_out,
+                         stream);
+}
+
+extern "C" int vg_pngm_implicit_step_noalloc(const double *m_d, double *out_d, int64_t q, const double *v_d,
+                                             const int64_t *row_d, const int32_t *col_d, const double *theta_d,
+                                             double c, double rtol, int max_iter, int *iters_out, double *relres_out,
+                                             void *stream) {
+    if (!pngm_implicit_args_ok(m_d, out_d, q, v_d, row_d, col_d, theta_d, c, rtol, max_iter, iters_out, relres_out)) {
+        set_error("bad PNGM implicit-step arguments");
+        return VG_EINVAL;
+    }
+    if (q > VG_PNGM_NOALLOC_MAX_Q) {
+        set_error("q = %lld primitives exceeds the static scratch (at most %d)", (long long)q, VG_PNGM_NOALLOC_MAX_Q);
+        return VG_EINVAL;
+    }
+    double *work = nullptr;
+    int rc = scratch_of_current_device(&work);
+    if (rc) return rc;
+    return pngm_implicit(m_d, out_d, q, v_d, row_d, col_d, theta_d, c, rtol, max_iter, work, iters_out, relres_out,
+                         stream);
 }
 
 extern "C" int vg_sign_update(double *theta_d, const double *grad_d, int64_t count, double lr, const double *scale_d,
