@@ -48,6 +48,10 @@ BYTES_RELATIVE_F32 = 5 * 4 + 5 * 4 + 4 + 32.0 / 64
 # neighbour rows (band of 8 rows: 10/8 of the voxels), the second pass reads
 # four pools and the code word again and writes the five pools; per step half
 BYTES_BAND_F32 = (10.0 / 8 * (4 * 4 + 4 + 32.0 / 64) + (4 * 4 + 4 + 32.0 / 64) + 5 * 4) / 2
+# compensated FP32 fields (float + 16-bit word per value), relative codes:
+# six bytes per pool read and written, the code word and the group bases
+BYTES_COMP_RELATIVE = 5 * 6 + 5 * 6 + 4 + 32.0 / 64
+BYTES_F64_RELATIVE = 5 * 8 + 5 * 8 + 4 + 32.0 / 64
 KERNEL_NAMES = {1: "table", 2: "rank", 3: "offset", 4: "relative", 5: "band"}
 KERNEL_FUNCS = {1: "k_step (6-slot table)", 2: "k_step_geo (rank index)", 3: "k_step_off (packed offsets)",
                 4: "k_step_off (relative codes)",
@@ -96,18 +100,97 @@ def timed(fn, stream=None):
     return e0.elapsed_time(e1), out
 
 
-def cpu_baseline(mask, spec, params, dt, steps):
-    """The FP64 oracle on the host cores, on the first `steps` steps."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _omp_threads(k=None):
+    """OpenMP threads of this process's runtime (the oracle's): read, or set
+    to k (the oracle is built with -fopenmp and runs its loops on the calling
+    thread's team)."""
+    import ctypes
+    gomp = ctypes.CDLL("libgomp.so.1")
+    if k is not None:
+        gomp.omp_set_num_threads(int(k))
+    return int(gomp.omp_get_max_threads())
+
+
+def oracle_gradient_seconds(steps=200, K=20):
+    """The oracle's FP64 discrete-adjoint gradient of a CO2-curve loss on the
+    16 x 128^3 gradient workload (region factors, seeds on every step's CO2
+    totals), checkpointed every K steps: forward to every checkpoint, then per
+    segment (last first) its states and the reverse sweep."""
+    import numpy as np
+    from oracle import oracle as orc
+    from paper_2406_04177_amd import inputs
+    masks, specs = inputs.workload_inputs("b16x128")
+    params = inputs.ModelParams()
+    dt = inputs.explicit_dt(params, 0.8)
+    og = orc.build_batch(masks)
+    reg = orc.octant_regions(og)
+    w = orc.edge_weights(og, reg, [1.0] * 8)
+    x0 = orc.fields_from_spec(og, specs)
+    seeds = np.zeros((steps + 1, og.nseg, 5))
+    seeds[:, :, 4] = 1.0 / ((steps + 1) * og.nseg)       # d(mean CO2 total) / d(CO2 total)
+    t0 = time.perf_counter()
+    ckpts, x = [], x0
+    for k0 in range(0, steps, K):
+        k = min(K, steps - k0)
+        ckpts.append((k0, k, x))
+        x, _ = orc.run(params, dt, og, x, k, w=w, with_totals=False)
+    lam, grad = None, np.zeros(20)
+    for k0, k, xc in reversed(ckpts):
+        st = orc.run_states(params, dt, og, xc, k, w=w)
+        sd = seeds[k0:k0 + k + 1].copy()
+        if k0 + k != steps:
+            sd[-1] = 0.0
+        lam, gr = orc.adjoint(params, dt, og, st, sd, w=w, region=reg, nreg=8, lam_final=lam)
+        grad += gr
+        del st
+    return time.perf_counter() - t0, og.n
+
+
+def cpu_baseline(mask, spec, params, dt, steps, steps_1t, grad_steps):
+    """The FP64 oracle on the host cores: the first `steps` steps of the
+    workload on all threads and `steps_1t` on one, and its checkpointed
+    discrete-adjoint gradient of the gradient workload over `grad_steps`
+    steps (checkpoints every 20; its reverse sweep is a plain serial loop:
+    200 steps take about two minutes, so the default sample is 40)."""
     from oracle import oracle as orc
     og = orc.build_graph(mask)
+    n = og.n
     x0 = orc.fields_from_spec(og, spec)
+    threads = _omp_threads()
     t0 = time.perf_counter()
     orc.run(params, dt, og, x0, steps, with_totals=False)
     sec = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", 0)) or os.cpu_count()
-    return {"value": 5.0 * og.n * steps / sec, "unit": "pore-voxel species updates/s", "cores": cores,
-            "kind": "oracle",
-            "sample": "%d explicit steps of the same 512^3 workload (n = %d), FP64, %.1f s" % (steps, og.n, sec)}
+    _omp_threads(1)
+    t0 = time.perf_counter()
+    orc.run(params, dt, og, x0, steps_1t, with_totals=False)
+    sec1 = time.perf_counter() - t0
+    _omp_threads(threads)
+    del x0, og
+    gsec, gn = oracle_gradient_seconds(grad_steps)
+    return {"value": 5.0 * n * steps / sec,
+            "unit": "pore-voxel species updates/s", "cores": threads, "kind": "oracle",
+            "sample": "%d explicit steps of the same 512^3 workload, FP64, %.1f s on %d threads"
+                      % (steps, sec, threads),
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+            "one_thread": {"value": 5.0 * n * steps_1t / sec1, "unit": "pore-voxel species updates/s",
+                           "sample": "%d explicit steps, FP64, %.1f s on 1 thread" % (steps_1t, sec1)},
+            "gradient_16x128": {"seconds": gsec, "steps": grad_steps, "checkpoint_every": 20, "n_pore_voxels": gn,
+                                "seconds_per_step": gsec / grad_steps,
+                                "threads": threads,
+                                "what": "FP64 discrete-adjoint gradient of a CO2-curve loss (20 parameters), "
+                                        "checkpointed forward + reverse sweep"}}
 
 
 def step_1024(steps=101):
@@ -184,8 +267,22 @@ def copy_1gib():
     return {"bytes_per_copy": 2 * 4 * (1 << 28), "GBs": 2 * 4 * (1 << 28) * 10 / (ms / 1e3) / 1e9}
 
 
-def accuracy_256(steps, N=256):
+def _errors_vs(ref_x, ref_t, x, t):
+    """Per-pool field errors (relative to each pool's max) and per-curve
+    totals errors (relative per logged point) against a reference run."""
     import numpy as np
+    names = ("MB", "DOM", "SOM", "P4", "CO2")
+    fe = {names[s]: float(np.abs(x[s] - ref_x[s]).max() / max(np.abs(ref_x[s]).max(), 1e-300)) for s in range(5)}
+    curves = names + ("total",)
+    te = {curves[s]: float((np.abs(t[:, s] - ref_t[:, s]) / np.maximum(np.abs(ref_t[:, s]), 1e-300)).max())
+          for s in range(6)}
+    return fe, te
+
+
+def precision_runs(N, steps, log_every=100, precs=("f32", "f32c", "f64")):
+    """The same explicit run in each precision on the N^3 workload: time per
+    step and the final state (FP64) with the totals log.  Each run is timed
+    as one call of `steps` steps (totals every `log_every`)."""
     import torch
     from paper_2406_04177_amd import inputs
     from paper_2406_04177_amd.graph import Graph
@@ -195,33 +292,52 @@ def accuracy_256(steps, N=256):
     params = inputs.ModelParams()
     dt = inputs.explicit_dt(params, 0.9)
     g = Graph.from_masks(mask)
-    res = {"workload": "%d^3 17%% porosity, %d explicit steps, totals every 100" % (N, steps), "n_pore_voxels": g.n}
+    x0 = g.fields_from_specs(spec, torch.float64)
     out = {}
-    for prec, dtype in (("f32", torch.float32), ("f64", torch.float64)):
+    for prec in precs:
         sim = Simulation(g, params, precision=prec, implicit=False)
-        sim.set_fields(g.fields_from_specs(spec, torch.float64).to(dtype))
-        sim.step(100, dt)
-        sim.set_fields(g.fields_from_specs(spec, torch.float64).to(dtype))
+        sim.set_fields(x0)
+        sim.step(20, dt)
+        sim.set_fields(x0)
         c0 = sim.totals()[0, 5]
-        ms, logt = timed(lambda: sim.step(steps, dt, log_every=100))
-        out[prec] = (sim.fields.double().cpu().numpy(), logt[:, 0, :].cpu().numpy(), c0)
-        res["%s_ms_per_step" % prec] = ms / steps
+        ms, logt = timed(lambda: sim.step(steps, dt, log_every=log_every))
+        out[prec] = {"ms_per_step": ms / steps, "x": sim.state().cpu().numpy(), "log": logt[:, 0, :].cpu().numpy(),
+                     "c0": c0, "kernel": KERNEL_NAMES[sim.kernel_in_use()]}
+        log("%d^3 %s: %d steps in %.1f s (%.4f ms/step, %s kernel)" % (N, prec, steps, ms / 1e3, ms / steps,
+                                                                     out[prec]["kernel"]))
         del sim
-    (x32, t32, c32), (x64, t64, c64) = out["f32"], out["f64"]
-    names = ("MB", "DOM", "SOM", "P4", "CO2")
-    res["field_rel_err"] = {names[s]: float(np.abs(x32[s] - x64[s]).max() / max(np.abs(x64[s]).max(), 1e-300))
-                            for s in range(5)}
-    curves = names + ("total",)
-    res["totals_curve_rel_err"] = {curves[s]: float((np.abs(t32[:, s] - t64[:, s])
-                                                     / np.maximum(np.abs(t64[:, s]), 1e-300)).max())
-                                   for s in range(6)}
-    res["total_carbon_drift_f64"] = float(np.abs(t64[:, 5] - c64).max() / c64)
-    res["total_carbon_drift_f32"] = float(np.abs(t32[:, 5] - c32).max() / c32)
-    res["fp32_speedup"] = res["f64_ms_per_step"] / res["f32_ms_per_step"]
-    res["reference"] = "the FP64 GPU step (bit-identical to the FP64 oracle)"
-    log("256^3 accuracy: FP32 %.4f ms/step, FP64 %.4f ms/step, field errors %s"
-        % (res["f32_ms_per_step"], res["f64_ms_per_step"],
-           ", ".join("%s %.1e" % kv for kv in res["field_rel_err"].items())))
+        torch.cuda.empty_cache()
+    return g.n, out
+
+
+def accuracy_runs(N, steps, label):
+    """FP32 and compensated-FP32 fields against the FP64 step (itself
+    bit-identical to the FP64 oracle) on the N^3 workload: error per species
+    (fields) and per totals curve, carbon drift, time per step."""
+    import numpy as np
+    n, out = precision_runs(N, steps)
+    ref = out["f64"]
+    res = {"workload": "%d^3 17%% porosity, %d explicit steps, totals every 100 (%s)" % (N, steps, label),
+           "n_pore_voxels": n, "reference": "the FP64 GPU step (bit-identical to the FP64 oracle)"}
+    for prec in ("f32", "f32c", "f64"):
+        r = out[prec]
+        res["%s_ms_per_step" % prec] = r["ms_per_step"]
+        res["%s_kernel" % prec] = r["kernel"]
+        res["total_carbon_drift_%s" % prec] = float(np.abs(r["log"][:, 5] - r["c0"]).max() / r["c0"])
+        if prec != "f64":
+            fe, te = _errors_vs(ref["x"], ref["log"], r["x"], r["log"])
+            res["%s_field_rel_err" % prec] = fe
+            res["%s_totals_curve_rel_err" % prec] = te
+            res["%s_max_err" % prec] = max(max(fe.values()), max(te.values()))
+            res["%s_meets_1e-5" % prec] = res["%s_max_err" % prec] <= 1e-5
+    res["f32c_own_bytes_per_voxel_step"] = BYTES_COMP_RELATIVE
+    res["f32c_achieved_GBs_own"] = BYTES_COMP_RELATIVE * n / (res["f32c_ms_per_step"] / 1e3) / 1e9
+    res["f64_achieved_GBs_own"] = BYTES_F64_RELATIVE * n / (res["f64_ms_per_step"] / 1e3) / 1e9
+    res["fp32_speedup_over_fp64"] = res["f64_ms_per_step"] / res["f32_ms_per_step"]
+    res["f32c_speedup_over_fp64"] = res["f64_ms_per_step"] / res["f32c_ms_per_step"]
+    log("%d^3 x %d accuracy: FP32 %.4f ms/step max err %.1e, compensated %.4f ms/step max err %.1e, FP64 %.4f ms/step"
+        % (N, steps, res["f32_ms_per_step"], res["f32_max_err"], res["f32c_ms_per_step"], res["f32c_max_err"],
+           res["f64_ms_per_step"]))
     return res
 
 
@@ -436,7 +552,12 @@ def main(argv=None):
     ap.add_argument("--quick", action="store_true", help="headline only (no extra rows, no CPU baseline)")
     ap.add_argument("--cpu-steps", type=int, default=450,
                     help="steps of the oracle CPU baseline (about 10-15 s on 16 cores)")
-    ap.add_argument("--acc-steps", type=int, default=10000, help="steps of the 256^3 FP32-vs-FP64 row")
+    ap.add_argument("--acc-steps", type=int, default=10000, help="steps of the 256^3 precision row")
+    ap.add_argument("--long-steps", type=int, default=100000,
+                    help="steps of the 512^3 precision row (FP32, compensated FP32, FP64; 0: skip)")
+    ap.add_argument("--cpu-steps-1t", type=int, default=20, help="steps of the one-thread oracle sample")
+    ap.add_argument("--cpu-grad-steps", type=int, default=40,
+                    help="steps of the oracle's gradient sample on the 16 x 128^3 workload (200 take ~2 min)")
     ap.add_argument("--grad-steps", type=int, default=2000, help="steps of the 16 x 128^3 gradient row")
     ap.add_argument("--fit-epochs", type=int, default=30, help="epochs of the 16 x 128^3 fitting row (0: skip)")
     ap.add_argument("--zlayer", type=int, default=1, help="run the 512^3 z-layer diffusion comparison (0: skip)")
@@ -481,8 +602,10 @@ def main(argv=None):
     sim.set_fields(x0)
     sim.step(args.warmup, dt, log_every=100)
     K = args.steps
-    tot_log = torch.empty((max(K // 100, 1), g.nseg, 6), dtype=torch.float64, device="cuda")
-    ms, _ = timed(lambda: sim.step(K, dt, log_every=100, totals_out=tot_log if K >= 100 else None))
+    # FP64 totals every 100 steps, or once at the end of a shorter timed run
+    every = min(100, K)
+    tot_log = torch.empty((K // every, g.nseg, 6), dtype=torch.float64, device="cuda")
+    ms, _ = timed(lambda: sim.step(K, dt, log_every=every, totals_out=tot_log))
     ms_step = ms / K
     vps = n * K / (ms / 1e3)
     # the dominant kernel's own average launch time: K2 = 4 m + 1 paper steps
@@ -515,12 +638,14 @@ def main(argv=None):
         "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "%d^3 17%% porosity explicit step, FP32 fields, FP64 totals every 100 steps" % N,
+        "config": {"workload": "%d^3 17%% porosity explicit step, FP32 fields, FP64 totals every %d steps"
+                               % (N, every),
                    "shape": [N, N, N], "n_pore_voxels": n, "dt_s": dt, "order": "transformation then diffusion",
                    "voxel_steps_per_s": vps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_GBs": None if traffic is None else traffic / (us_launch / 1e6) / 1e9,
+                     "traffic_frac": None if traffic is None else traffic / (us_launch / 1e6) / 1e9 / HBM_PEAK_GBS,
                      "kernel": "%s, FP32, DOM-only diffusion (fused transformation + diffusion)" % kname,
                      "neighbour_source": KERNEL_NAMES[kernel],
                      "launch_us": us_launch, "passes_per_launch": ppl, "bytes_per_voxel_step": bpv,
@@ -630,18 +755,23 @@ def main(argv=None):
         out["adjoint_forward_ratio"] = rows["a6_gradient_16x128"]["gradient_forward_ratio_all_d"]
         del sima, states, lam
         torch.cuda.empty_cache()
-        # FP32 fields + FP64 totals against the plain FP64 step on the 256^3
-        # workload: 10^4 steps, totals every 100, error per species (fields,
-        # relative to each pool's max) and per totals curve (relative per point)
-        rows["fp32_vs_fp64_256"] = accuracy_256(args.acc_steps)
+        # FP32 and compensated FP32 fields (FP64 totals) against the plain
+        # FP64 step: the 256^3 workload at its length (10^4 steps) and the
+        # 512^3 one at its (10^5 steps), totals every 100, error per species
+        # (fields, relative to each pool's max) and per totals curve
+        rows["precision_256"] = accuracy_runs(256, args.acc_steps, "FP32 vs FP64 workload")
+        if args.long_steps > 0:
+            rows["precision_512_long"] = accuracy_runs(N, args.long_steps, "full-size decomposition run")
         rows["copy_1GiB"] = copy_1gib()
         log("plain 1 GiB device copy: %.0f GB/s (read + written)" % rows["copy_1GiB"]["GBs"])
         if args.big:
             rows["explicit_1024"] = step_1024()
         # CPU baseline: the oracle on the host cores
-        cb = cpu_baseline(mask, spec, params, dt, args.cpu_steps)
+        cb = cpu_baseline(mask, spec, params, dt, args.cpu_steps, args.cpu_steps_1t, args.cpu_grad_steps)
         out["cpu_baseline"] = cb
-        log("cpu baseline: %.3e species updates/s on %d cores" % (cb["value"], cb["cores"]))
+        log("cpu baseline (%s): %.3e species updates/s on %d threads, %.3e on 1; oracle gradient "
+            "(16 x 128^3, %d steps) %.1f s" % (cb["cpu_model"], cb["value"], cb["cores"], cb["one_thread"]["value"],
+                                              args.cpu_grad_steps, cb["gradient_16x128"]["seconds"]))
     # the paper's own timing, other hardware (context only, not a target):
     # Table 1 test 2, explicit 0.1 s steps for 5 days on the 512^3 image
     # (about 0.17 x 512^3 pore voxels) in 7.9 days on a laptop CPU
@@ -651,6 +781,13 @@ def main(argv=None):
                             "source": "Table 1, test 2 (explicit 0.1 s, 5 simulated days, 7.9 days wall time)",
                             "gpu_over_paper": 5.0 * vps / (5.0 * paper_vps)}
     print(json.dumps(out), flush=True)
+    try:   # nothing here starts processes; report any that would outlive the run
+        import psutil
+        kids = psutil.Process().children(recursive=True)
+        if kids:
+            log("child processes at exit: %s" % [(k.pid, k.name()) for k in kids])
+    except Exception:
+        pass
     if args.calibrate_copy:
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)

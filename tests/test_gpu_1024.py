@@ -146,3 +146,53 @@ def test_adjoint_first_200_steps(big):
         errs[q] = abs(grad[q] - fd) / abs(fd)
     print("1024^3 adjoint (FP32) vs FD (FP64), relative:", errs, flush=True)
     assert max(errs.values()) <= 1e-3, errs
+
+
+def _band_against_oracle(mask, spec, label):
+    """Raster order and the band kernel that AUTO takes for FP32 (the
+    benchmark's launch configuration), uint32 indices and byte offsets at this
+    n: 21 FP32 steps (a transformation pass, five runs of four fused passes as
+    ten band launches, a diffusion pass) bit for bit equal to the same steps
+    in single passes with the relative codes, and within 1e-5 per pool of the
+    oracle; 5 FP64 steps with the relative codes bit for bit against the
+    oracle (the FP64 band kernel needs more LDS than a block has at this
+    width, so FP64 runs single passes here)."""
+    from paper_2406_04177_amd.graph import Graph
+    from paper_2406_04177_amd.sim import Simulation
+    g = Graph.from_masks(mask)
+    print(label, "raster: n =", g.n, flush=True)
+    assert Simulation(g, inputs.ModelParams(), precision="f32", implicit=False).kernel_in_use() == 5
+    og = orc.build_graph(mask)
+    p = inputs.ModelParams()
+    dt = inputs.explicit_dt(p)
+    x0 = orc.fields_from_spec(og, spec)
+    ref, _ = orc.run(p, dt, og, x0, 5, with_totals=False)
+    got, _ = run(g, spec, "f64", RELATIVE, 5)
+    np.testing.assert_array_equal(got, ref)
+    del got
+    ref, _ = orc.run(p, dt, og, x0, 21, with_totals=False)
+    got, _ = run(g, spec, "f32", 5, 21)
+    single, _ = run(g, spec, "f32", RELATIVE, 21)
+    np.testing.assert_array_equal(got, single)
+    del single
+    errs = []
+    for s in range(5):
+        scale = np.abs(ref[s]).max()
+        errs.append(float(np.abs(got[s].astype(np.float64) - ref[s]).max() / scale) if scale > 0
+                    else float(np.abs(got[s]).max()))
+    print(label, "band kernel FP32 after 21 steps, per pool:", errs, flush=True)
+    assert max(errs) <= 1e-5, errs
+
+
+def test_band_kernel_raster_1024(big):
+    mask, spec, _ = big
+    _band_against_oracle(mask, spec, "1024^3")
+
+
+def test_band_kernel_slab_of_eight(big):
+    """One GPU's share of the volume split into eight z-slabs, as the
+    benchmark's slab row times it: the first 128 planes as a volume of their
+    own (closed faces)."""
+    mask, _, _ = big
+    slab = np.ascontiguousarray(mask[:128])
+    _band_against_oracle(slab, inputs.init_uniform(slab, seed=0), "1024x1024x128")
