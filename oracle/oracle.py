@@ -25,7 +25,11 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "vg_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# VG_ORACLE_SANITIZE=1 (the sanitizer test, with the runtimes preloaded)
+# builds and loads a copy under AddressSanitizer and UndefinedBehaviorSanitizer
+_SANITIZE = os.environ.get("VG_ORACLE_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "liboracle_san.so" if _SANITIZE else "liboracle.so")
+_SAN_FLAGS = ["-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
 _lock = threading.Lock()
 _lib = None
 
@@ -40,8 +44,9 @@ def build(force: bool = False) -> str:
     so every operation rounds exactly as written)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
-               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        opt = _SAN_FLAGS if _SANITIZE else ["-O2"]
+        cmd = ["gcc"] + opt + ["-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB

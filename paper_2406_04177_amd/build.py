@@ -35,8 +35,10 @@ FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-ffp-contract=o
          "-Wno-unused-command-line-argument"]
 
 
-def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
-    """Compile every source to an object (in parallel), then link the library."""
+def build(verbose: bool = False, out: str = LIB, defines=(), extra_flags=()) -> str:
+    """Compile every source to an object (in parallel), then link the library.
+    ``extra_flags`` go to every compile (e.g. host-side sanitizers, each
+    behind ``-Xarch_host``)."""
     objdir = os.path.join(os.path.dirname(out), "_build") if out != LIB else os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
@@ -44,7 +46,8 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     for src in SOURCES:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
-        cmd = [hipcc()] + FLAGS + ["-D%s" % d for d in defines] + inc + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = ([hipcc()] + FLAGS + list(extra_flags) + ["-D%s" % d for d in defines] + inc
+               + ["-c", os.path.join(CSRC, src), "-o", obj])
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd)))

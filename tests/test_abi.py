@@ -278,3 +278,59 @@ def test_band_feature_workspace():
     assert ws(_lib.VG_FEAT_BAND, brick=8) == ws(0, brick=8)
     assert ws(_lib.VG_FEAT_BAND, periodic=1) == ws(0, periodic=1)
     assert ws(_lib.VG_FEAT_BAND, rank=False) == ws(0, rank=False)
+
+
+def test_batches_with_empty_volumes_every_precision():
+    """Descriptors of batches whose volumes are empty, smaller than a tile or
+    span several tiles, for every precision and feature set: the piece tables
+    and workspace layout are built on the host (exercised under the
+    sanitizers too); compensated fields add 12 B per voxel of compensation
+    words (2 B per pool, 2 B for the diffusing pool's ping-pong) and refuse
+    the adjoint."""
+    L = _lib.load()
+    layouts = ([0, 0, 300, 300, 1000, 70000], [0, 1], [0, 256, 512, 768], [0, 0, 0, 5, 5, 100001])
+    for offs in layouts:
+        seg = np.array(offs, np.int64)
+        sizes = {}
+        for prec in (_lib.VG_F32, _lib.VG_F64, _lib.VG_F32C):
+            for feat in (0, _lib.VG_FEAT_CG, _lib.VG_FEAT_ADJ, _lib.VG_FEAT_CG | _lib.VG_FEAT_ADJ):
+                for mob in (0, 1):
+                    desc = _lib.VgDesc()
+                    desc.n, desc.nseg, desc.precision = int(seg[-1]), len(seg) - 1, prec
+                    desc.seg_off = seg.ctypes.data
+                    desc.nbr_d = 0x1000
+                    desc.mobile_all, desc.features = mob, feat
+                    h = ctypes.c_void_p()
+                    rc = L.vg_create(ctypes.byref(desc), ctypes.byref(h))
+                    if prec == _lib.VG_F32C and feat & _lib.VG_FEAT_ADJ:
+                        assert rc == _lib.VG_EINVAL and not h.value
+                        continue
+                    assert rc == 0, (offs, prec, feat, L.vg_last_error())
+                    ws = ctypes.c_size_t(0)
+                    assert L.vg_workspace_bytes(h, ctypes.byref(ws)) == 0
+                    sizes[(prec, feat, mob)] = ws.value
+                    for k in (2, 5):       # rank index and band kernel need what this handle lacks
+                        assert L.vg_set_kernel(h, k) == _lib.VG_EINVAL
+                    x = np.zeros(5)
+                    assert L.vg_load_state(h, x.ctypes.data, _lib.VG_F64, None) == _lib.VG_ESTATE
+                    assert L.vg_store_state(h, x.ctypes.data, _lib.VG_F64, None) == _lib.VG_ESTATE
+                    L.vg_destroy(h)
+        n = int(seg[-1])
+        for feat in (0, _lib.VG_FEAT_CG):
+            for mob in (0, 1):
+                extra = sizes[(_lib.VG_F32C, feat, mob)] - sizes[(_lib.VG_F32, feat, mob)]
+                assert 2 * (5 + (5 if mob else 1)) * n <= extra <= 2 * (5 + (5 if mob else 1)) * n + 512, (offs, extra)
+
+
+def test_pngm_noalloc_validates_before_device_work():
+    L = _lib.load()
+    it, rel = ctypes.c_int(0), ctypes.c_double(0.0)
+    p = 0x1000
+    q = _lib.VG_PNGM_NOALLOC_MAX_Q + 1
+    assert L.vg_pngm_implicit_step_noalloc(p, p + 8, q, p, p, p, p, 1.0, 1e-12, 10, ctypes.byref(it),
+                                           ctypes.byref(rel), None) == _lib.VG_EINVAL
+    for bad in ((p, p, 10, 1.0, 1e-12, 10), (p, p + 8, 10, -1.0, 1e-12, 10), (p, p + 8, 10, 1.0, 0.0, 10),
+                (p, p + 8, 10, 1.0, 1e-12, 0), (0, p + 8, 10, 1.0, 1e-12, 10)):
+        m, o, qq, c, rtol, mi = bad
+        assert L.vg_pngm_implicit_step_noalloc(m, o, qq, p, p, p, p, c, rtol, mi, ctypes.byref(it),
+                                               ctypes.byref(rel), None) == _lib.VG_EINVAL
