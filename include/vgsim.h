@@ -170,6 +170,35 @@ int vg_range_sums(const void *x_d, int precision, int64_t n, const int64_t *offs
 int vg_brick_stats(const int32_t *vox_d, const int32_t *nbr_d, int64_t n, int nx, int ny, int nz, int b,
                    uint32_t *contact_d, unsigned long long *sums_d, void *stream);
 
+/* The primitive graph of the brick partition, assembled on the device
+ * (Sec. V.B's primitives, their volumes, contact surfaces and centroid
+ * distances, from which the starting conductances S_ij / d_ij follow).
+ * vg_pngm_partition_bytes gives the workspace size and the capacities the
+ * outputs need: max_prims = the number of bricks, max_edges = twice the
+ * number of face-adjacent brick pairs.  vg_pngm_partition then writes, for
+ * q primitives (the bricks holding pore voxels, in raster order of bricks)
+ * and E directed edges:
+ *   v_d [q]          pore voxels per primitive (FP64)
+ *   offsets_d [q+1]  start of each primitive's range in a compacted list
+ *                    enumerated brick by brick with bricks of side b
+ *   bricks_d [q]     brick index (raster order of bricks) of each primitive
+ *   row_d [q+1], col_d [E]  adjacency in CSR, columns ascending
+ *   S_d [E]          pore-voxel faces joining the two primitives (FP64)
+ *   dist_d [E]       distance of their centres of gravity in voxels,
+ *                    sqrt((dx^2 + dy^2) + dz^2) of centroids = coordinate
+ *                    sums / counts (FP64)
+ * and q, E to *q_out, *e_out (host).  vox_d / nbr_d as for vg_brick_stats
+ * (any enumeration of one volume, no periodic axis).  The workspace (work_d,
+ * work_bytes) holds the brick statistics and is overwritten.  Synchronises
+ * the stream.  VG_EINVAL for a null pointer, a bad shape or a short
+ * workspace. */
+int vg_pngm_partition_bytes(int nx, int ny, int nz, int b, size_t *work_bytes, int64_t *max_prims,
+                            int64_t *max_edges);
+int vg_pngm_partition(const int32_t *vox_d, const int32_t *nbr_d, int64_t n, int nx, int ny, int nz, int b,
+                      void *work_d, size_t work_bytes, double *v_d, int64_t *offsets_d, int32_t *bricks_d,
+                      int64_t *row_d, int32_t *col_d, double *S_d, double *dist_d, int64_t *q_out,
+                      int64_t *e_out, void *stream);
+
 /* Objective 1 (objective = 1: residual of the explicit scheme 3,
  * r_i = y_i - x_i + c sum_j theta_ij (x_i/v_i - x_j/v_j)) or objective 2 (the
  * implicit scheme 4, r_i = x_i - y_i - c sum_j theta_ij (y_i/v_i - y_j/v_j)),

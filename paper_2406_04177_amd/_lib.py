@@ -26,7 +26,7 @@ VG_PNGM_NOALLOC_MAX_Q = 65536
 
 EXPORTS = ("vg_strerror", "vg_last_error", "vg_version", "vg_rank_bytes", "vg_count_pores",
            "vg_build_graph", "vg_lookup", "vg_region_codes", "vg_range_sums",
-           "vg_brick_stats", "vg_pngm_loss_grad", "vg_pngm_step", "vg_pngm_implicit_step",
+           "vg_brick_stats", "vg_pngm_partition_bytes", "vg_pngm_partition", "vg_pngm_loss_grad", "vg_pngm_step", "vg_pngm_implicit_step",
            "vg_pngm_implicit_step_noalloc", "vg_sign_update", "vg_create", "vg_destroy",
            "vg_set_kernel", "vg_get_kernel", "vg_set_adjoint_options", "vg_set_params", "vg_set_regions", "vg_alt_elems", "vg_workspace_bytes", "vg_init_state",
            "vg_step_explicit", "vg_step_subcycled", "vg_solve_implicit_step", "vg_mass_totals", "vg_record", "vg_adjoint",
@@ -81,6 +81,9 @@ def load():
             "vg_region_codes": (I, [P, I64, I, I, I, U, P, P]),
             "vg_range_sums": (I, [P, I, I64, P, I64, P, P]),
             "vg_brick_stats": (I, [P, P, I64, I, I, I, I, P, P, P]),
+            "vg_pngm_partition_bytes": (I, [I, I, I, I, ctypes.POINTER(S), ctypes.POINTER(I64), ctypes.POINTER(I64)]),
+            "vg_pngm_partition": (I, [P, P, I64, I, I, I, I, P, S, P, P, P, P, P, P, P,
+                                      ctypes.POINTER(I64), ctypes.POINTER(I64), P]),
             "vg_pngm_loss_grad": (I, [P, P, I64, I64, P, P, P, P, D, I, P, P, P, P]),
             "vg_pngm_step": (I, [P, P, I64, P, P, P, P, D, P]),
             "vg_pngm_implicit_step": (I, [P, P, I64, P, P, P, P, D, D, I, P, P, P, P]),

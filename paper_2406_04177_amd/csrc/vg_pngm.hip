@@ -70,6 +70,130 @@ __global__ __launch_bounds__(kBlock) void k_brick_stats(const int32_t *__restric
     }
 }
 
+// ---------------------------------------------------------------- partition
+// The primitive graph of the brick partition from the brick statistics:
+// primitive i = the i-th brick (raster order of bricks) holding pore voxels;
+// v_i its pore voxels; offsets_i the start of its range in a brick-ordered
+// compact list; adjacency in CSR with ascending columns: a brick's
+// neighbours -z, -y, -x, +x, +y, +z have ascending brick (so primitive)
+// indices; S = the pore-voxel faces between the two bricks, d = the distance
+// of their centres of gravity (coordinate sums / count, exact integer sums).
+
+__device__ __forceinline__ void brick_xyz(const BrickGeom &G, int64_t k, int64_t &bx, int64_t &by, int64_t &bz) {
+    bx = k % G.nbx;
+    by = (k / G.nbx) % G.nby;
+    bz = k / ((int64_t)G.nbx * G.nby);
+}
+
+// Neighbour brick of k in order o = 0..5 (-z, -y, -x, +x, +y, +z) and the
+// faces between them (0: none or outside the box).
+__device__ __forceinline__ uint32_t brick_link(const BrickGeom &G, const uint32_t *__restrict__ contact, int64_t k,
+                                               int o, int64_t &kn) {
+    int64_t bx, by, bz;
+    brick_xyz(G, k, bx, by, bz);
+    const int64_t sx = 1, sy = G.nbx, sz = (int64_t)G.nbx * G.nby;
+    switch (o) {
+        case 0: kn = k - sz; return bz > 0 ? contact[kn * 3 + 2] : 0u;
+        case 1: kn = k - sy; return by > 0 ? contact[kn * 3 + 1] : 0u;
+        case 2: kn = k - sx; return bx > 0 ? contact[kn * 3 + 0] : 0u;
+        case 3: kn = k + sx; return contact[k * 3 + 0];   // faces exist only when brick k + 1 does
+        case 4: kn = k + sy; return contact[k * 3 + 1];
+        default: kn = k + sz; return contact[k * 3 + 2];
+    }
+}
+
+constexpr int kScanThreads = 1024;
+
+// One block: each thread takes a contiguous chunk of bricks, counts its
+// primitives, edges and pore voxels, the block scans the counts (exclusive,
+// in LDS), and each thread numbers its chunk's primitives and writes their
+// volume, range start, first edge and brick; scal = {q, E}.
+__global__ __launch_bounds__(kScanThreads) void k_prim_scan(const uint32_t *__restrict__ contact,
+                                                            const unsigned long long *__restrict__ sums,
+                                                            BrickGeom G, int64_t nb, int32_t *__restrict__ pid,
+                                                            double *__restrict__ v, int64_t *__restrict__ offsets,
+                                                            int32_t *__restrict__ bricks, int64_t *__restrict__ row,
+                                                            int64_t *__restrict__ scal) {
+    __shared__ int64_t sc[3][kScanThreads];
+    const int t = threadIdx.x;
+    const int64_t chunk = (nb + kScanThreads - 1) / kScanThreads;
+    const int64_t k0 = t * chunk < nb ? t * chunk : nb, k1 = k0 + chunk < nb ? k0 + chunk : nb;
+    int64_t cnt[3] = {0, 0, 0};   // primitives, edges, pore voxels
+    for (int64_t k = k0; k < k1; k++) {
+        const unsigned long long c = sums[k * 4];
+        if (!c) continue;
+        cnt[0] += 1;
+        cnt[2] += (int64_t)c;
+        for (int o = 0; o < 6; o++) {
+            int64_t kn;
+            cnt[1] += brick_link(G, contact, k, o, kn) ? 1 : 0;
+        }
+    }
+    for (int a = 0; a < 3; a++) sc[a][t] = cnt[a];
+    __syncthreads();
+    for (int w = 1; w < kScanThreads; w <<= 1) {   // inclusive scan (Hillis-Steele)
+        int64_t add[3] = {0, 0, 0};
+        if (t >= w)
+            for (int a = 0; a < 3; a++) add[a] = sc[a][t - w];
+        __syncthreads();
+        for (int a = 0; a < 3; a++) sc[a][t] += add[a];
+        __syncthreads();
+    }
+    int64_t base[3];
+    for (int a = 0; a < 3; a++) base[a] = sc[a][t] - cnt[a];
+    for (int64_t k = k0; k < k1; k++) {
+        const unsigned long long c = sums[k * 4];
+        if (!c) {
+            pid[k] = -1;
+            continue;
+        }
+        const int64_t i = base[0]++;
+        pid[k] = (int32_t)i;
+        v[i] = (double)c;
+        offsets[i] = base[2];
+        base[2] += (int64_t)c;
+        bricks[i] = (int32_t)k;
+        row[i] = base[1];
+        for (int o = 0; o < 6; o++) {
+            int64_t kn;
+            base[1] += brick_link(G, contact, k, o, kn) ? 1 : 0;
+        }
+    }
+    if (t == kScanThreads - 1) {
+        const int64_t q = sc[0][t], E = sc[1][t];
+        row[q] = E;
+        offsets[q] = sc[2][t];
+        scal[0] = q;
+        scal[1] = E;
+    }
+}
+
+// One thread per brick: the CSR row of its primitive.
+__global__ __launch_bounds__(kBlock) void k_prim_fill(const uint32_t *__restrict__ contact,
+                                                      const unsigned long long *__restrict__ sums, BrickGeom G,
+                                                      int64_t nb, const int32_t *__restrict__ pid,
+                                                      const int64_t *__restrict__ row, int32_t *__restrict__ col,
+                                                      double *__restrict__ S, double *__restrict__ dist) {
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= nb || !sums[k * 4]) return;
+    const double ck = (double)sums[k * 4];
+    const double cx = (double)sums[k * 4 + 1] / ck, cy = (double)sums[k * 4 + 2] / ck,
+                 cz = (double)sums[k * 4 + 3] / ck;
+    int64_t e = row[pid[k]];
+    for (int o = 0; o < 6; o++) {
+        int64_t kn;
+        const uint32_t f = brick_link(G, contact, k, o, kn);
+        if (!f) continue;
+        const double cn = (double)sums[kn * 4];
+        const double dx = cx - (double)sums[kn * 4 + 1] / cn, dy = cy - (double)sums[kn * 4 + 2] / cn,
+                     dz = cz - (double)sums[kn * 4 + 3] / cn;
+        col[e] = pid[kn];
+        S[e] = (double)f;
+        dist[e] = sqrt((dx * dx + dy * dy) + dz * dz);
+        e++;
+    }
+}
+
 // One thread per primitive row i: for every data pair p the residual of row
 // i, then the gradient terms of the row's edges (each edge belongs to one
 // row, so no two threads write the same entry) and the row's share of the
@@ -208,6 +332,90 @@ extern "C" int vg_brick_stats(const int32_t *vox_d, const int32_t *nbr_d, int64_
     if (n == 0) return VG_OK;
     hipLaunchKernelGGL(k_brick_stats, dim3(blocks_for(n)), dim3(kBlock), 0, s, vox_d, nbr_d, n, G, contact_d, sums_d);
     return launch_status("k_brick_stats");
+}
+
+namespace {
+// Brick grid, bricks, primitive and edge capacities of a partition.
+int partition_sizes(int nx, int ny, int nz, int b, BrickGeom *G, int64_t *nb, int64_t *max_edges) {
+    if (nx <= 0 || ny <= 0 || nz <= 0 || b <= 0) {
+        set_error("bad partition shape or brick size");
+        return VG_EINVAL;
+    }
+    *G = BrickGeom{nx, ny, nz, b, (nx + b - 1) / b, (ny + b - 1) / b, (nz + b - 1) / b};
+    const int64_t X = G->nbx, Y = G->nby, Z = G->nbz;
+    *nb = X * Y * Z;
+    *max_edges = 2 * ((X - 1) * Y * Z + X * (Y - 1) * Z + X * Y * (Z - 1));   // both directions of every pair
+    if (*nb >= ((int64_t)1 << 31)) {
+        set_error("too many bricks (%lld)", (long long)*nb);
+        return VG_EINVAL;
+    }
+    return VG_OK;
+}
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+size_t partition_work(int64_t nb) {
+    return align256(sizeof(uint32_t) * 3 * (size_t)nb) + align256(sizeof(unsigned long long) * 4 * (size_t)nb) +
+           align256(sizeof(int32_t) * (size_t)nb) + align256(sizeof(int64_t) * 2);
+}
+}  // namespace
+
+extern "C" int vg_pngm_partition_bytes(int nx, int ny, int nz, int b, size_t *work_bytes, int64_t *max_prims,
+                                       int64_t *max_edges) {
+    if (!work_bytes || !max_prims || !max_edges) {
+        set_error("null pointer argument");
+        return VG_EINVAL;
+    }
+    BrickGeom G;
+    int64_t nb = 0, me = 0;
+    const int rc = partition_sizes(nx, ny, nz, b, &G, &nb, &me);
+    if (rc) return rc;
+    *work_bytes = partition_work(nb);
+    *max_prims = nb;
+    *max_edges = me;
+    return VG_OK;
+}
+
+extern "C" int vg_pngm_partition(const int32_t *vox_d, const int32_t *nbr_d, int64_t n, int nx, int ny, int nz, int b,
+                                 void *work_d, size_t work_bytes, double *v_d, int64_t *offsets_d, int32_t *bricks_d,
+                                 int64_t *row_d, int32_t *col_d, double *S_d, double *dist_d, int64_t *q_out,
+                                 int64_t *e_out, void *stream) {
+    BrickGeom G;
+    int64_t nb = 0, me = 0;
+    int rc = partition_sizes(nx, ny, nz, b, &G, &nb, &me);
+    if (rc) return rc;
+    if (n < 0 || !q_out || !e_out || !work_d || !v_d || !offsets_d || !bricks_d || !row_d ||
+        (me > 0 && (!col_d || !S_d || !dist_d)) || (n > 0 && (!vox_d || !nbr_d))) {
+        set_error("bad partition arguments");
+        return VG_EINVAL;
+    }
+    if (work_bytes < partition_work(nb)) {
+        set_error("partition workspace too small: %zu < %zu bytes", work_bytes, partition_work(nb));
+        return VG_EINVAL;
+    }
+    char *w = (char *)work_d;
+    uint32_t *contact = (uint32_t *)w;
+    w += align256(sizeof(uint32_t) * 3 * (size_t)nb);
+    unsigned long long *sums = (unsigned long long *)w;
+    w += align256(sizeof(unsigned long long) * 4 * (size_t)nb);
+    int32_t *pid = (int32_t *)w;
+    w += align256(sizeof(int32_t) * (size_t)nb);
+    int64_t *scal = (int64_t *)w;
+    if ((rc = vg_brick_stats(vox_d, nbr_d, n, nx, ny, nz, b, contact, sums, stream))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_prim_scan, dim3(1), dim3(kScanThreads), 0, s, contact, sums, G, nb, pid, v_d, offsets_d,
+                       bricks_d, row_d, scal);
+    if ((rc = launch_status("k_prim_scan"))) return rc;
+    hipLaunchKernelGGL(k_prim_fill, dim3(blocks_for(nb)), dim3(kBlock), 0, s, contact, sums, G, nb, pid, row_d, col_d,
+                       S_d, dist_d);
+    if ((rc = launch_status("k_prim_fill"))) return rc;
+    int64_t host[2] = {0, 0};
+    if ((rc = hip_status(hipMemcpyAsync(host, scal, sizeof(host), hipMemcpyDeviceToHost, s), "partition sizes")))
+        return rc;
+    if ((rc = hip_status(hipStreamSynchronize(s), "partition sync"))) return rc;
+    *q_out = host[0];
+    *e_out = host[1];
+    return VG_OK;
 }
 
 extern "C" int vg_pngm_loss_grad(const double *X_d, const double *Y_d, int64_t l, int64_t q, const double *v_d,

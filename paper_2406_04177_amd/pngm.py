@@ -1,8 +1,8 @@
 """Pore-network (PNGM) conductances from voxel-method data (Sec. V).
 
 Primitives are the bricks of side b of the image (pore voxels of one brick);
-their graph, volumes, contact surfaces and centre distances come from
-``vg_brick_stats`` over the voxel graph; the data pairs (X^p, Y^p) are
+their graph, volumes, contact surfaces and centre distances are assembled on
+the device by ``vg_pngm_partition`` from the voxel graph; the data pairs (X^p, Y^p) are
 primitive masses of voxel-method diffusion runs taken dt apart (range sums
 over a brick-ordered compacted list, where each brick is one contiguous
 range); the objective (L1 or L2) and its gradient come from
@@ -39,46 +39,34 @@ class Partition:
 
 def partition(g: Graph, b: int) -> Partition:
     """The brick partition of a single, non-periodic volume whose compacted
-    list is brick-ordered with bricks of side b."""
+    list is brick-ordered with bricks of side b (assembled by
+    ``vg_pngm_partition``; the outputs are allocated at their capacities
+    and cut to q primitives and E edges)."""
     if g.nseg != 1 or g.periodic or g.brick != b:
         raise ValueError("need one volume, no periodic axis, brick order with bricks of side b")
     L = _lib.load()
     nz, ny, nx = g.shape
-    nbx, nby, nbz = -(-nx // b), -(-ny // b), -(-nz // b)
-    nb = nbx * nby * nbz
+    wb, mp, me = ctypes.c_size_t(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    _lib.check(L.vg_pngm_partition_bytes(nx, ny, nz, b, ctypes.byref(wb), ctypes.byref(mp), ctypes.byref(me)),
+               "vg_pngm_partition_bytes")
     dev = g.vox.device
-    contact = torch.empty((nb, 3), dtype=torch.int32, device=dev)
-    sums = torch.empty((nb, 4), dtype=torch.int64, device=dev)
-    _lib.check(L.vg_brick_stats(g.vox.data_ptr(), g.nbr.data_ptr(), g.n, nx, ny, nz, b, contact.data_ptr(),
-                                sums.data_ptr(), _lib.stream_ptr(None)), "vg_brick_stats")
-    # assembly of the (small) primitive graph on the host
-    contact = contact.cpu().numpy().view(np.uint32).astype(np.int64)
-    sums = sums.cpu().numpy().view(np.uint64).astype(np.float64)
-    cnt = sums[:, 0]
-    used = np.flatnonzero(cnt > 0)
-    q = used.size
-    pid = -np.ones(nb, np.int64)
-    pid[used] = np.arange(q)
-    cen = sums[used, 1:4] / cnt[used, None]
-    stride = (1, nbx, nbx * nby)
-    src, dst, S = [], [], []
-    for a in range(3):
-        k = np.flatnonzero(contact[:, a] > 0)
-        i, j = pid[k], pid[k + stride[a]]
-        src += [i, j]
-        dst += [j, i]
-        S += [contact[k, a], contact[k, a]]
-    src, dst, S = np.concatenate(src), np.concatenate(dst), np.concatenate(S).astype(np.float64)
-    order = np.lexsort((dst, src))
-    src, dst, S = src[order], dst[order], S[order]
-    row = np.zeros(q + 1, np.int64)
-    np.add.at(row, src + 1, 1)
-    row = np.cumsum(row)
-    d = np.sqrt(((cen[src] - cen[dst]) ** 2).sum(axis=1))
-    offsets = np.concatenate([[0], np.cumsum(cnt[used])]).astype(np.int64)
-    return Partition(b, q, torch.as_tensor(cnt[used], dtype=torch.float64, device=dev),
-                     torch.as_tensor(row, device=dev), torch.as_tensor(dst.astype(np.int32), device=dev),
-                     S, d, torch.as_tensor(offsets, device=dev), used)
+    f64, i64, i32 = torch.float64, torch.int64, torch.int32
+    work = torch.empty(wb.value, dtype=torch.uint8, device=dev)
+    v = torch.empty(mp.value, dtype=f64, device=dev)
+    offsets = torch.empty(mp.value + 1, dtype=i64, device=dev)
+    bricks = torch.empty(mp.value, dtype=i32, device=dev)
+    row = torch.empty(mp.value + 1, dtype=i64, device=dev)
+    col = torch.empty(max(me.value, 1), dtype=i32, device=dev)
+    S = torch.empty(max(me.value, 1), dtype=f64, device=dev)
+    d = torch.empty(max(me.value, 1), dtype=f64, device=dev)
+    q, e = ctypes.c_int64(0), ctypes.c_int64(0)
+    _lib.check(L.vg_pngm_partition(g.vox.data_ptr(), g.nbr.data_ptr(), g.n, nx, ny, nz, b, work.data_ptr(), wb.value,
+                                   v.data_ptr(), offsets.data_ptr(), bricks.data_ptr(), row.data_ptr(), col.data_ptr(),
+                                   S.data_ptr(), d.data_ptr(), ctypes.byref(q), ctypes.byref(e),
+                                   _lib.stream_ptr(None)), "vg_pngm_partition")
+    q, e = q.value, e.value
+    return Partition(b, q, v[:q].clone(), row[:q + 1].clone(), col[:e].clone(), S[:e].cpu().numpy(),
+                     d[:e].cpu().numpy(), offsets[:q + 1].clone(), bricks[:q].cpu().numpy().astype(np.int64))
 
 
 def primitive_masses(part: Partition, m: torch.Tensor) -> torch.Tensor:

@@ -334,3 +334,23 @@ def test_pngm_noalloc_validates_before_device_work():
         m, o, qq, c, rtol, mi = bad
         assert L.vg_pngm_implicit_step_noalloc(m, o, qq, p, p, p, p, c, rtol, mi, ctypes.byref(it),
                                                ctypes.byref(rel), None) == _lib.VG_EINVAL
+
+
+def test_pngm_partition_sizes_and_validation():
+    L = _lib.load()
+    wb, mp, me = ctypes.c_size_t(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    # 36 x 40 x 44 (nz, ny, nx) in bricks of 8: 6 x 5 x 5 bricks, 2 (5*5*5 + 6*4*5 + 6*5*4) directed pairs
+    assert L.vg_pngm_partition_bytes(44, 40, 36, 8, ctypes.byref(wb), ctypes.byref(mp), ctypes.byref(me)) == 0
+    assert mp.value == 150 and me.value == 730 and wb.value >= 150 * (12 + 32 + 4)
+    assert L.vg_pngm_partition_bytes(44, 40, 36, 0, ctypes.byref(wb), ctypes.byref(mp), ctypes.byref(me)) == _lib.VG_EINVAL
+    assert L.vg_pngm_partition_bytes(1, 1, 1, 4, ctypes.byref(wb), ctypes.byref(mp), ctypes.byref(me)) == 0
+    assert mp.value == 1 and me.value == 0
+    q, e = ctypes.c_int64(0), ctypes.c_int64(0)
+    p = 0x1000
+    args = [p, p, 10, 44, 40, 36, 8, p, 10, p, p, p, p, p, p, p, ctypes.byref(q), ctypes.byref(e), None]
+    assert L.vg_pngm_partition(*args) == _lib.VG_EINVAL            # workspace too small
+    args[8] = 1 << 20
+    for k in (0, 9, 13):
+        bad = list(args)
+        bad[k] = None
+        assert L.vg_pngm_partition(*bad) == _lib.VG_EINVAL

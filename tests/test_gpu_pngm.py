@@ -31,8 +31,38 @@ def test_partition_equals_oracle(vol):
     np.testing.assert_array_equal(part.row.cpu().numpy(), ref["row"])
     np.testing.assert_array_equal(part.col.cpu().numpy(), ref["col"])
     np.testing.assert_array_equal(part.S, ref["S"])
-    np.testing.assert_allclose(part.d, ref["d"], rtol=1e-13)
+    np.testing.assert_array_equal(part.d, ref["d"])     # same operations in the same order
     np.testing.assert_array_equal(part.offsets.cpu().numpy(), np.concatenate([[0], np.cumsum(ref["v"])]))
+
+
+@pytest.mark.parametrize("shape,por,b,seed", [((13, 11, 17), 0.5, 3, 1), ((20, 9, 14), 0.2, 5, 2),
+                                              ((8, 8, 8), 0.9, 16, 3), ((6, 7, 5), 0.6, 1, 4),
+                                              ((33, 18, 25), 0.35, 8, 5), ((10, 10, 10), 0.0, 4, 6)])
+def test_partition_raw_masks(shape, por, b, seed):
+    """Unfiltered random masks (isolated voxels, empty bricks, ragged bricks
+    at the far faces, one brick bigger than the box, one voxel per brick, no
+    pore at all): the device-assembled primitive graph equals the oracle's,
+    integers and distances bit for bit."""
+    from paper_2406_04177_amd.graph import Graph
+    from paper_2406_04177_amd import pngm
+    rng = np.random.default_rng(seed)
+    mask = (rng.random(shape) < por).astype(np.uint8)
+    g = Graph.from_masks(mask, brick=b)
+    part = pngm.partition(g, b)
+    ref = po.partition(mask, b)
+    assert part.q == ref["q"]
+    np.testing.assert_array_equal(part.v.cpu().numpy(), ref["v"])
+    np.testing.assert_array_equal(part.row.cpu().numpy(), ref["row"])
+    np.testing.assert_array_equal(part.col.cpu().numpy(), ref["col"])
+    np.testing.assert_array_equal(part.S, ref["S"])
+    np.testing.assert_array_equal(part.d, ref["d"])
+    np.testing.assert_array_equal(part.offsets.cpu().numpy(), np.concatenate([[0], np.cumsum(ref["v"])]))
+    # the bricks of the primitives, from the oracle's voxel-to-primitive map
+    nz, ny, nx = shape
+    nbx, nby = -(-nx // b), -(-ny // b)
+    zz, yy, xx = np.nonzero(mask)
+    brick = (zz // b * nby + yy // b) * nbx + xx // b
+    np.testing.assert_array_equal(part.bricks, np.unique(brick))
 
 
 def test_primitive_masses_equal_oracle(vol):
