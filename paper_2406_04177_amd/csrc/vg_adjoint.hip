@@ -68,7 +68,8 @@ __device__ __forceinline__ void transform_fwd(const Coef<R> &C, R &m1, R &m2, R 
 // Reverse of the transformation at pre-step masses x (branches re-taken from
 // x).  In: ybar = adjoint of T's outputs.  Out: adjoint of its inputs.  The
 // rate derivatives accumulate into g[0..6] = v_DOM, K_DOM, rho, mu, beta,
-// v_SOM, v_P4 (FP64).
+// v_SOM, v_P4 (FP64 sums of the voxel's terms, each formed in the field
+// type).
 template <typename R>
 __device__ __forceinline__ void transform_rev(const Coef<R> &C, const R (&x)[VG_NPOOL], R (&bar)[VG_NPOOL],
                                               double *g) {
@@ -94,7 +95,7 @@ __device__ __forceinline__ void transform_rev(const Coef<R> &C, const R (&x)[VG_
     R mortb;
     if (C.route == 0) {
         mortb = -y1 + C.beta * y2 + C.omb * y3;
-        g[4] += (double)morta * (double)(y2 - y3);
+        g[4] += (double)(morta * (y2 - y3));
     } else {
         mortb = -y1 + y4;
     }
@@ -104,27 +105,31 @@ __device__ __forceinline__ void transform_rev(const Coef<R> &C, const R (&x)[VG_
     if (up_clamp) {
         b2 += upb;
     } else {
-        const R gm = m2 / den;
+        // one division: d(uptake)/d(m2) = v m1 dt K / den^2 and
+        // d(uptake)/dK = -v m1 dt m2 / den^2 from 1/den
+        const R inv = R(1) / den;
+        const R gm = m2 * inv;
+        const R vmd = C.v_dom * m1 * dt * inv;
         b1 += upb * C.v_dom * gm * dt;
-        b2 += upb * C.v_dom * m1 * dt * C.k_dom / (den * den);
-        g[0] += (double)upb * (double)(gm * m1 * dt);
-        g[1] -= (double)upb * (double)(C.v_dom * m1 * dt * m2 / (den * den));
+        b2 += upb * vmd * (C.k_dom * inv);
+        g[0] += (double)(upb * (gm * m1 * dt));
+        g[1] -= (double)(upb * (vmd * gm));
     }
     if (rm == 0) {
         b1 += respb * C.rho * dt + mortb * C.mu * dt;
-        g[2] += (double)respb * (double)(m1 * dt);
-        g[3] += (double)mortb * (double)(m1 * dt);
+        g[2] += (double)(respb * (m1 * dt));
+        g[3] += (double)(mortb * (m1 * dt));
     } else if (rm == 1) {
         b1 += mortb;
     } else {
         const R mt = mortb - respb;
         b1 += respb + mt * C.mu * dt;
-        g[3] += (double)mt * (double)(m1 * dt);
+        g[3] += (double)(mt * (m1 * dt));
     }
     if (som_clamp) b3 += somb;
-    else { b3 += somb * C.v_som * dt; g[5] += (double)somb * (double)(m3 * dt); }
+    else { b3 += somb * C.v_som * dt; g[5] += (double)(somb * (m3 * dt)); }
     if (p4_clamp) b4 += p4b;
-    else { b4 += p4b * C.v_p4 * dt; g[6] += (double)p4b * (double)(m4 * dt); }
+    else { b4 += p4b * C.v_p4 * dt; g[6] += (double)(p4b * (m4 * dt)); }
     bar[0] = b1; bar[1] = b2; bar[2] = b3; bar[3] = b4; bar[4] = b5;
 }
 
@@ -184,7 +189,16 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces 
     using I = typename AdjIndex<NS>::T;
     __shared__ double lds[kWaves * kG];
     __shared__ R cl[VG_NREG];
+    // with region weights each thread keeps its dL/dc_r sums in LDS, region
+    // major (conflict-free whatever region each lane adds to): the region of
+    // a term depends on the voxel, so registers would need a select per
+    // region and term
+    __shared__ double creg[REG ? VG_NREG : 1][REG ? kBlock : 1];
     if (threadIdx.x < VG_NREG) cl[threadIdx.x] = C.c[threadIdx.x];
+    if (REG) {
+#pragma unroll
+        for (int r = 0; r < VG_NREG; r++) creg[r][threadIdx.x] = 0.0;
+    }
     __syncthreads();
     double g[kG];
 #pragma unroll
@@ -292,41 +306,40 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces 
 #pragma unroll
             for (int k = 0; k < 6; k++) lj[k] = elem(lin[s], j[k]);
             R sum = R(0);
-            double creg_own = 0.0, creg_x[3] = {0.0, 0.0, 0.0};
+            // the voxel's terms of dw/dc (half of each cross-octant edge
+            // to each side), summed in the field type
+            R creg_own = R(0), creg_x[3] = {R(0), R(0), R(0)};
 #pragma unroll
             for (int k = 0; k < 6; k++) {
                 const R dl = lj[k] - li[s];
                 sum += w[k] * dl;
                 if (REG && mobile<MOB>(s)) {
-                    const double tk = (double)dl;
                     if ((code >> (3 + k)) & 1u) {
-                        creg_own += 0.5 * tk;
-                        creg_x[k >> 1] += 0.5 * tk;
+                        creg_own += R(0.5) * dl;
+                        creg_x[k >> 1] += R(0.5) * dl;
                     } else {
-                        creg_own += tk;
+                        creg_own += dl;
                     }
                 }
             }
             bar[s] = mobile<MOB>(s) ? li[s] + C.a[s] * sum : li[s];
-            g[s] += (double)u[s] * (double)sum;   // dL/da_s
+            g[s] += (double)(u[s] * sum);   // dL/da_s (each voxel's term in the field type)
             if (REG && mobile<MOB>(s)) {
-                const double f = (double)C.a[s] * (double)u[s];
-                own_c += f * creg_own;
-                cross_c[0] += f * creg_x[0];
-                cross_c[1] += f * creg_x[1];
-                cross_c[2] += f * creg_x[2];
+                const R f = C.a[s] * u[s];
+                own_c += (double)(f * creg_own);
+                cross_c[0] += (double)(f * creg_x[0]);
+                cross_c[1] += (double)(f * creg_x[1]);
+                cross_c[2] += (double)(f * creg_x[2]);
             }
         }
         if (REG) {
-#pragma unroll
-            for (int r = 0; r < VG_NREG; r++) {
-                double v = 0.0;
-                if ((int)own == r) v += own_c;
-                if ((int)(own ^ 1u) == r) v += cross_c[0];
-                if ((int)(own ^ 2u) == r) v += cross_c[1];
-                if ((int)(own ^ 4u) == r) v += cross_c[2];
-                g[12 + r] += v;
-            }
+            // four region slots of this thread (the octant and its three
+            // neighbours across the mid-planes); private, in a fixed order
+            const unsigned t = threadIdx.x;
+            creg[own][t] += own_c;
+            creg[own ^ 1u][t] += cross_c[0];
+            creg[own ^ 2u][t] += cross_c[1];
+            creg[own ^ 4u][t] += cross_c[2];
         }
         // adjoint of the transformation half
         transform_rev(C, x, bar, &g[5]);
@@ -335,6 +348,10 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces 
         for (int s = 0; s < VG_NPOOL - 1; s++) elem(lout[s], i) = (R)((double)bar[s] + sd[s]);
         if (!CO2U) elem(lout[4], i) = (R)((double)bar[4] + sd[4]);
     }
+    }
+    if (REG) {
+#pragma unroll
+        for (int r = 0; r < VG_NREG; r++) g[12 + r] = creg[r][threadIdx.x];
     }
     block_sum<kG>(g, lds);
     if (threadIdx.x == 0) {
