@@ -1072,47 +1072,59 @@ __device__ __forceinline__ void band_first(const StepBufs<R> &B, const Coef<R> &
 
 // Second pass on U slots of the band range [bs, be) of plane q: the pools
 // are read again and the first pass's transformation recomputed from its
-// diffused DOM; the neighbours' first-pass DOM comes from LDS.
+// diffused DOM; the neighbours' first-pass DOM comes from LDS.  In two
+// parts, so that the loads can be issued before the first pass of the same
+// marching step and their latency overlaps it.
 template <typename R, int U>
-__device__ __forceinline__ void band_second(const StepBufs<R> &B, const Coef<R> &C, uint32_t base, uint32_t bs,
-                                            uint32_t be, uint32_t es, uint32_t esm, uint32_t esp, const R *d1m,
-                                            const R *d1c, const R *d1p, const R *dm) {
-    const uint32_t lane = threadIdx.x & 63u;
+struct BandSecond {
     uint32_t e[U], i[U], w[U];
     R m1[U], m3[U], m4[U], m5[U];
+};
+
+template <typename R, int U>
+__device__ __forceinline__ void band_second_load(const StepBufs<R> &B, uint32_t base, uint32_t bs, uint32_t be,
+                                                 BandSecond<R, U> &L) {
+    const uint32_t lane = threadIdx.x & 63u;
 #pragma unroll
     for (int u = 0; u < U; u++) {
-        e[u] = base + (uint32_t)(u * kBlock) + lane;
-        i[u] = e[u] < bs ? bs : (e[u] < be ? e[u] : be - 1u);
-        w[u] = packed_words<true>(B.pk, i[u]).a;
-        m1[u] = at(B.src[0], i[u]);
-        m3[u] = at(B.src[2], i[u]);
-        m4[u] = at(B.src[3], i[u]);
-        m5[u] = at(B.src[4], i[u]);
+        L.e[u] = base + (uint32_t)(u * kBlock) + lane;
+        L.i[u] = L.e[u] < bs ? bs : (L.e[u] < be ? L.e[u] : be - 1u);
+        L.w[u] = packed_words<true>(B.pk, L.i[u]).a;
+        L.m1[u] = at(B.src[0], L.i[u]);
+        L.m3[u] = at(B.src[2], L.i[u]);
+        L.m4[u] = at(B.src[3], L.i[u]);
+        L.m5[u] = at(B.src[4], L.i[u]);
     }
+}
+
+template <typename R, int U>
+__device__ __forceinline__ void band_second_finish(const StepBufs<R> &B, const Coef<R> &C, uint32_t base, uint32_t bs,
+                                                   uint32_t be, uint32_t es, uint32_t esm, uint32_t esp, const R *d1m,
+                                                   const R *d1c, const R *d1p, const R *dm, const BandSecond<R, U> &L) {
 #pragma unroll
     for (int u = 0; u < U; u++) {
         if (base + (uint32_t)(u * kBlock) >= be) break;   // uniform over the wave
-        R x1 = m1[u], x2 = dm[i[u] - es], x3 = m3[u], x4 = m4[u], x5 = m5[u];
+        const uint32_t i = L.i[u];
+        R x1 = L.m1[u], x2 = dm[i - es], x3 = L.m3[u], x4 = L.m4[u], x5 = L.m5[u];
         transform_alg<false>(C, x1, x2, x3, x4, x5);   // the first pass's output
         uint32_t j[6];
-        packed_decode<true>(B.pk, i[u], PackedWords{w[u], 0u}, j);
+        packed_decode<true>(B.pk, i, PackedWords{L.w[u], 0u}, j);
         R g[6];
 #pragma unroll
         for (int k = 0; k < 4; k++) g[k] = d1c[j[k] - es];   // same plane (absent: i itself)
-        g[4] = j[4] == i[u] ? x2 : d1m[j[4] - esm];
-        g[5] = j[5] == i[u] ? x2 : d1p[j[5] - esp];
+        g[4] = j[4] == i ? x2 : d1m[j[4] - esm];
+        g[5] = j[5] == i ? x2 : d1p[j[5] - esp];
         R d[6];
 #pragma unroll
         for (int k = 0; k < 6; k++) d[k] = g[k] - x2;
         x2 = x2 + C.a[1] * (((d[0] + d[1]) + (d[2] + d[3])) + (d[4] + d[5]));
         transform_alg<false>(C, x1, x2, x3, x4, x5);
-        if (e[u] >= bs && e[u] < be) {
-            at(B.dst[0], i[u]) = x1;
-            at(B.dst[1], i[u]) = x2;
-            at(B.dst[2], i[u]) = x3;
-            at(B.dst[3], i[u]) = x4;
-            at(B.dst[4], i[u]) = x5;
+        if (L.e[u] >= bs && L.e[u] < be) {
+            at(B.dst[0], i) = x1;
+            at(B.dst[1], i) = x2;
+            at(B.dst[2], i) = x3;
+            at(B.dst[3], i) = x4;
+            at(B.dst[4], i) = x5;
         }
     }
 }
@@ -1130,6 +1142,15 @@ __global__ __launch_bounds__(kBlock) void k_band2(StepBufs<R> B, Coef<R> C, Band
     const uint32_t wave = threadIdx.x >> 6;
     constexpr uint32_t kStep = (uint32_t)(kBandU * kBlock);
     for (int p = z0 - 1; p <= z1; p++) {
+        // the second pass of this step works on plane q = p - 1, band rows:
+        // its first slots' pools and codes are loaded before the first pass
+        const int q = p - 1;
+        const int64_t rq = (int64_t)q * G.ny;
+        const bool has_q = q >= z0 && q < z1;
+        const uint32_t qbs = has_q ? (uint32_t)rs[rq + y0] : 0u, qbe = has_q ? (uint32_t)rs[rq + y1] : 0u;
+        const uint32_t qbase = (qbs & ~63u) + wave * 64u;
+        BandSecond<R, kBandU> L2;
+        if (qbs < qbe && qbase < qbe) band_second_load<R, kBandU>(B, qbase, qbs, qbe, L2);
         // first pass on plane p, rows ey0 .. ey1 - 1 (waves start on 64-voxel
         // groups: the relative codes' bases are per group)
         const bool has_p = p >= 0 && p < G.nz;
@@ -1141,19 +1162,19 @@ __global__ __launch_bounds__(kBlock) void k_band2(StepBufs<R> B, Coef<R> C, Band
                 band_first<R, kBandU>(B, C, base, es, ee, d1, dm);
         }
         lds_barrier();
-        // second pass on plane q = p - 1, band rows
-        const int q = p - 1;
-        const int64_t rq = (int64_t)q * G.ny;
-        const bool has_q = q >= z0 && q < z1;
-        const uint32_t qbs = has_q ? (uint32_t)rs[rq + y0] : 0u, qbe = has_q ? (uint32_t)rs[rq + y1] : 0u;
+        // second pass on plane q, band rows
         if (qbs < qbe) {   // plane q is the block's and its band rows hold voxels
             const uint32_t qes = (uint32_t)rs[rq + ey0];
             const uint32_t esm = q > 0 ? (uint32_t)rs[rq - G.ny + ey0] : 0u;
             const uint32_t esp = q + 1 < G.nz ? (uint32_t)rs[rq + G.ny + ey0] : 0u;
-            for (uint32_t base = (qbs & ~63u) + wave * 64u; base < qbe; base += kStep)
-                band_second<R, kBandU>(B, C, base, qbs, qbe, qes, esm, esp, dom1 + ((q + 2) % 3) * G.cap,
-                                       dom1 + ((q + 3) % 3) * G.cap, dom1 + ((q + 4) % 3) * G.cap,
-                                       dmid + ((q + 2) % 2) * G.cap);
+            const R *d1m = dom1 + ((q + 2) % 3) * G.cap, *d1c = dom1 + ((q + 3) % 3) * G.cap,
+                    *d1p = dom1 + ((q + 4) % 3) * G.cap, *dmq = dmid + ((q + 2) % 2) * G.cap;
+            if (qbase < qbe) band_second_finish<R, kBandU>(B, C, qbase, qbs, qbe, qes, esm, esp, d1m, d1c, d1p, dmq, L2);
+            for (uint32_t base = qbase + kStep; base < qbe; base += kStep) {
+                BandSecond<R, kBandU> L;
+                band_second_load<R, kBandU>(B, base, qbs, qbe, L);
+                band_second_finish<R, kBandU>(B, C, base, qbs, qbe, qes, esm, esp, d1m, d1c, d1p, dmq, L);
+            }
         }
         lds_barrier();
     }
