@@ -208,7 +208,7 @@ def step_1024(steps=101):
     spec = inputs.init_uniform(mask, seed=0)
     g = Graph.from_masks(mask)
     slab = np.ascontiguousarray(mask[:128])
-    del mask
+    mask_full, spec_full = mask, spec
     log("1024^3 volume and graph in %.1f s (n = %d)" % (time.perf_counter() - t0, g.n))
     p = inputs.ModelParams()
     dt = inputs.explicit_dt(p, 0.9)
@@ -229,6 +229,28 @@ def step_1024(steps=101):
     log("1024^3: %.3f ms/step single passes, %.3f ms/step band kernel"
         % (res["ms_per_step_relative"], res["ms_per_step_band"]))
     del sim, x0, g
+    torch.cuda.empty_cache()
+    # the brick-ordered compacted list (8^3 bricks): no packed source fits its
+    # cross-brick distances, so AUTO takes the rank index (a neighbour's
+    # compact index from the pore bitmap); the table kernel for comparison
+    gb = Graph.from_masks(mask_full, brick=8)
+    x0 = gb.fields_from_specs(spec_full, torch.float32)
+    sim = Simulation(gb, p, precision="f32", implicit=False)
+    br = {"workload": "1024^3 17% porosity, brick-ordered compacted list (8^3 bricks), FP32 fields, "
+                      "FP64 totals every 100 steps", "auto_kernel": KERNEL_NAMES[sim.kernel_in_use()]}
+    for kern, name in ((2, "rank"), (1, "table")):
+        sim.set_kernel(kern)
+        sim.set_fields(x0)
+        sim.step(9, dt)
+        sim.set_fields(x0)
+        ms, _ = timed(lambda: sim.step(steps, dt, log_every=100))
+        br["ms_per_step_" + name] = ms / steps
+        br["achieved_GBs_64B_" + name] = BYTES_FUSED_F32 * gb.n / (ms / steps / 1e3) / 1e9
+    br["achieved_GBs_own_rank"] = BYTES_RANK_F32 * gb.n / (br["ms_per_step_rank"] / 1e3) / 1e9
+    res["brick_order"] = br
+    log("1024^3 brick order: %.3f ms/step rank index, %.3f ms/step table (AUTO %s)"
+        % (br["ms_per_step_rank"], br["ms_per_step_table"], br["auto_kernel"]))
+    del sim, x0, gb
     torch.cuda.empty_cache()
     # one GPU's share of the 1024^3 volume split into 8 z-slabs: its first 128
     # planes as a volume of their own (closed faces: no halo exchange)

@@ -316,6 +316,20 @@ int vg_destroy(vg_sim *h);
  * enough planes for chunks of at least 20 (about 512^3 and up). */
 #define VG_KERNEL_BAND     5
 int vg_set_kernel(vg_sim *h, int variant);
+
+/* Launching of the explicit step.  Runs of fused passes with no totals
+ * logged can be captured once as a HIP graph (on a private stream of the
+ * handle, never on the caller's) and replayed on the caller's stream: the
+ * same kernels with the same arguments in the same order, so the results
+ * are bit-identical; what changes is the launch cost, which bounds small
+ * volumes.  A captured run is re-captured after any change of parameters,
+ * regions, kernel choice, bound buffers or dt.  VG_LAUNCH_GRAPHS_AUTO
+ * (default): graphs for volumes of at most 2^19 pore voxels; _ON: always;
+ * _OFF: plain launches. */
+#define VG_LAUNCH_GRAPHS_AUTO 0u
+#define VG_LAUNCH_GRAPHS_ON   1u
+#define VG_LAUNCH_GRAPHS_OFF  2u
+int vg_set_launch_options(vg_sim *h, unsigned flags);
 int vg_get_kernel(const vg_sim *h, int *variant_in_use);
 /* Sets the model parameters (validated: h > 0, K_DOM > 0, rates >= 0,
  * 0 <= beta <= 1, D >= 0; only D[1] may be nonzero unless mobile_all). */

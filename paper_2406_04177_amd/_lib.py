@@ -23,12 +23,13 @@ VG_NPOOL, VG_NREG, VG_NGRAD = 5, 8, 20
 VG_KERNEL_AUTO, VG_KERNEL_TABLE, VG_KERNEL_RANK, VG_KERNEL_OFFSET, VG_KERNEL_RELATIVE, VG_KERNEL_BAND = 0, 1, 2, 3, 4, 5
 VG_ADJ_SKIP_STATIC_D = 1
 VG_PNGM_NOALLOC_MAX_Q = 65536
+VG_LAUNCH_GRAPHS_AUTO, VG_LAUNCH_GRAPHS_ON, VG_LAUNCH_GRAPHS_OFF = 0, 1, 2
 
 EXPORTS = ("vg_strerror", "vg_last_error", "vg_version", "vg_rank_bytes", "vg_count_pores",
            "vg_build_graph", "vg_lookup", "vg_region_codes", "vg_range_sums",
            "vg_brick_stats", "vg_pngm_partition_bytes", "vg_pngm_partition", "vg_pngm_loss_grad", "vg_pngm_step", "vg_pngm_implicit_step",
            "vg_pngm_implicit_step_noalloc", "vg_sign_update", "vg_create", "vg_destroy",
-           "vg_set_kernel", "vg_get_kernel", "vg_set_adjoint_options", "vg_set_params", "vg_set_regions", "vg_alt_elems", "vg_workspace_bytes", "vg_init_state",
+           "vg_set_kernel", "vg_get_kernel", "vg_set_launch_options", "vg_set_adjoint_options", "vg_set_params", "vg_set_regions", "vg_alt_elems", "vg_workspace_bytes", "vg_init_state",
            "vg_step_explicit", "vg_step_subcycled", "vg_solve_implicit_step", "vg_mass_totals", "vg_record", "vg_adjoint",
            "vg_seed_lambda", "vg_load_state", "vg_store_state")
 
@@ -93,6 +94,7 @@ def load():
             "vg_destroy": (I, [P]),
             "vg_set_kernel": (I, [P, I]),
             "vg_get_kernel": (I, [P, ctypes.POINTER(I)]),
+            "vg_set_launch_options": (I, [P, U]),
             "vg_set_adjoint_options": (I, [P, ctypes.c_uint]),
             "vg_set_params": (I, [P, ctypes.POINTER(VgParams)]),
             "vg_set_regions": (I, [P, ctypes.POINTER(D)]),

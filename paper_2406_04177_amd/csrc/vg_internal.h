@@ -541,6 +541,18 @@ struct vg_sim {
     int32_t *adj_flag = nullptr; // [nseg] nonzero: the CO2 adjoint of the volume is not uniform
     int adj_blocks = 0;
 
+    // replayed runs of fused passes (HIP graphs; see vg_step_explicit)
+    unsigned launch_flags = 0;      // VG_LAUNCH_*
+    hipStream_t capture_stream = nullptr;   // private stream the runs are captured on
+    uint64_t graph_version = 0;     // bumped by every change a captured run depends on
+    struct RunGraph {
+        hipGraphExec_t exec = nullptr;
+        int cur = 0, passes = 0, band = 0;
+        double dt = 0;
+        uint64_t version = 0;
+    };
+    RunGraph run_graph[2];          // one per parity of the mobile pools' ping-pong
+
     size_t elem() const { return prec == VG_F64 ? sizeof(double) : sizeof(float); }   // float for VG_F32C
     int mobile_mode() const { return mobile_all ? 2 : 1; }
 };

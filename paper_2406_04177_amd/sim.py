@@ -95,6 +95,12 @@ class Simulation:
         BAND (relative codes, pass pairs in one launch)."""
         _lib.check(self.L.vg_set_kernel(self.h, int(variant)), "vg_set_kernel")
 
+    def set_launch_options(self, graphs: str = "auto"):
+        """Replay runs of fused passes from captured HIP graphs: "auto" (small
+        volumes), "on" or "off"; results are bit-identical either way."""
+        flags = {"auto": _lib.VG_LAUNCH_GRAPHS_AUTO, "on": _lib.VG_LAUNCH_GRAPHS_ON, "off": _lib.VG_LAUNCH_GRAPHS_OFF}
+        _lib.check(self.L.vg_set_launch_options(self.h, flags[graphs]), "vg_set_launch_options")
+
     def kernel_in_use(self) -> int:
         """The kernel the next explicit passes use (TABLE, RANK, OFFSET, RELATIVE or BAND)."""
         v = ctypes.c_int(-1)
