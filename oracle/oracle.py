@@ -120,7 +120,7 @@ class OracleGraph:
         self.shape = tuple(shape)
         self.vox = vox
         self.nbr = nbr
-        self.seg_off = seg_off
+        self.seg_off = np.ascontiguousarray(seg_off, np.int64)   # handed to C as a pointer
 
     @property
     def n(self) -> int:

@@ -46,7 +46,7 @@ class _TotalsFn(torch.autograd.Function):
         sim.set_params(p)
         sim.set_regions(c)
         sim.set_fields(x0)
-        nseg = sim.graph.nseg
+        nseg = sim.nseg
         dev = sim.fields.device
         tot = torch.empty((nsteps + 1, nseg, 6), dtype=torch.float64, device=dev)
         tot[0] = torch.from_numpy(sim.totals()).to(dev)

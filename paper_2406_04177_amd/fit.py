@@ -17,7 +17,13 @@ coordinates instead (torch's optimiser: an option outside the paper).
 
 The loss is the mean over (step, volume) of the squared difference between
 the per-volume CO2 total and the target curve; an epoch uses every volume, or
-the subset of volumes given for it (``inputs.epoch_subsets``).
+the subset of volumes given for it (``inputs.epoch_subsets``).  Options: other
+curves (e.g. DOM and CO2, each divided by a scale) and finer segments (the
+eight octants of every volume, ``octant_segments``), on which the region
+factors act separately.  D_DOM and the region factors enter the model only as
+the products D_DOM c_r (the edge weights scale D), so no loss on the totals
+separates them: ``sensitivity`` / ``identifiability`` show which parameter
+combinations a loss sees.
 """
 from __future__ import annotations
 
@@ -28,17 +34,91 @@ from .autograd import simulate_totals
 from .pngm import sign_update
 
 
-def epoch_loss(sim, theta, x0, target, nsteps, dt, checkpoint_every, vols=None):
-    """Differentiable loss of one epoch ([nsteps+1, nvol] target, CUDA)."""
+def octant_segments(graph) -> np.ndarray:
+    """Segment offsets [nvol * 8 + 1] that split every volume of a graph into
+    its eight octants, for graphs whose compacted lists are octant-major:
+    cubic volumes of even side N enumerated in bricks of side N / 2 (brick
+    k of a volume is then octant k, 4 [z >= N/2] + 2 [y >= N/2] + [x >= N/2]).
+    The per-segment totals of a simulation given these segments are the
+    octant totals (the counts come from the library's region codes)."""
+    nz, ny, nx = graph.shape
+    if not (nx == ny == nz and nx % 2 == 0 and graph.brick == nx // 2):
+        raise ValueError("octant segments need cubic volumes of even side N in bricks of side N / 2")
+    codes = graph.rcode if graph.rcode is not None else graph.make_region_codes()
+    octant = (codes.to(torch.int64) & 7)
+    vol = torch.repeat_interleave(torch.arange(graph.nseg, device=octant.device),
+                                  torch.as_tensor(np.diff(graph.seg_off), device=octant.device))
+    counts = torch.bincount(vol * 8 + octant, minlength=graph.nseg * 8).cpu().numpy()
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    # octant-major inside each volume: the boundaries of the volumes are kept
+    assert np.array_equal(off[::8], graph.seg_off)
+    return off
+
+
+def segments_of(vols, per_vol: int):
+    """Segments of the given volumes when each volume has `per_vol` segments."""
+    return np.concatenate([np.arange(v * per_vol, (v + 1) * per_vol) for v in np.asarray(vols)])
+
+
+def curves_loss(tot, target, curves=(4,), scale=None, segs=None):
+    """Mean over (step, segment, curve) of ((total - target) / scale)^2:
+    tot [nsteps+1, nseg, 5] totals, target [nsteps+1, nseg] (one curve) or
+    [nsteps+1, nseg, len(curves)], scale one factor per curve (or None)."""
+    sel = tot[:, :, list(curves)]
+    if target.dim() == 2:
+        target = target[:, :, None]
+    d = sel - target
+    if scale is not None:
+        d = d / torch.as_tensor(scale, dtype=d.dtype, device=d.device)
+    if segs is not None:
+        d = d[:, torch.as_tensor(np.asarray(segs), device=d.device)]
+    return (d ** 2).mean()
+
+
+def epoch_loss(sim, theta, x0, target, nsteps, dt, checkpoint_every, vols=None, curves=(4,), scale=None,
+               segs_per_vol=1):
+    """Differentiable loss of one epoch (target on the device: [nsteps+1,
+    nseg] for the CO2 curve alone, else [nsteps+1, nseg, len(curves)]);
+    with `segs_per_vol` segments per volume (8: octants), `vols` selects
+    whole volumes."""
     tot = simulate_totals(sim, theta, x0, nsteps, dt, checkpoint_every)
-    if vols is None:
-        return ((tot[:, :, 4] - target) ** 2).mean()
-    idx = torch.as_tensor(np.asarray(vols), device=tot.device)
-    return ((tot[:, idx, 4] - target[:, idx]) ** 2).mean()
+    segs = None if vols is None else segments_of(vols, segs_per_vol)
+    return curves_loss(tot, target, curves, scale, segs)
+
+
+def sensitivity(sim, theta, x0, nsteps, dt, which, curves=(4,), scale=None, rel_eps=1e-4, checkpoint_every=100):
+    """Sensitivity of the totals curves (every step and segment, divided by
+    `scale` per curve) to the logarithm of each parameter in `which`, by
+    central differences of the forward run: J [n_outputs, len(which)].  Its
+    singular values tell which parameter combinations a loss on these curves
+    identifies (a zero singular value: a direction the curves cannot see)."""
+    cols = []
+    with torch.no_grad():
+        for q in which:
+            tp, tm = theta.clone(), theta.clone()
+            h = rel_eps * float(theta[q])
+            tp[q] += h
+            tm[q] -= h
+            up = simulate_totals(sim, tp, x0, nsteps, dt, checkpoint_every)[:, :, list(curves)]
+            dn = simulate_totals(sim, tm, x0, nsteps, dt, checkpoint_every)[:, :, list(curves)]
+            d = (up - dn) / (2 * rel_eps)
+            if scale is not None:
+                d = d / torch.as_tensor(scale, dtype=d.dtype, device=d.device)
+            cols.append(d.reshape(-1))
+    return torch.stack(cols, 1)
+
+
+def identifiability(J, names):
+    """Singular values of J (descending, relative to the largest) and, for
+    the smallest, the parameter direction (unit vector over `names`)."""
+    U, S, Vh = torch.linalg.svd(J.to(torch.float64), full_matrices=False)
+    s = (S / S[0]).cpu().numpy()
+    weakest = Vh[-1].cpu().numpy()
+    return s, dict(zip(names, map(float, weakest)))
 
 
 def fit(sim, x0, target, theta0, nsteps, dt, which, epochs=30, checkpoint_every=100, lr=0.1,
-        halve_every=10, subsets=None, method="sign", box=(0.5, 1.5)):
+        halve_every=10, subsets=None, method="sign", box=(0.5, 1.5), curves=(4,), curve_scale=None, segs_per_vol=1):
     """Returns (theta history [epochs+1, 20] FP64, loss history [epochs])."""
     theta = theta0.detach().to(torch.float64).cpu().clone()
     scale = theta.clone()
@@ -54,7 +134,7 @@ def fit(sim, x0, target, theta0, nsteps, dt, which, epochs=30, checkpoint_every=
         rate = lr * 0.5 ** (e // halve_every)
         th = theta.clone().requires_grad_(True)
         vols = None if subsets is None else subsets[e]
-        loss = epoch_loss(sim, th, x0, target, nsteps, dt, checkpoint_every, vols)
+        loss = epoch_loss(sim, th, x0, target, nsteps, dt, checkpoint_every, vols, curves, curve_scale, segs_per_vol)
         loss.backward()
         g = th.grad.detach()
         losses.append(float(loss.detach()))

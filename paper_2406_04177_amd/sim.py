@@ -39,7 +39,7 @@ class Simulation:
     def __init__(self, graph: Graph, params: ModelParams, precision: str = "f32",
                  implicit: bool = True, adjoint: bool = False, mobile_all=None,
                  step_order: int = _lib.VG_ORDER_TD, regions=None, stream=None, rank_neighbours: bool = True,
-                 band: bool = True):
+                 band: bool = True, segments=None):
         self.L = _lib.load()
         self.graph = graph
         self.precision = precision
@@ -50,20 +50,23 @@ class Simulation:
             mobile_all = any(float(d) != 0.0 for s, d in enumerate(params.D) if s != 1)
         features = ((_lib.VG_FEAT_CG if implicit else 0) | (_lib.VG_FEAT_ADJ if adjoint else 0)
                     | (_lib.VG_FEAT_BAND if band else 0))
-        self._seg = np.ascontiguousarray(graph.seg_off, np.int64)
+        # segments of the totals (and of the adjoint's seeds): the volumes, or
+        # a finer split of the compacted list given by the caller
+        self._seg = np.ascontiguousarray(graph.seg_off if segments is None else segments, np.int64)
+        self.nseg = int(self._seg.size - 1)
         use_regions = regions is not None or graph.rcode is not None
         if use_regions and graph.rcode is None:
             graph.make_region_codes(stream)
         desc = _lib.VgDesc()
         desc.n = graph.n
-        desc.nseg = graph.nseg
+        desc.nseg = self.nseg
         desc.precision = _PREC[precision]
         desc.seg_off = self._seg.ctypes.data
         desc.nbr_d = graph.nbr.data_ptr() if graph.n else None
         desc.rcode_d = graph.rcode.data_ptr() if (use_regions and graph.n) else None
         desc.mobile_all = 1 if mobile_all else 0
         desc.features = features
-        if graph.nseg == 1 and graph.n and rank_neighbours:
+        if self.nseg == 1 and graph.n and rank_neighbours:
             nz, ny, nx = graph.shape
             desc.rank_d = graph.ranks[0].data_ptr()
             desc.vox_d = graph.vox.data_ptr()
@@ -159,7 +162,7 @@ class Simulation:
         nlog = nsteps // log_every if log_every > 0 else 0
         log = totals_out
         if nlog and log is None:
-            log = torch.empty((nlog, self.graph.nseg, 6), dtype=torch.float64, device=self.fields.device)
+            log = torch.empty((nlog, self.nseg, 6), dtype=torch.float64, device=self.fields.device)
         _lib.check(self.L.vg_step_explicit(self.h, int(nsteps), float(dt), int(log_every),
                                            log.data_ptr() if nlog else None,
                                            _lib.VG_FORCE if force else 0, self._sp()), "vg_step_explicit")
@@ -183,7 +186,7 @@ class Simulation:
 
     def totals(self) -> np.ndarray:
         """[nseg, 6] FP64 totals (pools 0-4, total carbon) of the current state."""
-        out = np.zeros((self.graph.nseg, 6), np.float64)
+        out = np.zeros((self.nseg, 6), np.float64)
         _lib.check(self.L.vg_mass_totals(self.h, out.ctypes.data_as(ctypes.c_void_p), self._sp()),
                    "vg_mass_totals")
         return out

@@ -93,3 +93,53 @@ def test_adam_variant_reduces_the_loss():
                        method="adam")
     assert losses[-1] < 0.1 * losses[0]
     assert abs(hist[-1][7] / truth[7] - 1) < 0.03
+
+
+def test_octant_dom_co2_fit_follows_the_oracle():
+    """The loss on per-octant DOM and CO2 curves (three 16^3 volumes in
+    bricks of 8, one segment per octant; D_DOM held as the gauge of the
+    D c_r products): segment offsets, every epoch's loss and every move
+    against the oracle (FP64)."""
+    from paper_2406_04177_amd.fit import fit, octant_segments
+    from paper_2406_04177_amd.graph import Graph
+    from paper_2406_04177_amd.sim import Simulation
+    masks = [inputs.synthetic_volume((16, 16, 16), porosity=por, seed=b) for b, por in enumerate((0.3, 0.35, 0.25))]
+    specs = [inputs.init_random_all(m, b) for b, m in enumerate(masks)]
+    p = inputs.ModelParams(D=(0, 1e-9, 0, 0, 0), v_dom=2e-3, k_dom=0.5, rho=3e-4, mu=2e-4, beta=0.55,
+                           v_som=1e-4, v_p4=2e-4)
+    dt = inputs.explicit_dt(p, 0.8 / 1.5 ** 2)
+    ogb = orc.build_batch(masks, brick=8)
+    og = fo.octant_graph(ogb)
+    x0o = orc.fields_from_spec(ogb, specs)
+    nsteps, epochs = 24, 12
+    truth = theta_np(p, [1.08, 0.93, 1.05, 0.9, 1.1, 0.95, 1.02, 0.97])
+    truth[5] *= 1.06
+    truth[7] *= 0.93
+    tp, tc = fo.theta_to_params(truth, p)
+    _, tot = orc.run(tp, dt, og, x0o, nsteps, w=orc.edge_weights(og, orc.octant_regions(og), tc))
+    target = tot[:, :, [1, 4]]
+    scale = np.abs(target).max(axis=(0, 1))
+    theta0 = theta_np(p)
+    which = [5, 7] + list(range(12, 20))
+    subsets = inputs.epoch_subsets(len(masks), 2, epochs, seed=1)
+    g = Graph.from_masks(masks, brick=8, regions=True)
+    seg = octant_segments(g)
+    np.testing.assert_array_equal(seg, og.seg_off)
+    sim = Simulation(g, p, precision="f64", implicit=False, adjoint=True, regions=[1.0] * 8, segments=seg)
+    x0 = g.fields_from_specs(specs, torch.float64)
+    hist, losses = fit(sim, x0, torch.as_tensor(target, device="cuda"), torch.as_tensor(theta0), nsteps, dt, which,
+                       epochs=epochs, checkpoint_every=5, subsets=subsets, curves=(1, 4), curve_scale=scale, segs_per_vol=8)
+    others = [q for q in range(20) if q not in which]
+    for e in range(epochs):
+        lo, go = fo.loss_and_gradient(hist[e], p, dt, og, x0o, target, subsets[e], curves=(1, 4), scale=scale,
+                                      segs_per_vol=8)
+        assert abs(losses[e] - lo) <= 1e-10 * lo, (e, losses[e], lo)
+        rate = 0.1 * 0.5 ** (e // 10)
+        gmax = np.abs(go[which]).max()
+        for q in which:
+            lo_q, hi_q = 0.5 * theta0[q], 1.5 * theta0[q]
+            moves = [-np.sign(go[q])] if abs(go[q]) > 1e-6 * gmax else [-1.0, 0.0, 1.0]
+            allowed = [min(max(hist[e][q] + m * rate * theta0[q], lo_q), hi_q) for m in moves]
+            assert min(abs(hist[e + 1][q] - a) for a in allowed) <= 1e-12 * theta0[q], (e, q, hist[e + 1][q], allowed)
+        np.testing.assert_array_equal(hist[e + 1][others], theta0[others])
+    assert losses[-1] < losses[0]

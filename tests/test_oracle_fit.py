@@ -94,3 +94,66 @@ def test_fit_recovers_the_respiration_rate():
     assert abs(hist[-1][7] - truth[7]) <= 0.0125 * theta0[7]
     assert losses[-1] < 1e-2 * losses[0]
     np.testing.assert_array_equal(np.delete(hist[-1], 7), np.delete(theta0, 7))
+
+
+def octant_case():
+    """Three 16^3 volumes enumerated in bricks of 8 (octant-major inside each)."""
+    masks = [inputs.synthetic_volume((16, 16, 16), porosity=por, seed=b) for b, por in enumerate((0.3, 0.35, 0.25))]
+    specs = [inputs.init_random_all(m, b) for b, m in enumerate(masks)]
+    og = fo.octant_graph(orc.build_batch(masks, brick=8))
+    p = inputs.ModelParams(D=(0, 1e-9, 0, 0, 0), v_dom=2e-3, k_dom=0.5, rho=3e-4, mu=2e-4, beta=0.55,
+                           v_som=1e-4, v_p4=2e-4)
+    dt = inputs.explicit_dt(p, 0.8)
+    return og, p, dt, orc.fields_from_spec(orc.build_batch(masks, brick=8), specs)
+
+
+def test_octant_graph_by_hand():
+    """Two all-pore 4^3 volumes in bricks of 2: every octant holds 2^3 voxels,
+    segment k of volume v holds exactly octant k of v (named voxels), and the
+    octant totals add up to the volume totals."""
+    masks = [np.ones((4, 4, 4), np.uint8)] * 2
+    og = fo.octant_graph(orc.build_batch(masks, brick=2))
+    assert og.seg_off.tolist() == list(range(0, 129, 8))
+    lin = lambda x, y, z: x + 4 * (y + 4 * z)
+    seg = np.repeat(np.arange(16), 8)
+    where = {int(v): s for v, s in zip(og.vox[:64], seg[:64])}
+    assert where[lin(0, 0, 0)] == 0 and where[lin(1, 1, 1)] == 0
+    assert where[lin(2, 0, 0)] == 1 and where[lin(3, 1, 1)] == 1
+    assert where[lin(0, 2, 0)] == 2 and where[lin(0, 0, 2)] == 4
+    assert where[lin(3, 3, 3)] == 7 and where[lin(2, 2, 2)] == 7
+    assert int(seg[64 + 8 * 3]) == 11                    # volume 1, octant 3
+    x = np.random.default_rng(0).random((5, og.n))
+    t8 = orc.totals(og, x)
+    gvol = orc.OracleGraph(og.shape, og.vox, og.nbr, og.seg_off[::8])
+    np.testing.assert_allclose(t8.reshape(2, 8, 6).sum(axis=1), orc.totals(gvol, x), rtol=1e-14)
+    # raster order is not octant-major: refused
+    with pytest.raises(ValueError):
+        fo.octant_graph(orc.build_batch(masks))
+
+
+@pytest.mark.parametrize("vols", [None, [0, 2]])
+def test_octant_dom_co2_loss_gradient_matches_central_differences(vols):
+    """The loss on the per-octant DOM and CO2 curves (each divided by a scale),
+    on whole volumes or a subset."""
+    og, p, dt, x0 = octant_case()
+    nsteps = 16
+    truth = theta_of(p, [1.1, 0.9, 1.0, 1.05, 0.95, 1.0, 0.92, 1.08])
+    tp, tc = fo.theta_to_params(truth, p)
+    _, tot = orc.run(tp, dt, og, x0, nsteps, w=orc.edge_weights(og, orc.octant_regions(og), tc))
+    target = tot[:, :, [1, 4]]
+    scale = np.abs(target).max(axis=(0, 1))
+    theta = theta_of(p)
+    kw = dict(vols=vols, curves=(1, 4), scale=scale, segs_per_vol=8)
+    loss, g = fo.loss_and_gradient(theta, p, dt, og, x0, target, **kw)
+
+    def central(q, h):
+        tp_, tm_ = theta.copy(), theta.copy()
+        tp_[q] += h
+        tm_[q] -= h
+        return (fo.loss_and_gradient(tp_, p, dt, og, x0, target, **kw)[0]
+                - fo.loss_and_gradient(tm_, p, dt, og, x0, target, **kw)[0]) / (2 * h)
+
+    for q in (1, 5, 7, 12, 15, 19):
+        h = 1e-3 * theta[q]
+        fd = (4 * central(q, h / 2) - central(q, h)) / 3
+        assert abs(g[q] - fd) <= 1e-4 * abs(fd), (q, g[q], fd)
