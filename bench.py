@@ -48,6 +48,8 @@ BYTES_RELATIVE_F32 = 5 * 4 + 5 * 4 + 4 + 32.0 / 64
 # neighbour rows (band of 8 rows: 10/8 of the voxels), the second pass reads
 # four pools and the code word again and writes the five pools; per step half
 BYTES_BAND_F32 = (10.0 / 8 * (4 * 4 + 4 + 32.0 / 64) + (4 * 4 + 4 + 32.0 / 64) + 5 * 4) / 2
+# compensated FP32 fields: the method's algorithmic count with 6-byte values
+BYTES_FUSED_F32C = 5 * 6 + 5 * 6 + 6 * 4
 # compensated FP32 fields (float + 16-bit word per value), relative codes:
 # six bytes per pool read and written, the code word and the group bases
 BYTES_COMP_RELATIVE = 5 * 6 + 5 * 6 + 4 + 32.0 / 64
@@ -648,6 +650,12 @@ def main(argv=None):
     ap.add_argument("--big", type=int, default=1, help="run the 1024^3 explicit-step row (0: skip)")
     ap.add_argument("--kernel", choices=("auto", "table", "rank", "offset", "relative", "band"), default="auto",
                     help="neighbour source of the explicit-step kernel")
+    ap.add_argument("--precision", choices=("f32", "f32c", "f64"), default="f32",
+                    help="fields of the headline step: FP32, compensated FP32 or FP64 (totals FP64 in every case)")
+    ap.add_argument("--rows", default=None,
+                    help="comma-separated rows to run after the headline (default: all unless --quick): " + ",".join(
+                        ("sources", "alg2", "fp64", "implicit", "adjoint", "zlayer", "pngm", "gradient", "fit",
+                         "precision", "copy", "big", "cpu")))
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="finish with three plain 1 GiB device copies (scale for HBM byte counters)")
     args = ap.parse_args(argv)
@@ -678,11 +686,12 @@ def main(argv=None):
     n = g.n
     log("n = %d pore voxels; graph build %.2f ms (incl. mask upload and host sync)" % (n, ms_graph))
 
-    sim = Simulation(g, params, precision="f32", implicit=False, adjoint=False)
+    prec = args.precision
+    sim = Simulation(g, params, precision=prec, implicit=False, adjoint=False)
     sim.set_kernel({"auto": 0, "table": 1, "rank": 2, "offset": 3, "relative": 4, "band": 5}[args.kernel])
     kernel = sim.kernel_in_use()
     x0 = g.fields_from_specs(spec, torch.float32)
-    sim.set_fields(x0)
+    sim.set_fields(x0 if prec == "f32" else g.fields_from_specs(spec, torch.float64))
     sim.step(args.warmup, dt, log_every=100)
     K = args.steps
     # FP64 totals every 100 steps, or once at the end of a shorter timed run
@@ -700,36 +709,41 @@ def main(argv=None):
     ms_k, _ = timed(lambda: sim.step(K2, dt))
     ms_1, _ = timed(lambda: sim.step(1, dt))
     us_launch = (ms_k - ms_1) / ((K2 - 1) / ppl) * 1e3
-    own_bpv = OWN_BYTES[kernel]
     # the roofline counts the method's algorithmic bytes per voxel and step
-    # (five pools read and written plus the 6-slot neighbour table, 64 B)
-    # whichever neighbour source the kernel uses, times the passes one launch
-    # applies; own_bytes_per_voxel is what the kernel itself moves per step
-    bpv = BYTES_FUSED_F32
+    # (five pools read and written plus the 6-slot neighbour table: 64 B for
+    # FP32 fields) whichever neighbour source the kernel uses, times the
+    # passes one launch applies; own_bytes_per_voxel is what the kernel
+    # itself moves per step
+    if prec == "f32":
+        own_bpv, bpv = OWN_BYTES[kernel], BYTES_FUSED_F32
+    elif prec == "f32c":
+        own_bpv, bpv = BYTES_COMP_RELATIVE if kernel == 4 else BYTES_FUSED_F32C, BYTES_FUSED_F32C
+    else:
+        own_bpv, bpv = BYTES_F64_RELATIVE if kernel == 4 else BYTES_FUSED_F64, BYTES_FUSED_F64
     achieved = bpv * ppl * n / (us_launch / 1e6) / 1e9
-    kname = KERNEL_FUNCS[kernel]
+    kname = KERNEL_FUNCS[kernel] if prec != "f32c" else "k_step_c (compensated FP32, relative codes)"
     traffic = None
-    rec = MEASURED_TRAFFIC.get((KERNEL_NAMES[kernel], N))
+    rec = MEASURED_TRAFFIC.get((KERNEL_NAMES[kernel] + ("" if prec == "f32" else "_" + prec), N))
     if rec is not None and rec[1] == sources_sha():
         traffic = rec[0]
-    log("explicit FP32: %.4f ms/step, %.3e voxel-steps/s; %s kernel %.2f us/launch (%d pass(es)), %.0f GB/s "
-        "algorithmic" % (ms_step, vps, KERNEL_NAMES[kernel], us_launch, ppl, achieved))
+    log("explicit %s: %.4f ms/step, %.3e voxel-steps/s; %s kernel %.2f us/launch (%d pass(es)), %.0f GB/s "
+        "algorithmic" % (prec.upper(), ms_step, vps, KERNEL_NAMES[kernel], us_launch, ppl, achieved))
     out = {
         "metric": METRIC,
         "value": 5.0 * vps,
         "unit": "pore-voxel species updates/s",
         "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "%d^3 17%% porosity explicit step, FP32 fields, FP64 totals every %d steps"
-                               % (N, every),
+        "dtype": prec, "data": "synthetic",
+        "config": {"workload": "%d^3 17%% porosity explicit step, %s fields, FP64 totals every %d steps"
+                               % (N, {"f32": "FP32", "f32c": "compensated FP32", "f64": "FP64"}[prec], every),
                    "shape": [N, N, N], "n_pore_voxels": n, "dt_s": dt, "order": "transformation then diffusion",
                    "voxel_steps_per_s": vps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_GBs": None if traffic is None else traffic / (us_launch / 1e6) / 1e9,
                      "traffic_frac": None if traffic is None else traffic / (us_launch / 1e6) / 1e9 / HBM_PEAK_GBS,
-                     "kernel": "%s, FP32, DOM-only diffusion (fused transformation + diffusion)" % kname,
+                     "kernel": "%s, %s, DOM-only diffusion (fused transformation + diffusion)" % (kname, prec.upper()),
                      "neighbour_source": KERNEL_NAMES[kernel],
                      "launch_us": us_launch, "passes_per_launch": ppl, "bytes_per_voxel_step": bpv,
                      "bytes_per_launch": bpv * ppl * n, "own_bytes_per_voxel_step": own_bpv,
@@ -737,22 +751,35 @@ def main(argv=None):
     }
     del tot_log
 
-    if not args.quick:
+    selected = None if args.rows is None else set(r.strip() for r in args.rows.split(",") if r.strip())
+
+    def want(name):
+        return (selected is None and not args.quick) or (selected is not None and name in selected)
+
+    if selected is not None or not args.quick:
         rows = {}
         rows["a1_graph_build_ms"] = ms_graph
+    sim32 = sim
+    if prec != "f32" and (want("sources") or want("alg2")):
+        sim32 = Simulation(g, params, precision="f32", implicit=False, adjoint=False)
+        sim32.set_fields(x0)
+        sim32.step(20, dt)
+        kernel = sim32.kernel_in_use()
+    if want("sources"):
         # the other neighbour sources on the same state, for comparison
         for other in (1, 2, 3, 4, 5):
-            if other == kernel:
+            if other == kernel and prec == "f32":
                 continue
-            sim.set_kernel(other)
-            sim.step(20, dt)
-            mso, _ = timed(lambda: sim.step(K // 2, dt, log_every=100))
+            sim32.set_kernel(other)
+            sim32.step(20, dt)
+            mso, _ = timed(lambda: sim32.step(K // 2, dt, log_every=100))
             rows["fp32_step_%s_kernel" % KERNEL_NAMES[other]] = {
                 "ms_per_step": mso / (K // 2), "own_bytes_per_voxel": OWN_BYTES[other],
                 "achieved_GBs_64B": BYTES_FUSED_F32 * n / (mso / (K // 2) / 1e3) / 1e9,
                 "achieved_GBs_own": OWN_BYTES[other] * n / (mso / (K // 2) / 1e3) / 1e9}
             log("explicit FP32, %s kernel: %.4f ms/step" % (KERNEL_NAMES[other], mso / (K // 2)))
-        sim.set_kernel(kernel)
+        sim32.set_kernel(0)
+    if want("alg2"):
         # Algorithm 2 (sequential transformation) and unequal steps (the
         # paper's test 3 ratio: transformation 4.3x the diffusion step)
         sim2 = Simulation(g, params.replace(sequential=True), precision="f32", implicit=False, adjoint=False)
@@ -772,6 +799,7 @@ def main(argv=None):
         log("Algorithm 2: %.4f ms/step; sub-cycled (dt_t = 4.3 dt_d): %.4f ms per diffusion step"
             % (ms2 / (K // 2), mss / ndiff))
         del sim2
+    if want("fp64") or want("implicit"):
         # plain FP64 step on the same input
         sim64 = Simulation(g, params, precision="f64", implicit=True, adjoint=False)
         sim64.set_fields(x0.double())
@@ -782,6 +810,7 @@ def main(argv=None):
                              "achieved_GBs": BYTES_FUSED_F64 * n / (ms64 / k64 / 1e3) / 1e9,
                              "fp32_speedup": (ms64 / k64) / ms_step}
         log("explicit FP64: %.4f ms/step (FP32 speed-up %.2fx)" % (ms64 / k64, (ms64 / k64) / ms_step))
+    if want("implicit"):
         # a5: implicit step at 20x the explicit bound (FP64 CG vectors, rtol 1e-10)
         dti = 20.0 * inputs.explicit_dt(params, 1.0)
         sim64.set_fields(x0.double())
@@ -796,8 +825,10 @@ def main(argv=None):
                                     "cg_iterations": its, "ms_per_cg_iteration": msi / max(sum(its), 1),
                                     "precision": "f64 fields, f64 CG"}
         log("implicit: %.2f ms/step, CG iterations %s" % (msi / nimp, its))
+    if want("fp64") or want("implicit"):
         del sim64
         torch.cuda.empty_cache()
+    if want("adjoint"):
         # a6: adjoint / forward time ratio over a 20-step segment
         sima = Simulation(g, params, precision="f32", implicit=False, adjoint=True)
         sima.set_fields(x0)
@@ -827,28 +858,33 @@ def main(argv=None):
         log("adjoint/forward ratio %.2f (record %.2f ms, adjoint %.2f ms, forward %.2f ms); "
             "static-pool D gradients skipped: adjoint %.2f ms, ratio %.2f"
             % ((msr + msa) / msf, msr, msa, msf, msa_s, (msr + msa_s) / msf))
-        if args.zlayer:
-            rows["f3_zlayer_diffusion"] = zlayer_experiment(mask)
-        if args.pngm:
-            rows["f4_pngm_512"] = pngm_row(mask)
-        rows["a6_gradient_16x128"] = gradient_batch(args.grad_steps)
-        if args.fit_epochs > 0:
-            rows["f1_fit_16x128"] = fit_batch(args.fit_epochs, steps=args.grad_steps)
-        out["rows"] = rows
-        out["adjoint_forward_ratio"] = rows["a6_gradient_16x128"]["gradient_forward_ratio_all_d"]
         del sima, states, lam
         torch.cuda.empty_cache()
+    if want("zlayer") and args.zlayer:
+        rows["f3_zlayer_diffusion"] = zlayer_experiment(mask)
+    if want("pngm") and args.pngm:
+        rows["f4_pngm_512"] = pngm_row(mask)
+    if want("gradient"):
+        rows["a6_gradient_16x128"] = gradient_batch(args.grad_steps)
+        out["adjoint_forward_ratio"] = rows["a6_gradient_16x128"]["gradient_forward_ratio_all_d"]
+    if want("fit") and args.fit_epochs > 0:
+        rows["f1_fit_16x128"] = fit_batch(args.fit_epochs, steps=args.grad_steps)
+    if selected is not None or not args.quick:
+        out["rows"] = rows
         # FP32 and compensated FP32 fields (FP64 totals) against the plain
         # FP64 step: the 256^3 workload at its length (10^4 steps) and the
         # 512^3 one at its (10^5 steps), totals every 100, error per species
         # (fields, relative to each pool's max) and per totals curve
+    if want("precision"):
         rows["precision_256"] = accuracy_runs(256, args.acc_steps, "FP32 vs FP64 workload")
         if args.long_steps > 0:
             rows["precision_512_long"] = accuracy_runs(N, args.long_steps, "full-size decomposition run")
+    if want("copy"):
         rows["copy_1GiB"] = copy_1gib()
         log("plain 1 GiB device copy: %.0f GB/s (read + written)" % rows["copy_1GiB"]["GBs"])
-        if args.big:
-            rows["explicit_1024"] = step_1024()
+    if want("big") and args.big:
+        rows["explicit_1024"] = step_1024()
+    if want("cpu"):
         # CPU baseline: the oracle on the host cores
         cb = cpu_baseline(mask, spec, params, dt, args.cpu_steps, args.cpu_steps_1t, args.cpu_grad_steps)
         out["cpu_baseline"] = cb
