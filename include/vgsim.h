@@ -283,6 +283,12 @@ typedef struct vg_desc {
  * workspace also holds a row index ((nz * ny + 1) int32) and a second set of
  * the five fields (5 n elements of the field type). */
 #define VG_FEAT_BAND 4
+/* Workspace for the multigrid preconditioner (vg_set_preconditioner): needs
+ * VG_FEAT_CG and a single volume with a rank index (rank_d, vox_d) and no
+ * periodic axis.  Holds the hierarchy, at most about 100 B per cell of the
+ * grid of half the resolution (the bound assumes every 2x2x2 block holds a
+ * pore voxel), built by vg_init_state. */
+#define VG_FEAT_MG   8
 
 /* Creates a handle (host memory only) and sets default parameters. */
 int vg_create(const vg_desc *desc, vg_sim **out);
@@ -380,13 +386,42 @@ int vg_step_explicit(vg_sim *h, int64_t nsteps, double dt, int64_t log_every,
 int vg_step_subcycled(vg_sim *h, int64_t n_t, double dt_t, double dt_d, unsigned flags, void *stream);
 
 /* One implicit step (Scheme 2): the transformation, then for each pool with
- * D_s > 0 the system (I + a_s L_w) y = x_s solved by Jacobi-preconditioned CG
- * in FP64 (start y = x_s; stop at ||x_s - B y||_2 <= rtol ||x_s||_2).
+ * D_s > 0 the system (I + a_s L_w) y = x_s solved by preconditioned CG
+ * (Jacobi as in the paper, or the multigrid option below) in FP64 (start
+ * y = x_s; stop at ||x_s - B y||_2 <= rtol ||x_s||_2).
  * iters_h[5] / relres_h[5] (host, may be NULL) receive the iterations and
  * final relative residual per pool.  Returns VG_ENOCONV if a pool stopped at
  * max_iter (the state still takes the last iterate).  Synchronises stream. */
 int vg_solve_implicit_step(vg_sim *h, double dt, double rtol, int max_iter, int *iters_h,
                            double *relres_h, void *stream);
+
+/* Preconditioner of the implicit step's CG.  VG_PRECOND_JACOBI (default):
+ * the inverse diagonal of the system matrix, as in Sec. III.
+ * VG_PRECOND_MG (an addition to the paper; needs a handle created with
+ * VG_FEAT_MG): one V-cycle over aggregates of 2x2x2 cells.  Level l+1 has a
+ * cell for every occupied 2x2x2 block of level l's grid (level 0: the pore
+ * voxels); its operator is the Galerkin product P^T B P with the piecewise-
+ * constant P, i.e. again mass + a * weighted Laplacian, with the number of
+ * voxels of a cell as its mass and the summed weights of the edges between
+ * two cells as their weight.  Damped Jacobi (omega 0.8) once before and once
+ * after each coarse correction, 8 sweeps on the coarsest level (at most 4096
+ * cells, or where the grid stops shrinking).  A fixed symmetric positive
+ * definite map, so the iteration is still CG with the same stopping rule; it
+ * takes far fewer iterations for a = D dt / h^2 >> 1 at about twice the
+ * cost of one.  Summation orders are fixed (results do not depend on
+ * scheduling).  VG_EINVAL for MG without VG_FEAT_MG; with a grid that cannot
+ * be coarsened (one voxel) MG falls back to Jacobi. */
+#define VG_PRECOND_JACOBI 0
+#define VG_PRECOND_MG     1
+int vg_set_preconditioner(vg_sim *h, int which);
+/* Levels of the multigrid hierarchy (0 without VG_FEAT_MG) and, if cells_h
+ * is not NULL, the cells of each (cells_h[VG_MG_MAX_LEVELS], level 0 = n). */
+#define VG_MG_MAX_LEVELS 12
+int vg_mg_levels(const vg_sim *h, int *levels, int64_t *cells_h);
+/* z = M^-1 r for the system I + a L_w: the current preconditioner applied
+ * once (r_d, z_d: device [n] FP64, distinct).  Uses the CG vectors of the
+ * workspace (do not overlap with an implicit step on the same handle). */
+int vg_precondition(vg_sim *h, double a, const double *r_d, double *z_d, void *stream);
 
 /* Totals of the bound state: out_h[g][0..5] (host), FP64, fixed summation
  * order.  Returns VG_ENONFINITE if any total is not finite.  Synchronises. */

@@ -18,7 +18,9 @@ VG_OK, VG_EINVAL, VG_EUNSTABLE, VG_ENOCONV, VG_ENONFINITE, VG_EHIP, VG_ESTATE = 
 VG_F32, VG_F64, VG_F32C = 0, 1, 2
 VG_ORDER_TD, VG_ORDER_DT = 0, 1
 VG_FORCE = 1
-VG_FEAT_CG, VG_FEAT_ADJ, VG_FEAT_BAND = 1, 2, 4
+VG_FEAT_CG, VG_FEAT_ADJ, VG_FEAT_BAND, VG_FEAT_MG = 1, 2, 4, 8
+VG_PRECOND_JACOBI, VG_PRECOND_MG = 0, 1
+VG_MG_MAX_LEVELS = 12
 VG_NPOOL, VG_NREG, VG_NGRAD = 5, 8, 20
 VG_KERNEL_AUTO, VG_KERNEL_TABLE, VG_KERNEL_RANK, VG_KERNEL_OFFSET, VG_KERNEL_RELATIVE, VG_KERNEL_BAND = 0, 1, 2, 3, 4, 5
 VG_ADJ_SKIP_STATIC_D = 1
@@ -30,7 +32,8 @@ EXPORTS = ("vg_strerror", "vg_last_error", "vg_version", "vg_rank_bytes", "vg_co
            "vg_brick_stats", "vg_pngm_partition_bytes", "vg_pngm_partition", "vg_pngm_loss_grad", "vg_pngm_step", "vg_pngm_implicit_step",
            "vg_pngm_implicit_step_noalloc", "vg_sign_update", "vg_create", "vg_destroy",
            "vg_set_kernel", "vg_get_kernel", "vg_set_launch_options", "vg_set_adjoint_options", "vg_set_params", "vg_set_regions", "vg_alt_elems", "vg_workspace_bytes", "vg_init_state",
-           "vg_step_explicit", "vg_step_subcycled", "vg_solve_implicit_step", "vg_mass_totals", "vg_record", "vg_adjoint",
+           "vg_step_explicit", "vg_step_subcycled", "vg_solve_implicit_step", "vg_set_preconditioner",
+           "vg_mg_levels", "vg_precondition", "vg_mass_totals", "vg_record", "vg_adjoint",
            "vg_seed_lambda", "vg_load_state", "vg_store_state")
 
 
@@ -104,6 +107,9 @@ def load():
             "vg_step_explicit": (I, [P, I64, D, I64, P, U, P]),
             "vg_step_subcycled": (I, [P, I64, D, D, U, P]),
             "vg_solve_implicit_step": (I, [P, D, D, I, P, P, P]),
+            "vg_set_preconditioner": (I, [P, I]),
+            "vg_mg_levels": (I, [P, ctypes.POINTER(I), P]),
+            "vg_precondition": (I, [P, D, P, P, P]),
             "vg_mass_totals": (I, [P, P, P]),
             "vg_record": (I, [P, I64, D, P, P]),
             "vg_adjoint": (I, [P, I64, D, P, P, P, P, P]),

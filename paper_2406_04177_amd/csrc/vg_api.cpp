@@ -99,6 +99,31 @@ size_t layout(vg_sim *h, char *base) {
         h->cg_part = (double *)take(sizeof(double) * 4 * (size_t)h->cg_blocks);
         h->cg_scal = (double *)take(sizeof(double) * 8);
     }
+    if (h->features & VG_FEAT_MG) {
+        // the hierarchy at the capacities mg_plan reserved (set-up scratch:
+        // the occupancy bytes of the largest coarse grid)
+        h->mg[0].parent = (int32_t *)take(sizeof(int32_t) * (size_t)h->n);
+        size_t mask = 1;
+        for (int l = 1; l < h->mg_plan_levels; l++) {
+            vg_sim::MgLevel &L = h->mg[l];
+            const size_t cap = (size_t)L.cap;
+            L.vox = (int32_t *)take(sizeof(int32_t) * cap);
+            L.nbr = (int32_t *)take(sizeof(int32_t) * 6 * cap);
+            L.w = (float *)take(sizeof(float) * 6 * cap);
+            L.mass = (float *)take(sizeof(float) * cap);
+            L.invd = (double *)take(sizeof(double) * cap);
+            L.r = (double *)take(sizeof(double) * cap);
+            L.x = (double *)take(sizeof(double) * cap);
+            L.e = (double *)take(sizeof(double) * cap);
+            L.parent = (int32_t *)take(sizeof(int32_t) * cap);
+            size_t rb = 0;
+            vg_rank_bytes(L.nx, L.ny, L.nz, 0, &rb);
+            L.rank = (RankWord *)take(rb);
+            const size_t cells = (size_t)L.nx * (size_t)L.ny * (size_t)L.nz;
+            mask = cells > mask ? cells : mask;
+        }
+        h->mg_mask = (uint8_t *)take(mask);
+    }
     if (h->features & VG_FEAT_ADJ) {
         h->lam_alt = take(h->elem() * VG_NPOOL * (size_t)h->n);
         h->adj_part = (double *)take(sizeof(double) * VG_NGRAD * (size_t)h->adj_blocks);
@@ -256,7 +281,10 @@ extern "C" int vg_create(const vg_desc *d, vg_sim **out) {
     if (d->seg_off[0] != 0 || d->seg_off[d->nseg] != d->n) { set_error("seg_off must run from 0 to n"); return VG_EINVAL; }
     for (int g = 0; g < d->nseg; g++)
         if (d->seg_off[g + 1] < d->seg_off[g]) { set_error("seg_off must be non-decreasing"); return VG_EINVAL; }
-    if (d->features & ~(VG_FEAT_CG | VG_FEAT_ADJ | VG_FEAT_BAND)) { set_error("unknown feature bits"); return VG_EINVAL; }
+    if (d->features & ~(VG_FEAT_CG | VG_FEAT_ADJ | VG_FEAT_BAND | VG_FEAT_MG)) {
+        set_error("unknown feature bits");
+        return VG_EINVAL;
+    }
     vg_sim *h = new (std::nothrow) vg_sim();
     if (!h) { set_error("out of host memory"); return VG_EINVAL; }
     h->n = d->n;
@@ -291,6 +319,15 @@ extern "C" int vg_create(const vg_desc *d, vg_sim **out) {
     p.mort_to_p4 = 0;
     p.step_order = VG_ORDER_TD;
     h->params = p;
+    if (h->features & VG_FEAT_MG) {
+        if (!(h->features & VG_FEAT_CG) || !h->rank) {
+            set_error("VG_FEAT_MG needs VG_FEAT_CG and a single volume with a rank index, no periodic axis and "
+                      "every dimension <= 1024");
+            delete h;
+            return VG_EINVAL;
+        }
+        mg_plan(h);
+    }
     make_pieces(h);
     *out = h;
     return VG_OK;
@@ -423,6 +460,7 @@ extern "C" int vg_set_regions(vg_sim *h, const double *c) {
         if (!(c[r] > 0) || !std::isfinite(c[r])) { set_error("region factors must be finite and > 0"); return VG_EINVAL; }
     for (int r = 0; r < VG_NREG; r++) h->c[r] = c[r];
     drop_graphs(h);
+    h->mg_wdone = false;   // the coarse weights sum the region-weighted edges
     return VG_OK;
 }
 
@@ -440,6 +478,11 @@ extern "C" int vg_workspace_bytes(const vg_sim *h, size_t *bytes) {
     tmp.nchunks = h->nchunks;
     tmp.rank = h->rank;   // the geometry words are part of the workspace when a rank index is used
     tmp.vox = h->vox; tmp.nx = h->nx; tmp.ny = h->ny; tmp.nz = h->nz; tmp.brick = h->brick; tmp.periodic = h->periodic;
+    tmp.mg_plan_levels = h->mg_plan_levels;
+    for (int l = 0; l < h->mg_plan_levels; l++) {
+        tmp.mg[l].nx = h->mg[l].nx; tmp.mg[l].ny = h->mg[l].ny; tmp.mg[l].nz = h->mg[l].nz;
+        tmp.mg[l].cap = h->mg[l].cap;
+    }
     *bytes = layout(&tmp, nullptr);
     return VG_OK;
 }
@@ -484,6 +527,7 @@ extern "C" int vg_init_state(vg_sim *h, void *fields_d, void *alt_d, void *work_
     if ((rc = launch_geometry(h, s))) return rc;
     if ((rc = build_offsets(h, s))) return rc;
     if ((rc = build_band(h, s))) return rc;
+    if ((h->features & VG_FEAT_MG) && (rc = mg_build(h, s))) return rc;
     // the host tables must outlive the asynchronous copies
     if ((rc = hip_status(hipStreamSynchronize(s), "synchronise"))) return rc;
     h->bound = true;
@@ -649,6 +693,34 @@ extern "C" int vg_solve_implicit_step(vg_sim *h, double dt, double rtol, int max
     if (status == VG_ENOCONV) set_error("CG reached max_iter = %d above rtol = %g", max_iter, rtol);
     if ((rc = hip_status(hipStreamSynchronize(s), "synchronise"))) return rc;
     return status;
+}
+
+extern "C" int vg_set_preconditioner(vg_sim *h, int which) {
+    if (!h) { set_error("handle is NULL"); return VG_EINVAL; }
+    if (which != VG_PRECOND_JACOBI && which != VG_PRECOND_MG) { set_error("unknown preconditioner"); return VG_EINVAL; }
+    if (which == VG_PRECOND_MG && !(h->features & VG_FEAT_MG)) {
+        set_error("the multigrid preconditioner needs a handle created with VG_FEAT_MG");
+        return VG_EINVAL;
+    }
+    h->precond = which;
+    return VG_OK;
+}
+
+extern "C" int vg_mg_levels(const vg_sim *h, int *levels, int64_t *cells_h) {
+    if (!h || !levels) { set_error("null pointer argument"); return VG_EINVAL; }
+    *levels = h->mg_levels;
+    if (cells_h)
+        for (int l = 0; l < VG_MG_MAX_LEVELS; l++) cells_h[l] = l < h->mg_levels ? h->mg[l].n : 0;
+    return VG_OK;
+}
+
+extern "C" int vg_precondition(vg_sim *h, double a, const double *r_d, double *z_d, void *stream) {
+    int rc = need_bound(h);
+    if (rc) return rc;
+    if (!(h->features & VG_FEAT_CG)) { set_error("handle created without VG_FEAT_CG"); return VG_ESTATE; }
+    if (!(a >= 0) || !std::isfinite(a)) { set_error("need a finite a >= 0"); return VG_EINVAL; }
+    if (h->n > 0 && (!r_d || !z_d || r_d == z_d)) { set_error("need distinct r_d and z_d"); return VG_EINVAL; }
+    return mg_apply(h, a, r_d, z_d, (hipStream_t)stream);
 }
 
 extern "C" int vg_record(vg_sim *h, int64_t nsteps, double dt, void *states_d, void *stream) {

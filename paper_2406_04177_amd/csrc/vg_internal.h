@@ -533,6 +533,25 @@ struct vg_sim {
     double *cg_part = nullptr;   // [cg_blocks][4]
     double *cg_scal = nullptr;   // scalars (see vg_cg.hip)
     int cg_blocks = 0;
+    // multigrid preconditioner of the CG (VG_FEAT_MG; vg_cg.hip).  Level 0 is
+    // the pore voxels (the CG's own vectors); levels >= 1 are aggregates.
+    struct MgLevel {
+        int64_t n = 0, cap = 0;          // cells; capacity reserved in the workspace
+        int nx = 0, ny = 0, nz = 0;      // grid of the level
+        int32_t *vox = nullptr;          // [cap] linear index of each cell in its grid (levels >= 1)
+        int32_t *nbr = nullptr;          // [6][cap] neighbour cells, -1 if absent (levels >= 1)
+        float *w = nullptr;              // [6][cap] edge weights, 0 if absent (levels >= 1)
+        float *mass = nullptr;           // [cap] voxels in the cell (levels >= 1)
+        double *invd = nullptr, *r = nullptr, *x = nullptr, *e = nullptr;   // [cap] (levels >= 1)
+        int32_t *parent = nullptr;       // [cap] cell of the next level (all but the coarsest)
+        vg::RankWord *rank = nullptr;    // rank index of the grid (levels >= 1; level 0 uses the handle's)
+    };
+    MgLevel mg[VG_MG_MAX_LEVELS];
+    int mg_levels = 0;                   // levels built (0: none)
+    int mg_plan_levels = 0;              // levels the workspace reserves
+    bool mg_wdone = false;               // coarse weights follow the current region factors
+    uint8_t *mg_mask = nullptr;          // set-up scratch: occupancy of the next coarser grid
+    int precond = VG_PRECOND_JACOBI;
     // adjoint
     unsigned adj_flags = 0;      // VG_ADJ_* options
     char *lam_alt = nullptr;     // [5][n] field type
@@ -581,6 +600,11 @@ int restore_canonical(vg_sim *h, hipStream_t s);
 // vg_cg.hip
 int run_cg(vg_sim *h, int pool, double a, double rtol, int max_iter, int *iters, double *relres,
            hipStream_t s);
+// grids and capacities of the multigrid levels the workspace reserves
+// (fills h->mg[*].nx/ny/nz/cap and h->mg_plan_levels)
+void mg_plan(vg_sim *h);
+int mg_build(vg_sim *h, hipStream_t s);    // the hierarchy (structure and weights), at vg_init_state
+int mg_apply(vg_sim *h, double a, const double *r, double *z, hipStream_t s);   // vg_precondition
 // vg_adjoint.hip
 int launch_record(vg_sim *h, int64_t nsteps, double dt, void *states, hipStream_t s);
 int launch_adjoint(vg_sim *h, int64_t nsteps, double dt, const void *states, const double *seeds,

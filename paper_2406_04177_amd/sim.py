@@ -39,7 +39,7 @@ class Simulation:
     def __init__(self, graph: Graph, params: ModelParams, precision: str = "f32",
                  implicit: bool = True, adjoint: bool = False, mobile_all=None,
                  step_order: int = _lib.VG_ORDER_TD, regions=None, stream=None, rank_neighbours: bool = True,
-                 band: bool = True, segments=None):
+                 band: bool = True, segments=None, multigrid: bool = False):
         self.L = _lib.load()
         self.graph = graph
         self.precision = precision
@@ -49,7 +49,7 @@ class Simulation:
         if mobile_all is None:
             mobile_all = any(float(d) != 0.0 for s, d in enumerate(params.D) if s != 1)
         features = ((_lib.VG_FEAT_CG if implicit else 0) | (_lib.VG_FEAT_ADJ if adjoint else 0)
-                    | (_lib.VG_FEAT_BAND if band else 0))
+                    | (_lib.VG_FEAT_BAND if band else 0) | (_lib.VG_FEAT_MG if multigrid else 0))
         # segments of the totals (and of the adjoint's seeds): the volumes, or
         # a finer split of the compacted list given by the caller
         self._seg = np.ascontiguousarray(graph.seg_off if segments is None else segments, np.int64)
@@ -183,6 +183,30 @@ class Simulation:
         if check:
             _lib.check(rc, "vg_solve_implicit_step")
         return list(it), list(rr), rc
+
+    def set_preconditioner(self, which: str = "jacobi"):
+        """Preconditioner of the implicit step's CG: "jacobi" (the paper's) or
+        "mg" (the multigrid V-cycle; needs multigrid=True at construction)."""
+        v = {"jacobi": _lib.VG_PRECOND_JACOBI, "mg": _lib.VG_PRECOND_MG}[which]
+        _lib.check(self.L.vg_set_preconditioner(self.h, v), "vg_set_preconditioner")
+
+    def mg_levels(self) -> list:
+        """Cells of each level of the multigrid hierarchy (empty without one)."""
+        lv = ctypes.c_int(0)
+        cells = (ctypes.c_int64 * _lib.VG_MG_MAX_LEVELS)()
+        _lib.check(self.L.vg_mg_levels(self.h, ctypes.byref(lv), cells), "vg_mg_levels")
+        return [int(cells[l]) for l in range(lv.value)]
+
+    def precondition(self, a: float, r: torch.Tensor) -> torch.Tensor:
+        """z = M^-1 r for the system I + a L_w with the current preconditioner
+        (r: [n] float64 on the device)."""
+        r = r.contiguous()
+        if r.dtype != torch.float64 or r.numel() != self.graph.n:
+            raise ValueError("r must be a float64 vector of n entries")
+        z = torch.empty_like(r)
+        _lib.check(self.L.vg_precondition(self.h, float(a), r.data_ptr(), z.data_ptr(), self._sp()),
+                   "vg_precondition")
+        return z
 
     def totals(self) -> np.ndarray:
         """[nseg, 6] FP64 totals (pools 0-4, total carbon) of the current state."""

@@ -252,7 +252,7 @@ def test_band_feature_workspace():
     rc, h, _ = make_handle(features=_lib.VG_FEAT_BAND)
     assert rc == 0
     L.vg_destroy(h)
-    rc, h, _ = make_handle(features=8)
+    rc, h, _ = make_handle(features=16)
     assert rc == _lib.VG_EINVAL
     n = 1 << 20
 
@@ -354,3 +354,54 @@ def test_pngm_partition_sizes_and_validation():
         bad = list(args)
         bad[k] = None
         assert L.vg_pngm_partition(*bad) == _lib.VG_EINVAL
+
+
+def test_multigrid_feature_validation_and_workspace():
+    """VG_FEAT_MG needs VG_FEAT_CG and a single volume with a rank index and
+    no periodic axis; it reserves the hierarchy at its bound (level l + 1:
+    min(cells of level l, cells of the half-resolution grid), about 92 B per
+    cell plus the grid's rank index) and a parent index per voxel.  The
+    preconditioner choice and the level query validate on the host."""
+    L = _lib.load()
+    n = 1 << 18
+    CG, MG = _lib.VG_FEAT_CG, _lib.VG_FEAT_MG
+
+    def create(features, rank=True, periodic=0, side=64):
+        seg = np.array([0, n], np.int64)
+        desc = _lib.VgDesc()
+        desc.n, desc.nseg, desc.precision = n, 1, _lib.VG_F64
+        desc.seg_off = seg.ctypes.data
+        desc.nbr_d = 0x1000
+        desc.features = features
+        if rank:
+            desc.rank_d, desc.vox_d = 0x2000, 0x3000    # never dereferenced here
+            desc.nx = desc.ny = desc.nz = side
+            desc.periodic = periodic
+        h = ctypes.c_void_p()
+        return L.vg_create(ctypes.byref(desc), ctypes.byref(h)), h
+
+    for bad in (dict(features=MG), dict(features=CG | MG, rank=False), dict(features=CG | MG, periodic=1)):
+        rc, _ = create(**bad)
+        assert rc == _lib.VG_EINVAL, bad
+        assert b"VG_FEAT_MG" in L.vg_last_error()
+    rc, h0 = create(CG)
+    rc1, h1 = create(CG | MG)
+    assert rc == 0 and rc1 == 0
+    w0, w1 = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert L.vg_workspace_bytes(h0, ctypes.byref(w0)) == 0 and L.vg_workspace_bytes(h1, ctypes.byref(w1)) == 0
+    caps = [32 ** 3, 16 ** 3, 8 ** 3, 4 ** 3, 2 ** 3, 1]    # levels 1.. of a 64^3 grid (n > 32^3)
+    assert w1.value - w0.value >= 4 * n + 92 * sum(caps)
+    assert w1.value - w0.value <= 4 * n + 92 * sum(caps) + 64 * 1024 + 32 ** 3 + 256 * 40
+    # preconditioner choice
+    assert L.vg_set_preconditioner(h0, _lib.VG_PRECOND_MG) == _lib.VG_EINVAL
+    assert b"VG_FEAT_MG" in L.vg_last_error()
+    assert L.vg_set_preconditioner(h1, 7) == _lib.VG_EINVAL
+    assert L.vg_set_preconditioner(h1, _lib.VG_PRECOND_MG) == 0
+    assert L.vg_set_preconditioner(h0, _lib.VG_PRECOND_JACOBI) == 0
+    lv = ctypes.c_int(-1)
+    cells = (ctypes.c_int64 * _lib.VG_MG_MAX_LEVELS)()
+    assert L.vg_mg_levels(h1, ctypes.byref(lv), cells) == 0 and lv.value == 0    # built by vg_init_state
+    assert L.vg_mg_levels(h1, None, None) == _lib.VG_EINVAL
+    assert L.vg_precondition(h1, 1.0, 0x1000, 0x2000, None) == _lib.VG_ESTATE   # nothing bound yet
+    for h in (h0, h1):
+        L.vg_destroy(h)
