@@ -531,6 +531,7 @@ def zlayer_experiment(mask):
     1.76 h of diffusion, explicit 0.1 s steps vs implicit 30 s steps, the DOM
     mass per z-layer."""
     import numpy as np
+    import torch
     from paper_2406_04177_amd import diffusion_experiment as de
     from paper_2406_04177_amd.graph import Graph
     g = Graph.from_masks(mask)
@@ -540,18 +541,28 @@ def zlayer_experiment(mask):
     ms_i, (sim_i, its) = timed(lambda: de.run_implicit(mask, g, dt=30.0, precision="f32", rtol=1e-10))
     pi = de.layer_profile(sim_i, mask)
     del sim_i
+    torch.cuda.empty_cache()
+    ms_m, (sim_m, its_m) = timed(lambda: de.run_implicit(mask, g, dt=30.0, precision="f32", rtol=1e-10,
+                                                           multigrid=True))
+    pm = de.layer_profile(sim_m, mask)
+    del sim_m
     res = {"workload": "512^3, M0 = %.4f mg on layers 0-1, D = 100950 voxel^2/day, %.0f s" % (de.M0, de.T_END),
            "explicit": {"dt_s": 0.1, "steps": nsteps, "ms": ms_e, "mass_rel_err": float(abs(pe.sum() / de.M0 - 1))},
            "implicit": {"dt_s": 30.0, "steps": len(its), "cg_iterations": int(sum(its)), "ms": ms_i,
-                        "mass_rel_err": float(abs(pi.sum() / de.M0 - 1))},
+                        "mass_rel_err": float(abs(pi.sum() / de.M0 - 1)), "preconditioner": "Jacobi (the paper's)"},
+           "implicit_multigrid": {"dt_s": 30.0, "steps": len(its_m), "cg_iterations": int(sum(its_m)), "ms": ms_m,
+                                  "mass_rel_err": float(abs(pm.sum() / de.M0 - 1)),
+                                  "profile_max_abs_diff_vs_jacobi_rel_to_peak": float(np.abs(pm - pi).max() / pi.max()),
+                                  "note": "ms includes building the hierarchy"},
            "profile_max_abs_diff_rel_to_peak": float(np.abs(pe - pi).max() / pe.max()),
            "profile_layers_0_4_explicit": [float(v) for v in pe[:5]],
            "profile_layers_0_4_implicit": [float(v) for v in pi[:5]],
            "layer_of_half_mass_explicit": int(np.searchsorted(np.cumsum(pe), de.M0 / 2)),
            "layer_of_half_mass_implicit": int(np.searchsorted(np.cumsum(pi), de.M0 / 2))}
-    log("z-layer experiment: explicit %d steps %.1f s, implicit %d steps (%d CG iterations) %.1f s; "
-        "profiles differ by %.2e of the peak" % (nsteps, ms_e / 1e3, len(its), sum(its), ms_i / 1e3,
-                                                  res["profile_max_abs_diff_rel_to_peak"]))
+    log("z-layer experiment: explicit %d steps %.1f s, implicit %d steps (%d CG iterations) %.1f s, with "
+        "multigrid %d CG iterations %.1f s; profiles differ by %.2e of the peak"
+        % (nsteps, ms_e / 1e3, len(its), sum(its), ms_i / 1e3, sum(its_m), ms_m / 1e3,
+           res["profile_max_abs_diff_rel_to_peak"]))
     return res
 
 
@@ -803,7 +814,9 @@ def main(argv=None):
         del sim2
     if want("fp64") or want("implicit"):
         # plain FP64 step on the same input
-        sim64 = Simulation(g, params, precision="f64", implicit=True, adjoint=False)
+        t_mg = time.perf_counter()
+        sim64 = Simulation(g, params, precision="f64", implicit=True, adjoint=False, multigrid=want("implicit"))
+        ms_mg_setup = (time.perf_counter() - t_mg) * 1e3
         sim64.set_fields(x0.double())
         sim64.step(20, dt)
         k64 = max(K // 4, 50)
@@ -825,8 +838,23 @@ def main(argv=None):
         msi, _ = timed(imp)
         rows["a5_implicit_step"] = {"dt_s": dti, "rtol": 1e-10, "ms_per_step": msi / nimp,
                                     "cg_iterations": its, "ms_per_cg_iteration": msi / max(sum(its), 1),
-                                    "precision": "f64 fields, f64 CG"}
+                                    "precision": "f64 fields, f64 CG", "preconditioner": "Jacobi (the paper's)"}
         log("implicit: %.2f ms/step, CG iterations %s" % (msi / nimp, its))
+        # the same steps with the multigrid V-cycle as preconditioner
+        sim64.set_preconditioner("mg")
+        sim64.set_fields(x0.double())
+        sim64.implicit_step(dti)
+        its_mg = []
+        def imp_mg():
+            for _ in range(nimp):
+                its_mg.append(sim64.implicit_step(dti, rtol=1e-10)[0][1])
+        msm, _ = timed(imp_mg)
+        rows["a5_implicit_step"]["multigrid"] = {
+            "ms_per_step": msm / nimp, "cg_iterations": its_mg, "ms_per_cg_iteration": msm / max(sum(its_mg), 1),
+            "levels": sim64.mg_levels(), "ms_handle_with_hierarchy": ms_mg_setup,
+            "speedup_vs_jacobi": (msi / nimp) / (msm / nimp)}
+        log("implicit, multigrid: %.2f ms/step, CG iterations %s, levels %s" % (msm / nimp, its_mg,
+                                                                              sim64.mg_levels()))
     if want("fp64") or want("implicit"):
         del sim64
         torch.cuda.empty_cache()

@@ -404,8 +404,8 @@ int vg_solve_implicit_step(vg_sim *h, double dt, double rtol, int max_iter, int 
  * constant P, i.e. again mass + a * weighted Laplacian, with the number of
  * voxels of a cell as its mass and the summed weights of the edges between
  * two cells as their weight.  Damped Jacobi (omega 0.8) once before and once
- * after each coarse correction, 8 sweeps on the coarsest level (at most 4096
- * cells, or where the grid stops shrinking).  A fixed symmetric positive
+ * after each coarse correction, 8 sweeps on the coarsest level (at most 1024
+ * cells).  A fixed symmetric positive
  * definite map, so the iteration is still CG with the same stopping rule; it
  * takes far fewer iterations for a = D dt / h^2 >> 1 at about twice the
  * cost of one.  Summation orders are fixed (results do not depend on

@@ -103,6 +103,7 @@ size_t layout(vg_sim *h, char *base) {
         // the hierarchy at the capacities mg_plan reserved (set-up scratch:
         // the occupancy bytes of the largest coarse grid)
         h->mg[0].parent = (int32_t *)take(sizeof(int32_t) * (size_t)h->n);
+        h->mg[0].e = (double *)take(sizeof(double) * (size_t)h->n);   // fine residual / prolongated iterate
         size_t mask = 1;
         for (int l = 1; l < h->mg_plan_levels; l++) {
             vg_sim::MgLevel &L = h->mg[l];

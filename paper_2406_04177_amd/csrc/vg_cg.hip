@@ -36,14 +36,24 @@
 // than its diagonal).  The restriction is computed per coarse cell from its
 // children (found with the level's rank index in a fixed order) and the
 // prolongation per fine cell from its parent, so no sum depends on
-// scheduling.  In MG mode the update kernel forms r and r.r only; the
-// V-cycle's last kernel writes z and the r.z partials.
+// scheduling.  Every level's kernels are one thread per cell: residual,
+// restriction (sum over the children), prolongation (add the parent's
+// value), post-smoothing.  In MG mode the update kernel also forms the
+// pre-smoothed iterate w D^-1 r (in z); the V-cycle's last kernel writes z
+// and the r.z partials.
 #include "vg_internal.h"
 
 namespace vg {
 namespace {
 
 enum { S_RZ = 0, S_RR, S_BB, S_ALPHA, S_BETA, S_DONE, S_ITER, S_RTOL2, S_NSCAL = 8 };
+
+// multigrid V-cycle
+constexpr double kMgOmega = 0.8;        // damping of the Jacobi smoother
+constexpr int64_t kMgCoarsest = 1024;   // a level this small is solved by sweeps alone
+constexpr int kMgSweeps = 8;            // damped Jacobi sweeps on the coarsest level
+constexpr int kMgCoarseThreads = 1024;  // the coarsest level's single block
+constexpr int kMgCoarseMax = 4096;      // cells the coarsest kernel holds in LDS
 
 __device__ __forceinline__ double weight(const uint16_t *rcode, const double *cl, int64_t i, int k,
                                          bool reg) {
@@ -126,8 +136,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs A, F field,
         const double zi = mi * ri;
         y[i] = b;
         r[i] = ri;
-        if (!MG) z[i] = zi;
-        p[i] = MG ? 0.0 : zi;   // MG: z comes from the V-cycle, and the first direction is z + 0 * p
+        // MG: z holds the V-cycle's pre-smoothed iterate w D^-1 r until the
+        // cycle overwrites it; the first direction is then z + 0 * p
+        z[i] = MG ? kMgOmega * ri * mi : zi;
+        p[i] = MG ? 0.0 : zi;
         if (REG) m[i] = mi;
         else ((uint8_t *)m)[i] = (uint8_t)deg;   // 1/diag is then one of 7 values
         q[i] = 0.0;    // B p of no direction: the first q is B z alone (beta = 0)
@@ -214,9 +226,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, int64_t ntiles,
         const int64_t i = t * kTile + v * kBlock + threadIdx.x;
         if (i >= n) continue;
         const double ri = r[i] - alpha * q[i];
+        const double mi = REG ? m[i] : mtab[((const uint8_t *)m)[i]];
         r[i] = ri;
-        if (!MG) {
-            const double zi = (REG ? m[i] : mtab[((const uint8_t *)m)[i]]) * ri;
+        if (MG) {
+            z[i] = kMgOmega * ri * mi;   // the V-cycle's pre-smoothed iterate
+        } else {
+            const double zi = mi * ri;
             z[i] = zi;
             acc[0] += ri * zi;
         }
@@ -225,7 +240,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, int64_t ntiles,
     }
     block_sum<2>(acc, lds);
     if (threadIdx.x == 0) {
-        if (!MG) part[(int64_t)blockIdx.x * 4] = acc[0];
+        if (!MG) part[(int64_t)blockIdx.x * 4] = acc[0];   // MG: the V-cycle writes r.z
         part[(int64_t)blockIdx.x * 4 + 1] = acc[1];
     }
 }
@@ -272,11 +287,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_writeback(int64_t n, const double
 }
 
 // ---------------------------------------------------------------- multigrid
-constexpr double kMgOmega = 0.8;        // damping of the Jacobi smoother
-constexpr int64_t kMgCoarsest = 4096;   // a level this small is solved by sweeps alone
-constexpr int kMgSweeps = 8;            // damped Jacobi sweeps on the coarsest level
-constexpr int kMgCoarseThreads = 1024;  // the coarsest level's single block
-static_assert(kMgSweeps % 2 == 0, "the coarsest sweeps must end in the e vector");
 
 // One level of the hierarchy as the kernels see it (levels >= 1).
 struct MgView {
@@ -397,125 +407,136 @@ __global__ __launch_bounds__(kBlock) void k_mg_invd(const float *__restrict__ w,
     invd[i] = 1.0 / ((double)mass[i] + a * s);
 }
 
-// Restriction from the fine level, one thread per cell of level 1: the sum
-// over its voxels of r - B x0, x0 = w D^-1 r (the pre-smoothed iterate, formed
-// at each voxel and neighbour from r and the diagonal); also level 1's
-// pre-smoothed iterate.  Voxels are reached in child order, so the neighbour
-// source is the table or the packed offsets (per-voxel words).
+// Fine-level residual of the pre-smoothed iterate: t = r - B x0 (x0 = w D^-1 r,
+// written by the update kernel), one thread per voxel.
 template <bool REG, int NS>
-__global__ __launch_bounds__(kBlock) void k_mg_restrict0(CgArgs A, const RankWord *__restrict__ rank, Geom g,
-                                                         const double *__restrict__ r, const double *__restrict__ m,
-                                                         MgView C, const double *__restrict__ scal) {
+__global__ __launch_bounds__(kBlock) void k_mg_res0(CgArgs A, const double *__restrict__ r,
+                                                    const double *__restrict__ x0, double *__restrict__ t,
+                                                    const double *__restrict__ scal) {
     if (scal[S_DONE] != 0.0) return;
     __shared__ double cl[VG_NREG];
-    __shared__ double mtab[8];
     if (threadIdx.x < VG_NREG) cl[threadIdx.x] = A.c[threadIdx.x];
-    if (!REG && threadIdx.x < 7) mtab[threadIdx.x] = 1.0 / (1.0 + A.a * (double)threadIdx.x);
     __syncthreads();
-    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (c >= C.n) return;
-    int X, Y, Z;
-    mg_cell_xyz(C.vox, c, C.g.nx, C.g.ny, X, Y, Z);
-    double sum = 0.0;
-    mg_children(rank, g, X, Y, Z, [&](int64_t i, int) {
-        const double ri = r[i];
-        const double xi = kMgOmega * ri * fine_minv<REG>(m, mtab, i);
-        int64_t j[6];
-        bool pres[6];
-        cg_neighbours<NS>(A, i, j, pres);
-        double rj[6], mj[6];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= A.n) return;
+    const double xi = x0[i];
+    int64_t j[6];
+    bool pres[6];
+    cg_neighbours<NS>(A, i, j, pres);
+    double xj[6];
 #pragma unroll
-        for (int k = 0; k < 6; k++) {
-            rj[k] = r[j[k]];
-            mj[k] = fine_minv<REG>(m, mtab, j[k]);
-        }
-        double s = 0.0;
+    for (int k = 0; k < 6; k++) xj[k] = x0[j[k]];
+    double s = 0.0;
 #pragma unroll
-        for (int k = 0; k < 6; k++) {
-            if (!pres[k]) continue;
-            s += weight(A.rcode, cl, i, k, REG) * (xi - kMgOmega * rj[k] * mj[k]);
-        }
-        sum += ri - (xi + A.a * s);
-    });
-    C.r[c] = sum;
-    C.x[c] = kMgOmega * sum * C.invd[c];
-}
-
-// Restriction from level l (F) to level l + 1 (C), one thread per cell of
-// C: the sum over its children of r - B x with the pre-smoothed x of F.
-__global__ __launch_bounds__(kBlock) void k_mg_restrict(MgView F, MgView C, double a,
-                                                        const double *__restrict__ scal) {
-    if (scal[S_DONE] != 0.0) return;
-    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (c >= C.n) return;
-    int X, Y, Z;
-    mg_cell_xyz(C.vox, c, C.g.nx, C.g.ny, X, Y, Z);
-    double sum = 0.0;
-    mg_children(F.rank, F.g, X, Y, Z, [&](int64_t i, int) {
-        const double xi = F.x[i];
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < 6; k++) {
-            const int32_t j = F.nbr[(int64_t)k * F.ld + i];
-            if (j >= 0) s += (double)F.w[(int64_t)k * F.ld + i] * (xi - F.x[j]);
-        }
-        sum += F.r[i] - ((double)F.mass[i] * xi + a * s);
-    });
-    C.r[c] = sum;
-    C.x[c] = kMgOmega * sum * C.invd[c];
-}
-
-// The coarsest level: kMgSweeps damped Jacobi sweeps from zero in one block
-// (the first is the x the restriction wrote); ping-pong x <-> e, ending in e.
-__global__ __launch_bounds__(kMgCoarseThreads) void k_mg_coarsest(MgView L, double a,
-                                                                  const double *__restrict__ scal) {
-    if (scal[S_DONE] != 0.0) return;
-    double *src = L.x, *dst = L.e;
-    for (int sweep = 1; sweep < kMgSweeps; sweep++) {
-        for (int64_t i = threadIdx.x; i < L.n; i += kMgCoarseThreads) {
-            const double xi = src[i];
-            double s = 0.0;
-#pragma unroll
-            for (int k = 0; k < 6; k++) {
-                const int32_t j = L.nbr[(int64_t)k * L.ld + i];
-                if (j >= 0) s += (double)L.w[(int64_t)k * L.ld + i] * (xi - src[j]);
-            }
-            dst[i] = xi + kMgOmega * (L.r[i] - ((double)L.mass[i] * xi + a * s)) * L.invd[i];
-        }
-        __syncthreads();
-        double *t = src;
-        src = dst;
-        dst = t;
+    for (int k = 0; k < 6; k++) {
+        if (!pres[k]) continue;
+        s += weight(A.rcode, cl, i, k, REG) * (xi - xj[k]);
     }
-    // kMgSweeps - 1 sweeps (an odd number): the last one wrote e
+    t[i] = r[i] - (xi + A.a * s);
 }
 
-// Prolongation and post-smoothing on level l >= 1: y = x + e_(l+1)[parent],
-// e_l = y + w D^-1 (r - B y).
-__global__ __launch_bounds__(kBlock) void k_mg_prolong(MgView L, const double *__restrict__ ec, double a,
-                                                       const double *__restrict__ scal) {
+// Residual on level l >= 1 (into e, free until the upward pass): r - B x.
+__global__ __launch_bounds__(kBlock) void k_mg_res(MgView L, double a, const double *__restrict__ scal) {
     if (scal[S_DONE] != 0.0) return;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= L.n) return;
-    const double yi = L.x[i] + ec[L.parent[i]];
+    const double xi = L.x[i];
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < 6; k++) {
         const int32_t j = L.nbr[(int64_t)k * L.ld + i];
-        if (j >= 0) s += (double)L.w[(int64_t)k * L.ld + i] * (yi - (L.x[j] + ec[L.parent[j]]));
+        if (j >= 0) s += (double)L.w[(int64_t)k * L.ld + i] * (xi - L.x[j]);
     }
-    L.e[i] = yi + kMgOmega * (L.r[i] - ((double)L.mass[i] * yi + a * s)) * L.invd[i];
+    L.e[i] = L.r[i] - ((double)L.mass[i] * xi + a * s);
 }
 
-// Prolongation and post-smoothing on the fine level: y = x0 + e_1[parent],
-// z = y + w D^-1 (r - B y); writes z and the per-block r.z partials (slot 0,
-// the grid-stride blocks of the other CG kernels).
+// Restriction, one thread per cell of the coarser level C: the sum of the
+// finer level's residuals over its children (fixed order); also C's
+// pre-smoothed iterate w D^-1 r.  (Eight lanes per cell with a butterfly sum
+// measured twice as slow at 512^3.)
+__global__ __launch_bounds__(kBlock) void k_mg_sum(const RankWord *__restrict__ rank, Geom g,
+                                                   const double *__restrict__ res, MgView C,
+                                                   const double *__restrict__ scal) {
+    if (scal[S_DONE] != 0.0) return;
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= C.n) return;
+    int X, Y, Z;
+    mg_cell_xyz(C.vox, c, C.g.nx, C.g.ny, X, Y, Z);
+    double sum = 0.0;
+    mg_children(rank, g, X, Y, Z, [&](int64_t i, int) { sum += res[i]; });
+    C.r[c] = sum;
+    C.x[c] = kMgOmega * sum * C.invd[c];
+}
+
+// The coarsest level (at most kMgCoarseMax cells): kMgSweeps damped Jacobi
+// sweeps from zero (the first is the x the restriction wrote) in one block,
+// the iterate in LDS; the result goes to e.
+__global__ __launch_bounds__(kMgCoarseThreads) void k_mg_coarsest(MgView L, double a,
+                                                                  const double *__restrict__ scal) {
+    if (scal[S_DONE] != 0.0) return;
+    __shared__ double xs[2][kMgCoarseMax];
+    constexpr int kPer = kMgCoarseMax / kMgCoarseThreads;
+    for (int u = 0; u < kPer; u++) {
+        const int64_t i = threadIdx.x + (int64_t)u * kMgCoarseThreads;
+        if (i < L.n) xs[0][i] = L.x[i];
+    }
+    __syncthreads();
+    int src = 0;
+    for (int sweep = 1; sweep < kMgSweeps; sweep++) {
+        for (int u = 0; u < kPer; u++) {
+            const int64_t i = threadIdx.x + (int64_t)u * kMgCoarseThreads;
+            if (i >= L.n) continue;
+            const double xi = xs[src][i];
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                const int32_t j = L.nbr[(int64_t)k * L.ld + i];
+                if (j >= 0) s += (double)L.w[(int64_t)k * L.ld + i] * (xi - xs[src][j]);
+            }
+            xs[src ^ 1][i] = xi + kMgOmega * (L.r[i] - ((double)L.mass[i] * xi + a * s)) * L.invd[i];
+        }
+        __syncthreads();
+        src ^= 1;
+    }
+    for (int u = 0; u < kPer; u++) {
+        const int64_t i = threadIdx.x + (int64_t)u * kMgCoarseThreads;
+        if (i < L.n) L.e[i] = xs[src][i];
+    }
+}
+
+// Prolongation: y = x + sol_c[parent] (any level; streaming).
+__global__ __launch_bounds__(kBlock) void k_mg_pro(int64_t n, const double *__restrict__ x,
+                                                   const int32_t *__restrict__ parent,
+                                                   const double *__restrict__ solc, double *__restrict__ y,
+                                                   const double *__restrict__ scal) {
+    if (scal[S_DONE] != 0.0) return;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) y[i] = x[i] + solc[parent[i]];
+}
+
+// Post-smoothing on level l >= 1: x = y + w D^-1 (r - B y), y in e.
+__global__ __launch_bounds__(kBlock) void k_mg_post(MgView L, double a, const double *__restrict__ scal) {
+    if (scal[S_DONE] != 0.0) return;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= L.n) return;
+    const double yi = L.e[i];
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        const int32_t j = L.nbr[(int64_t)k * L.ld + i];
+        if (j >= 0) s += (double)L.w[(int64_t)k * L.ld + i] * (yi - L.e[j]);
+    }
+    L.x[i] = yi + kMgOmega * (L.r[i] - ((double)L.mass[i] * yi + a * s)) * L.invd[i];
+}
+
+// Post-smoothing on the fine level: z = y + w D^-1 (r - B y), y in t; writes
+// z and the per-block r.z partials (slot 0, the grid-stride blocks of the
+// other CG kernels).
 template <bool REG, int NS>
-__global__ __launch_bounds__(kBlock) void k_mg_prolong0(CgArgs A, const double *__restrict__ r,
-                                                        const double *__restrict__ m,
-                                                        const int32_t *__restrict__ parent,
-                                                        const double *__restrict__ e1, double *__restrict__ z,
-                                                        const double *__restrict__ scal, double *__restrict__ part) {
+__global__ __launch_bounds__(kBlock) void k_mg_post0(CgArgs A, const double *__restrict__ r,
+                                                     const double *__restrict__ m, const double *__restrict__ y,
+                                                     double *__restrict__ z, const double *__restrict__ scal,
+                                                     double *__restrict__ part) {
     if (scal[S_DONE] != 0.0) return;
     __shared__ double lds[kWaves];
     __shared__ double cl[VG_NREG];
@@ -530,14 +551,14 @@ __global__ __launch_bounds__(kBlock) void k_mg_prolong0(CgArgs A, const double *
     for (int v = 0; v < kVPT; v++) {
         const int64_t i = t * kTile + v * kBlock + threadIdx.x;
         if (i >= A.n) continue;
-        const double ri = r[i], mi = fine_minv<REG>(m, mtab, i);
-        const double yi = kMgOmega * ri * mi + e1[parent[i]];
+        const double yi = y[i];
         int64_t j[6];
         bool pres[6];
         cg_neighbours<NS>(A, i, j, pres);
         double yj[6];
 #pragma unroll
-        for (int k = 0; k < 6; k++) yj[k] = kMgOmega * r[j[k]] * fine_minv<REG>(m, mtab, j[k]) + e1[parent[j[k]]];
+        for (int k = 0; k < 6; k++) yj[k] = y[j[k]];
+        const double ri = r[i], mi = fine_minv<REG>(m, mtab, i);
         double s = 0.0;
 #pragma unroll
         for (int k = 0; k < 6; k++) {
@@ -551,6 +572,17 @@ __global__ __launch_bounds__(kBlock) void k_mg_prolong0(CgArgs A, const double *
     }
     block_sum<1>(acc, lds);
     if (threadIdx.x == 0) part[(int64_t)blockIdx.x * 4] = acc[0];
+}
+
+// The pre-smoothed fine iterate for a given r (vg_precondition): x0 = w D^-1 r.
+template <bool REG>
+__global__ __launch_bounds__(kBlock) void k_mg_x0(int64_t n, double a, const double *__restrict__ r,
+                                                  const double *__restrict__ m, double *__restrict__ x0) {
+    __shared__ double mtab[8];
+    if (!REG && threadIdx.x < 7) mtab[threadIdx.x] = 1.0 / (1.0 + a * (double)threadIdx.x);
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) x0[i] = kMgOmega * r[i] * fine_minv<REG>(m, mtab, i);
 }
 
 // Jacobi as a separate map (vg_precondition): z = D^-1 r.
@@ -661,39 +693,48 @@ int mg_prepare(vg_sim *h, double a, hipStream_t s) {
     return VG_OK;
 }
 
-// z = V-cycle(r) on the fine level (m: the fine diagonal as the init kernel
-// wrote it); r.z partials in part slot 0 of G blocks.
+// z = V-cycle(r) on the fine level: z holds x0 = w D^-1 r on entry (the
+// update or init kernel wrote it), m the fine diagonal as the init kernel
+// wrote it; r.z partials go to part slot 0 of G blocks.  Each level's
+// result: x (levels between), e (the coarsest).
 template <bool REG, int NS>
 int mg_vcycle(vg_sim *h, const CgArgs &A, const double *r, const double *m, double *z, int G, hipStream_t s) {
     const int L = h->mg_levels;
-    const Geom g0 = fine_geom(h);
+    const double a = A.a;
+    double *t = h->mg[0].e;   // fine residual, then the prolongated iterate
     int rc;
-    {
-        const MgView c1 = mg_view(h, 1);
-        // the restriction walks voxels in child order: per-voxel neighbour words
-        if (NS != NS_TABLE && h->off_ok)
-            hipLaunchKernelGGL((k_mg_restrict0<REG, NS_OFF>), dim3(mg_grid(c1.n)), dim3(kBlock), 0, s, A,
-                               (const RankWord *)h->rank, g0, r, m, c1, h->cg_scal);
-        else
-            hipLaunchKernelGGL((k_mg_restrict0<REG, NS_TABLE>), dim3(mg_grid(c1.n)), dim3(kBlock), 0, s, A,
-                               (const RankWord *)h->rank, g0, r, m, c1, h->cg_scal);
-        if ((rc = launch_status("k_mg_restrict0"))) return rc;
-    }
+    hipLaunchKernelGGL((k_mg_res0<REG, NS>), dim3(mg_grid(h->n)), dim3(kBlock), 0, s, A, r, (const double *)z, t,
+                       h->cg_scal);
+    if ((rc = launch_status("k_mg_res0"))) return rc;
+    hipLaunchKernelGGL(k_mg_sum, dim3(mg_grid(h->mg[1].n)), dim3(kBlock), 0, s, (const RankWord *)h->rank,
+                       fine_geom(h), (const double *)t, mg_view(h, 1), h->cg_scal);
+    if ((rc = launch_status("k_mg_sum"))) return rc;
     for (int l = 1; l + 1 < L; l++) {
-        hipLaunchKernelGGL(k_mg_restrict, dim3(mg_grid(h->mg[l + 1].n)), dim3(kBlock), 0, s, mg_view(h, l),
-                           mg_view(h, l + 1), A.a, h->cg_scal);
-        if ((rc = launch_status("k_mg_restrict"))) return rc;
+        const MgView F = mg_view(h, l);
+        hipLaunchKernelGGL(k_mg_res, dim3(mg_grid(F.n)), dim3(kBlock), 0, s, F, a, h->cg_scal);
+        if ((rc = launch_status("k_mg_res"))) return rc;
+        hipLaunchKernelGGL(k_mg_sum, dim3(mg_grid(h->mg[l + 1].n)), dim3(kBlock), 0, s, F.rank, F.g,
+                           (const double *)F.e, mg_view(h, l + 1), h->cg_scal);
+        if ((rc = launch_status("k_mg_sum"))) return rc;
     }
-    hipLaunchKernelGGL(k_mg_coarsest, dim3(1), dim3(kMgCoarseThreads), 0, s, mg_view(h, L - 1), A.a, h->cg_scal);
+    hipLaunchKernelGGL(k_mg_coarsest, dim3(1), dim3(kMgCoarseThreads), 0, s, mg_view(h, L - 1), a, h->cg_scal);
     if ((rc = launch_status("k_mg_coarsest"))) return rc;
     for (int l = L - 2; l >= 1; l--) {
-        hipLaunchKernelGGL(k_mg_prolong, dim3(mg_grid(h->mg[l].n)), dim3(kBlock), 0, s, mg_view(h, l),
-                           (const double *)h->mg[l + 1].e, A.a, h->cg_scal);
-        if ((rc = launch_status("k_mg_prolong"))) return rc;
+        const MgView V = mg_view(h, l);
+        const double *solc = l + 1 == L - 1 ? h->mg[l + 1].e : h->mg[l + 1].x;
+        hipLaunchKernelGGL(k_mg_pro, dim3(mg_grid(V.n)), dim3(kBlock), 0, s, V.n, (const double *)V.x, V.parent,
+                           solc, V.e, h->cg_scal);
+        if ((rc = launch_status("k_mg_pro"))) return rc;
+        hipLaunchKernelGGL(k_mg_post, dim3(mg_grid(V.n)), dim3(kBlock), 0, s, V, a, h->cg_scal);
+        if ((rc = launch_status("k_mg_post"))) return rc;
     }
-    hipLaunchKernelGGL((k_mg_prolong0<REG, NS>), dim3(G), dim3(kBlock), 0, s, A, r, m,
-                       (const int32_t *)h->mg[0].parent, (const double *)h->mg[1].e, z, h->cg_scal, h->cg_part);
-    return launch_status("k_mg_prolong0");
+    const double *sol1 = L == 2 ? h->mg[1].e : h->mg[1].x;
+    hipLaunchKernelGGL(k_mg_pro, dim3(mg_grid(h->n)), dim3(kBlock), 0, s, h->n, (const double *)z,
+                       (const int32_t *)h->mg[0].parent, sol1, t, h->cg_scal);
+    if ((rc = launch_status("k_mg_pro"))) return rc;
+    hipLaunchKernelGGL((k_mg_post0<REG, NS>), dim3(G), dim3(kBlock), 0, s, A, r, m, (const double *)t, z, h->cg_scal,
+                       h->cg_part);
+    return launch_status("k_mg_post0");
 }
 
 // storage of one pool of the bound fields
@@ -792,6 +833,9 @@ int mg_apply_ns(vg_sim *h, double a, const double *r, double *z, hipStream_t s) 
     // the V-cycle's kernels check the convergence flag: clear it
     if ((rc = hip_status(hipMemsetAsync(h->cg_scal, 0, sizeof(double) * S_NSCAL, s), "cg scalars"))) return rc;
     if ((rc = mg_prepare(h, a, s))) return rc;
+    if (reg) hipLaunchKernelGGL(k_mg_x0<true>, dim3(mg_grid(h->n)), dim3(kBlock), 0, s, h->n, a, r, h->cg_m, z);
+    else hipLaunchKernelGGL(k_mg_x0<false>, dim3(mg_grid(h->n)), dim3(kBlock), 0, s, h->n, a, r, h->cg_m, z);
+    if ((rc = launch_status("k_mg_x0"))) return rc;
     return reg ? mg_vcycle<true, NS>(h, A, r, h->cg_m, z, h->cg_blocks, s)
                : mg_vcycle<false, NS>(h, A, r, h->cg_m, z, h->cg_blocks, s);
 }
@@ -857,6 +901,10 @@ int mg_build(vg_sim *h, hipStream_t s) {
         l++;
     }
     h->mg_levels = l + 1;
+    if (h->mg_levels >= 2 && h->mg[l].n > kMgCoarseMax) {
+        set_error("multigrid: coarsest level of %lld cells", (long long)h->mg[l].n);
+        return VG_EINVAL;
+    }
     return mg_weights(h, s);
 }
 

@@ -57,10 +57,14 @@ def run_explicit(mask, g, dt=0.1, t_end=T_END, precision="f32", kernel=0):
     return sim, nsteps
 
 
-def run_implicit(mask, g, dt=30.0, t_end=T_END, precision="f32", rtol=1e-10, kernel=0):
-    """Whole steps of dt, then one step of the remainder so the run ends at t_end."""
+def run_implicit(mask, g, dt=30.0, t_end=T_END, precision="f32", rtol=1e-10, kernel=0, multigrid=False):
+    """Whole steps of dt, then one step of the remainder so the run ends at
+    t_end; CG preconditioned by the diagonal (the paper's) or, with
+    multigrid=True, by the library's multigrid V-cycle."""
     p = params()
-    sim = Simulation(g, p, precision=precision, implicit=True)
+    sim = Simulation(g, p, precision=precision, implicit=True, multigrid=multigrid)
+    if multigrid:
+        sim.set_preconditioner("mg")
     sim.set_kernel(kernel)
     sim.set_fields(initial_fields(mask, g))
     nfull = int(math.floor(t_end / dt + 1e-9))

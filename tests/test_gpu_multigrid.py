@@ -6,7 +6,7 @@ the library: aggregates of 2x2x2 cells by position, level l + 1's operator
 the Galerkin product P^T B_l P with the piecewise-constant P (mass vector and
 weighted Laplacian), damped Jacobi (0.8) once before and once after each
 coarse correction, 8 sweeps from zero on the coarsest level (reached once a
-level has at most 4096 cells).  Checks: the hierarchy's cell counts, the
+level has at most 1024 cells).  Checks: the hierarchy's cell counts, the
 V-cycle against that restatement, its symmetry and positive definiteness,
 and solves whose true residual (the oracle's matrix) meets rtol and whose
 answer agrees with the oracle's tight Jacobi-PCG solve within kappa * rtol,
@@ -21,7 +21,7 @@ from paper_2406_04177_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-OMEGA, COARSEST, SWEEPS, MAX_LEVELS = 0.8, 4096, 8, 12
+OMEGA, COARSEST, SWEEPS, MAX_LEVELS = 0.8, 1024, 8, 12
 
 
 def ref_hierarchy(og, w0):

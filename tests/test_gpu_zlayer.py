@@ -55,14 +55,16 @@ def test_explicit_profile_fp64_equals_oracle():
     np.testing.assert_allclose(prof.sum(), de.M0, rtol=1e-12)              # no flux out of the image
 
 
+@pytest.mark.parametrize("multigrid", [False, True], ids=["jacobi", "multigrid"])
 @pytest.mark.parametrize("t_end", [30.0, 40.0])
-def test_implicit_profile_against_oracle(t_end):
+def test_implicit_profile_against_oracle(t_end, multigrid):
     """30 s steps (and a 10 s remainder for t_end = 40 s): the GPU iterate is
-    within kappa * rtol of the oracle's tight solve, layer by layer."""
+    within kappa * rtol of the oracle's tight solve, layer by layer (with the
+    paper's Jacobi preconditioner and with the multigrid one)."""
     from paper_2406_04177_amd import diffusion_experiment as de
     mask, g, og = small()
     rtol = 1e-11
-    sim, its = de.run_implicit(mask, g, dt=30.0, t_end=t_end, precision="f64", rtol=rtol)
+    sim, its = de.run_implicit(mask, g, dt=30.0, t_end=t_end, precision="f64", rtol=rtol, multigrid=multigrid)
     prof = de.layer_profile(sim, mask)
     x = de.initial_fields(mask, g).cpu().numpy()
     p = de.params()
