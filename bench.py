@@ -399,9 +399,14 @@ def gradient_batch(steps, K=100):
     res = {"workload": "16 x 128^3 batch (n = %d), %d FP32 steps, CO2 totals every step, checkpoints every %d"
                        % (g.n, steps, K), "forward_ms": ms_fwd}
 
+    # the forward records as many segments as fit 85 % of the free device
+    # memory (at this size all 20: 226 GB of FP32 states), the backward
+    # runs the others again
+    tape = int(0.85 * torch.cuda.mem_get_info()[0])
+
     def grad():
         th = theta.clone().requires_grad_(True)
-        loss = co2_mse(simulate_totals(sim, th, x0, steps, dt, K), target)
+        loss = co2_mse(simulate_totals(sim, th, x0, steps, dt, K, tape_bytes=tape), target)
         loss.backward()
         return th.grad
     for skip in (False, True):
@@ -415,6 +420,20 @@ def gradient_batch(steps, K=100):
     log("16 x 128^3 gradient: forward %.1f ms, gradient %.1f ms (ratio %.2f), skipping static D %.1f ms (%.2f)"
         % (ms_fwd, res["gradient_ms_all_d"], res["gradient_forward_ratio_all_d"], res["gradient_ms_skip_static_d"],
            res["gradient_forward_ratio_skip_static_d"]))
+    # without the forward's recorded segments (every segment run again in the backward)
+    sim.set_adjoint_options(skip_static_d=False)
+
+    def grad_no_tape():
+        th = theta.clone().requires_grad_(True)
+        loss = co2_mse(simulate_totals(sim, th, x0, steps, dt, K, tape_bytes=0), target)
+        loss.backward()
+    res["taped_segments"] = "%d of %d" % (sim.last_taped_segments, (steps + K - 1) // K)
+    ms_nt, _ = timed(grad_no_tape)
+    res["gradient_ms_all_d_no_tape"] = ms_nt
+    res["tape"] = ("segments the forward records itself (vg_step_record): the last ones whose states fit 85 % of "
+                   "the free device memory; the others are recorded again in the backward")
+    del sim, x0
+    torch.cuda.empty_cache()
     return res
 
 

@@ -459,6 +459,16 @@ int vg_store_state(vg_sim *h, void *x_d, int x_precision, void *stream);
  * VG_EINVAL for params.sequential = 1 (the reverse sweep differentiates
  * Algorithm 1) and for the diffuse-first step order. */
 int vg_record(vg_sim *h, int64_t nsteps, double dt, void *states_d, void *stream);
+/* The forward run and its record in one: advances the bound state nsteps
+ * steps, writes to states_d what vg_record writes for the same start, and
+ * logs the totals after every step to totals_log_d[nsteps][nseg][6] (as
+ * vg_step_explicit with log_every = 1).  The same kernels in the same order,
+ * so the state and the totals are bit-identical to vg_step_explicit's and
+ * the states to vg_record's; it lets a caller that can hold the states of a
+ * whole segment skip the segment's second forward run.  Same validation as
+ * vg_record plus the stability bound (VG_FORCE in flags skips it). */
+int vg_step_record(vg_sim *h, int64_t nsteps, double dt, void *states_d, double *totals_log_d, unsigned flags,
+                   void *stream);
 int vg_adjoint(vg_sim *h, int64_t nsteps, double dt, const void *states_d, const double *seeds_d,
                void *lambda_d, double *grad_d, void *stream);
 /* lambda_d[s][i] = (zero ? 0 : lambda_d[s][i]) + seed_d[g(i)][s] (seed_d

@@ -11,6 +11,11 @@ values) and of the initial fields ``x0``.  The backward pass is the library's
 hand-written discrete adjoint (``vg_adjoint``) with checkpointed recomputation:
 the forward keeps the state at the start of every ``checkpoint_every`` steps;
 the backward re-records each segment (``vg_record``) and sweeps it in reverse.
+Segments whose recorded states fit ``tape_bytes`` (default: half the free
+device memory at the forward; 0 turns it off) are recorded by the forward
+itself (``vg_step_record``: the same kernels, bit-identical states and
+totals), so the backward sweeps them without running them again; the last
+segments are the ones kept, and each is freed once swept.
 """
 from __future__ import annotations
 
@@ -41,7 +46,7 @@ def params_of(theta, base: ModelParams) -> tuple:
 
 class _TotalsFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, theta, x0, sim, nsteps, dt, K):
+    def forward(ctx, theta, x0, sim, nsteps, dt, K, tape_bytes):
         p, c = params_of(theta, sim.params)
         sim.set_params(p)
         sim.set_regions(c)
@@ -52,12 +57,27 @@ class _TotalsFn(torch.autograd.Function):
         tot[0] = torch.from_numpy(sim.totals()).to(dev)
         ckpts = []
         keep = any(ctx.needs_input_grad[:2])      # no checkpoints when no gradient is wanted
-        k0 = 0
-        while k0 < nsteps:
-            k = min(K, nsteps - k0)
-            ckpts.append((k0, k, sim.fields.clone() if keep else None))
-            sim.step(k, dt, log_every=1, totals_out=tot[k0 + 1:k0 + 1 + k])
-            k0 += k
+        segs = [(k0, min(K, nsteps - k0)) for k0 in range(0, nsteps, K)]
+        # the last segments whose states fit the budget are recorded on the way
+        per_step = 5 * sim.graph.n * torch.empty((), dtype=sim.dtype).element_size()
+        if tape_bytes is None:
+            tape_bytes = torch.cuda.mem_get_info(dev)[0] // 2 if dev.type == "cuda" else 0
+        taped, budget = set(), int(tape_bytes) if keep else 0
+        for k0, k in reversed(segs):
+            if k * per_step > budget:
+                break
+            budget -= k * per_step
+            taped.add(k0)
+        for k0, k in segs:
+            if k0 in taped:
+                tape = torch.empty((k, 5, sim.graph.n), dtype=sim.dtype, device=dev)
+                sim.step_record(k, dt, tape, tot[k0 + 1:k0 + 1 + k])
+                ckpts.append((k0, k, tape))
+            else:
+                ckpts.append((k0, k, sim.fields.clone() if keep else None))
+                sim.step(k, dt, log_every=1, totals_out=tot[k0 + 1:k0 + 1 + k])
+        ctx.taped = taped
+        sim.last_taped_segments = len(taped)   # for reporting
         ctx.sim, ctx.dt, ctx.ckpts, ctx.nsteps = sim, dt, ckpts, nsteps
         ctx.params, ctx.regions = p, c       # the backward differentiates at this forward's theta
         ctx.theta_device = theta.device
@@ -78,24 +98,29 @@ class _TotalsFn(torch.autograd.Function):
         lam = torch.zeros((5, n), dtype=sim.dtype, device=dev)
         sim.seed_lambda(seeds[ctx.nsteps], lam, zero=True)
         grad = torch.zeros(NTHETA, dtype=torch.float64, device=dev)
-        kmax = max(k for _, k, _ in ctx.ckpts) if ctx.ckpts else 0
-        states = torch.empty((max(kmax, 1), 5, n), dtype=sim.dtype, device=dev)
-        for k0, k, ck in reversed(ctx.ckpts):
+        kmax = max((k for k0, k, _ in ctx.ckpts if k0 not in ctx.taped), default=0)
+        states = torch.empty((kmax, 5, n), dtype=sim.dtype, device=dev) if kmax else None
+        for idx in range(len(ctx.ckpts) - 1, -1, -1):
+            k0, k, ck = ctx.ckpts[idx]
+            if k0 in ctx.taped:
+                sim.adjoint(k, dt, ck, seeds[k0:k0 + k], lam, grad)
+                ctx.ckpts[idx] = (k0, k, None)   # free the tape once swept
+                continue
             sim.set_fields(ck)
             sim.record(k, dt, states)
             sim.adjoint(k, dt, states, seeds[k0:k0 + k], lam, grad)
         sim.set_params(prev_p)
         if prev_c is not None:
             sim.set_regions(prev_c)
-        return (grad.to(ctx.theta_device), lam.to(ctx.x0_dtype), None, None, None, None)
+        return (grad.to(ctx.theta_device), lam.to(ctx.x0_dtype), None, None, None, None, None)
 
 
 def simulate_totals(sim, theta: torch.Tensor, x0: torch.Tensor, nsteps: int, dt: float,
-                    checkpoint_every: int = 100) -> torch.Tensor:
+                    checkpoint_every: int = 100, tape_bytes=None) -> torch.Tensor:
     """Differentiable [nsteps+1, nseg, 5] totals; see the module docstring."""
     if nsteps < 1 or checkpoint_every < 1:
         raise ValueError("need nsteps >= 1 and checkpoint_every >= 1")
-    return _TotalsFn.apply(theta, x0, sim, int(nsteps), float(dt), int(checkpoint_every))
+    return _TotalsFn.apply(theta, x0, sim, int(nsteps), float(dt), int(checkpoint_every), tape_bytes)
 
 
 def co2_mse(totals: torch.Tensor, target: torch.Tensor) -> torch.Tensor:

@@ -143,6 +143,8 @@ struct AdjBufs {
     R *lout = nullptr;           // lambda^k
     const double *seed = nullptr;   // [nseg][5] for this step
     const R *co2 = nullptr;      // [nseg] CO2 adjoint lambda^(k+1) per volume (CO2U)
+    R *co2_next = nullptr;       // [nseg] lambda^k's, written by block 0 (CO2U; the other buffer)
+    int nseg = 0;
     int64_t n = 0, ntiles = 0;
 };
 
@@ -200,6 +202,12 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces 
         for (int r = 0; r < VG_NREG; r++) creg[r][threadIdx.x] = 0.0;
     }
     __syncthreads();
+    if (CO2U && blockIdx.x == 0) {
+        // the uniform CO2 adjoint after this step: only the seed changes it,
+        // with the per-voxel update's rounding, (R)((double)lambda + seed)
+        for (int s = threadIdx.x; s < A.nseg; s += kBlock)
+            A.co2_next[s] = (R)((double)A.co2[s] + A.seed[(int64_t)s * VG_NPOOL + 4]);
+    }
     double g[kG];
 #pragma unroll
     for (int q = 0; q < kG; q++) g[q] = 0.0;
@@ -437,14 +445,6 @@ __global__ __launch_bounds__(kBlock) void k_co2_init(const R *__restrict__ lam4,
     co2[g] = p < pc.npieces && pc.piece_seg[p] == g ? lam4[pc.piece_lo[p]] : R(0);
 }
 
-// One reverse step of the uniform CO2 adjoint: the same rounding as the
-// per-voxel update, (R)((double)lambda + seed).
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_co2_step(R *__restrict__ co2, int nseg, const double *__restrict__ seed) {
-    const int g = (int)(blockIdx.x * kBlock + threadIdx.x);
-    if (g < nseg) co2[g] = (R)((double)co2[g] + seed[(int64_t)g * VG_NPOOL + 4]);
-}
-
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_co2_expand(R *__restrict__ lam4, int64_t n, Pieces pc,
                                                        const R *__restrict__ co2) {
@@ -508,7 +508,9 @@ int adjoint_sweep(vg_sim *h, int64_t nsteps, double dt, const void *states, cons
     const bool reg = h->rcode != nullptr;
     Pieces pc{h->piece_first, h->piece_lo, h->piece_seg, h->npieces};
     const unsigned nb_n = (unsigned)((n + kBlock - 1) / kBlock), nb_g = (unsigned)((h->nseg + kBlock - 1) / kBlock);
-    R *co2 = (R *)h->adj_co2;
+    // the uniform CO2 adjoint per volume, in two buffers: reverse step m reads
+    // co2b[m & 1] and its block 0 writes the next value into the other
+    R *co2b[2] = {(R *)h->adj_co2, (R *)h->adj_co2 + h->nseg};
     R *lam4 = (R *)lambda + 4 * n;
     // a CO2 adjoint uniform over each volume travels as one value per volume
     bool co2u = false;
@@ -524,7 +526,7 @@ int adjoint_sweep(vg_sim *h, int64_t nsteps, double dt, const void *states, cons
         co2u = true;
         for (int32_t f : flag) co2u = co2u && f == 0;
         if (co2u) {
-            hipLaunchKernelGGL(k_co2_init<R>, dim3(nb_g), dim3(kBlock), 0, s, lam4, h->nseg, pc, h->seg_first, co2);
+            hipLaunchKernelGGL(k_co2_init<R>, dim3(nb_g), dim3(kBlock), 0, s, lam4, h->nseg, pc, h->seg_first, co2b[0]);
             if ((rc = launch_status("k_co2_init"))) return rc;
         }
     }
@@ -537,17 +539,16 @@ int adjoint_sweep(vg_sim *h, int64_t nsteps, double dt, const void *states, cons
         A.lin = bufs[cur];
         A.lout = bufs[cur ^ 1];
         A.seed = seeds + jstep * (int64_t)h->nseg * VG_NPOOL;
-        A.co2 = co2u ? co2 : nullptr;
+        const int m = (int)((nsteps - 1 - jstep) & 1);
+        A.co2 = co2u ? co2b[m] : nullptr;
+        A.co2_next = co2u ? co2b[m ^ 1] : nullptr;
+        A.nseg = h->nseg;
         A.n = n;
         A.ntiles = h->ntiles;
         const bool fx = jstep == 0;
         if (h->mobile_all) rc = reg ? launch_adj_step<R, 2, true>(h, fx, A, C, s) : launch_adj_step<R, 2, false>(h, fx, A, C, s);
         else rc = reg ? launch_adj_step<R, 1, true>(h, fx, A, C, s) : launch_adj_step<R, 1, false>(h, fx, A, C, s);
         if (rc) return rc;
-        if (co2u) {
-            hipLaunchKernelGGL(k_co2_step<R>, dim3(nb_g), dim3(kBlock), 0, s, co2, h->nseg, A.seed);
-            if ((rc = launch_status("k_co2_step"))) return rc;
-        }
         cur ^= 1;
     }
     if (cur) {
@@ -557,7 +558,8 @@ int adjoint_sweep(vg_sim *h, int64_t nsteps, double dt, const void *states, cons
                                             hipMemcpyDeviceToDevice, s), "lambda copy"))) return rc;
     }
     if (co2u) {
-        hipLaunchKernelGGL(k_co2_expand<R>, dim3(nb_n), dim3(kBlock), 0, s, lam4, n, pc, (const R *)co2);
+        hipLaunchKernelGGL(k_co2_expand<R>, dim3(nb_n), dim3(kBlock), 0, s, lam4, n, pc,
+                           (const R *)co2b[nsteps & 1]);
         if ((rc = launch_status("k_co2_expand"))) return rc;
     }
     const double scale_d = dt / (h->params.h * h->params.h);

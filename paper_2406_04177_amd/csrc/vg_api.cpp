@@ -128,7 +128,7 @@ size_t layout(vg_sim *h, char *base) {
     if (h->features & VG_FEAT_ADJ) {
         h->lam_alt = take(h->elem() * VG_NPOOL * (size_t)h->n);
         h->adj_part = (double *)take(sizeof(double) * VG_NGRAD * (size_t)h->adj_blocks);
-        h->adj_co2 = take(h->elem() * (size_t)h->nseg);
+        h->adj_co2 = take(h->elem() * 2 * (size_t)h->nseg);
         h->adj_flag = (int32_t *)take(sizeof(int32_t) * (size_t)h->nseg);
     }
     if (band_geometry(h)) {
@@ -732,6 +732,59 @@ extern "C" int vg_record(vg_sim *h, int64_t nsteps, double dt, void *states_d, v
     if (h->params.sequential) { set_error("the adjoint follows Algorithm 1 only"); return VG_EINVAL; }
     if (nsteps < 0 || !(dt > 0) || (nsteps > 0 && h->n > 0 && !states_d)) { set_error("bad record arguments"); return VG_EINVAL; }
     return launch_record(h, nsteps, dt, states_d, (hipStream_t)stream);
+}
+
+extern "C" int vg_step_record(vg_sim *h, int64_t nsteps, double dt, void *states_d, double *totals_log_d,
+                              unsigned flags, void *stream) {
+    int rc = need_bound(h);
+    if (rc) return rc;
+    if (!(h->features & VG_FEAT_ADJ)) { set_error("handle created without VG_FEAT_ADJ"); return VG_ESTATE; }
+    if (h->params.step_order != VG_ORDER_TD) { set_error("the adjoint supports the paper order only"); return VG_EINVAL; }
+    if (h->params.sequential) { set_error("the adjoint follows Algorithm 1 only"); return VG_EINVAL; }
+    if (flags & ~VG_FORCE) { set_error("unknown flags"); return VG_EINVAL; }
+    if (nsteps < 0 || !(dt > 0) || !std::isfinite(dt) ||
+        (nsteps > 0 && h->n > 0 && (!states_d || !totals_log_d))) {
+        set_error("bad step-record arguments");
+        return VG_EINVAL;
+    }
+    if (!(flags & VG_FORCE) && (rc = check_stable(h, dt))) return rc;
+    if (nsteps == 0 || h->n == 0) return VG_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t row = (size_t)h->nseg * 6;
+    const int64_t n = h->n;
+    const size_t esz = h->elem();
+    char *st = (char *)states_d;
+    auto state = [&](int64_t j, int p) { return (void *)(st + ((size_t)j * VG_NPOOL + p) * n * esz); };
+    // states[0] = x^k0, states[j] = T(D(states[j-1])) (T alone for j = 1);
+    // the fused pass j >= 2 sees x^(k0+j-1) between its halves: row j-2
+    if ((rc = launch_record(h, 1, dt, states_d, s))) return rc;
+    for (int64_t j = 1; j < nsteps; j++) {
+        const void *src[VG_NPOOL];
+        void *dst[VG_NPOOL];
+        for (int p = 0; p < VG_NPOOL; p++) {
+            src[p] = state(j - 1, p);
+            dst[p] = state(j, p);
+        }
+        if ((rc = launch_pass_bufs(h, j == 1 ? MODE_T : MODE_DT, j == 1 ? TOT_NONE : TOT_MID, dt, src, dst, s)))
+            return rc;
+        if (j >= 2 && (rc = launch_totals_finalize(h, totals_log_d + (size_t)(j - 2) * row, s))) return rc;
+    }
+    // the last two steps into the bound fields (canonical between calls):
+    // T(D(states[nsteps-1])) (T alone when nsteps = 1), then D
+    {
+        const void *src[VG_NPOOL];
+        void *dst[VG_NPOOL];
+        for (int p = 0; p < VG_NPOOL; p++) {
+            src[p] = state(nsteps - 1, p);
+            dst[p] = h->fields + (size_t)p * n * esz;
+        }
+        const bool one = nsteps == 1;
+        if ((rc = launch_pass_bufs(h, one ? MODE_T : MODE_DT, one ? TOT_NONE : TOT_MID, dt, src, dst, s))) return rc;
+        if (!one && (rc = launch_totals_finalize(h, totals_log_d + (size_t)(nsteps - 2) * row, s))) return rc;
+    }
+    if ((rc = launch_pass(h, MODE_D, TOT_OUT, dt, s))) return rc;
+    if ((rc = launch_totals_finalize(h, totals_log_d + (size_t)(nsteps - 1) * row, s))) return rc;
+    return restore_canonical(h, s);
 }
 
 extern "C" int vg_adjoint(vg_sim *h, int64_t nsteps, double dt, const void *states_d, const double *seeds_d,

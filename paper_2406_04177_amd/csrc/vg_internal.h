@@ -556,7 +556,7 @@ struct vg_sim {
     unsigned adj_flags = 0;      // VG_ADJ_* options
     char *lam_alt = nullptr;     // [5][n] field type
     double *adj_part = nullptr;  // [adj_blocks][VG_NGRAD]
-    char *adj_co2 = nullptr;     // [nseg] field type: the CO2 adjoint of each volume (uniform case)
+    char *adj_co2 = nullptr;     // [2][nseg] field type: the CO2 adjoint of each volume (uniform case)
     int32_t *adj_flag = nullptr; // [nseg] nonzero: the CO2 adjoint of the volume is not uniform
     int adj_blocks = 0;
 

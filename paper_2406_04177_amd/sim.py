@@ -219,6 +219,19 @@ class Simulation:
     def record(self, nsteps: int, dt: float, states: torch.Tensor):
         _lib.check(self.L.vg_record(self.h, int(nsteps), float(dt), states.data_ptr(), self._sp()), "vg_record")
 
+    def step_record(self, nsteps: int, dt: float, states: torch.Tensor, totals_out: torch.Tensor,
+                    force: bool = False):
+        """Advance nsteps steps, recording the adjoint's states ([nsteps, 5, n]
+        field type, as record()) and the totals after every step into
+        totals_out ([nsteps, nseg, 6] FP64 on the device)."""
+        if totals_out.dtype != torch.float64 or not totals_out.is_contiguous() or \
+                totals_out.numel() < nsteps * self.nseg * 6:
+            raise ValueError("totals_out must be a contiguous float64 tensor of nsteps * nseg * 6 entries")
+        if states.dtype != self.dtype or not states.is_contiguous() or states.numel() < nsteps * 5 * self.graph.n:
+            raise ValueError("states must be a contiguous [nsteps, 5, n] tensor of the field type")
+        _lib.check(self.L.vg_step_record(self.h, int(nsteps), float(dt), states.data_ptr(), totals_out.data_ptr(),
+                                         _lib.VG_FORCE if force else 0, self._sp()), "vg_step_record")
+
     def adjoint(self, nsteps: int, dt: float, states: torch.Tensor, seeds: torch.Tensor, lam: torch.Tensor,
                 grad: torch.Tensor):
         _lib.check(self.L.vg_adjoint(self.h, int(nsteps), float(dt), states.data_ptr(), seeds.data_ptr(),

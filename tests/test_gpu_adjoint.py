@@ -298,3 +298,69 @@ def test_reverse_sweep_with_given_final_adjoint(uniform_co2):
     scale = np.abs(g_or).max()
     for q in range(5, 12):   # the kinetic rates (well conditioned)
         assert abs(gg[q] - g_or[q]) <= 1e-9 * abs(g_or[q]) + 1e-12 * scale, (q, gg[q], g_or[q])
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+@pytest.mark.parametrize("k", [1, 2, 7])
+def test_step_record_equals_step_and_record(precision, k):
+    """vg_step_record: the state and every step's totals bit-identical to
+    vg_step_explicit with log_every = 1, the states to vg_record's, for one
+    to several steps and both field types (batch with unequal volumes)."""
+    from paper_2406_04177_amd.graph import Graph
+    from paper_2406_04177_amd.sim import Simulation
+    masks, specs = batch(seed=9)
+    p = rates()
+    c = [1.0, 0.9, 0.8, 1.05, 0.95, 0.85, 1.0, 0.9]
+    dt = inputs.explicit_dt(p, 0.8)
+    g = Graph.from_masks(masks, regions=True)
+    dtype = torch.float64 if precision == "f64" else torch.float32
+    x0 = g.fields_from_specs(specs, dtype)
+    sim = Simulation(g, p, precision=precision, implicit=False, adjoint=True, regions=c)
+    sim.set_fields(x0)
+    sim.step(3, dt)                      # start away from the initial state
+    start = sim.fields.clone()
+    ref_states = torch.empty((k, 5, g.n), dtype=dtype, device="cuda")
+    sim.record(k, dt, ref_states)
+    ref_tot = torch.empty((k, g.nseg, 6), dtype=torch.float64, device="cuda")
+    sim.step(k, dt, log_every=1, totals_out=ref_tot)
+    ref_x = sim.fields.clone()
+    sim.set_fields(start)
+    states = torch.empty_like(ref_states)
+    tot = torch.empty_like(ref_tot)
+    sim.step_record(k, dt, states, tot)
+    torch.cuda.synchronize()
+    assert torch.equal(sim.fields, ref_x)
+    assert torch.equal(tot, ref_tot)
+    assert torch.equal(states, ref_states)
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_taped_segments_give_the_same_gradient(precision):
+    """Segments recorded by the forward (the default memory budget keeps all
+    of them here) and segments recorded again in the backward (no budget)
+    give bit-identical gradients and totals; a budget for some segments
+    only mixes both."""
+    from paper_2406_04177_amd.autograd import simulate_totals, theta_of
+    from paper_2406_04177_amd.graph import Graph
+    from paper_2406_04177_amd.sim import Simulation
+    masks, specs = batch(seed=3)
+    p = rates()
+    c = [0.8, 0.9, 1.0, 0.85, 0.95, 0.75, 0.9, 1.0]
+    dt = inputs.explicit_dt(p, 0.8)
+    nsteps, K = 23, 5
+    g = Graph.from_masks(masks, regions=True)
+    sim = Simulation(g, p, precision=precision, implicit=False, adjoint=True, regions=c)
+    dtype = torch.float64 if precision == "f64" else torch.float32
+    seeds = torch.as_tensor(np.random.default_rng(2).standard_normal((nsteps + 1, len(masks), 5)), device="cuda")
+    per_seg = K * 5 * g.n * torch.empty((), dtype=dtype).element_size()
+    out = []
+    for tape in (0, None, 2 * per_seg + 1):
+        x0 = g.fields_from_specs(specs, dtype).requires_grad_(True)
+        theta = theta_of(p, c).requires_grad_(True)
+        tot = simulate_totals(sim, theta, x0, nsteps, dt, checkpoint_every=K, tape_bytes=tape)
+        (tot * seeds).sum().backward()
+        out.append((theta.grad.clone(), x0.grad.clone(), tot.detach().clone()))
+    for gr, lam, tot in out[1:]:
+        assert torch.equal(gr, out[0][0])
+        assert torch.equal(lam, out[0][1])
+        assert torch.equal(tot, out[0][2])
