@@ -76,11 +76,11 @@ size_t layout(vg_sim *h, char *base) {
     h->piece_lo = (int64_t *)take(sizeof(int64_t) * (size_t)(h->npieces + 1));
     h->piece_seg = (int32_t *)take(sizeof(int32_t) * (size_t)h->npieces);
     h->seg_first = (int32_t *)take(sizeof(int32_t) * (size_t)(h->nseg + 1));
-    h->part = (double *)take(sizeof(double) * VG_NPOOL * (size_t)h->npieces);
+    h->part = (double *)take(sizeof(double) * VG_NPOOL * (size_t)h->npieces * (size_t)h->tot_batch);
     h->tot_tmp = (double *)take(sizeof(double) * 6 * (size_t)h->nseg);
     h->chunk_first = (int32_t *)take(sizeof(int32_t) * (size_t)(h->nchunks + 1));
     h->seg_chunk = (int32_t *)take(sizeof(int32_t) * (size_t)(h->nseg + 1));
-    h->chunk_part = (double *)take(sizeof(double) * VG_NPOOL * (size_t)h->nchunks);
+    h->chunk_part = (double *)take(sizeof(double) * VG_NPOOL * (size_t)h->nchunks * (size_t)h->tot_batch);
     h->geo = h->rank ? (uint32_t *)take(sizeof(uint32_t) * (size_t)h->n) : nullptr;
     h->off_m = (uint32_t *)take(sizeof(uint32_t) * (size_t)h->n);
     h->off_p = (uint32_t *)take(sizeof(uint32_t) * (size_t)h->n);
@@ -186,6 +186,10 @@ void make_pieces(vg_sim *h) {
     }
     h->seg_chunk_h[h->nseg] = h->nchunks;
     h->chunk_first_h.push_back(h->npieces);
+    // logged passes per totals launch: up to 32, within 32 MB of partials
+    const int64_t row_bytes = (int64_t)sizeof(double) * VG_NPOOL * (h->npieces > 0 ? h->npieces : 1);
+    const int64_t tb = ((int64_t)32 << 20) / row_bytes;
+    h->tot_batch = (int)(tb < 1 ? 1 : (tb > 32 ? 32 : tb));
     const int64_t cap = 2048;
     h->cg_blocks = (int)(h->ntiles < cap ? (h->ntiles > 0 ? h->ntiles : 1) : cap);
     h->adj_blocks = h->cg_blocks;
@@ -476,7 +480,7 @@ extern "C" int vg_workspace_bytes(const vg_sim *h, size_t *bytes) {
     vg_sim tmp;
     tmp.n = h->n; tmp.nseg = h->nseg; tmp.prec = h->prec; tmp.features = h->features; tmp.mobile_all = h->mobile_all;
     tmp.ntiles = h->ntiles; tmp.npieces = h->npieces; tmp.cg_blocks = h->cg_blocks; tmp.adj_blocks = h->adj_blocks;
-    tmp.nchunks = h->nchunks;
+    tmp.nchunks = h->nchunks; tmp.tot_batch = h->tot_batch;
     tmp.rank = h->rank;   // the geometry words are part of the workspace when a rank index is used
     tmp.vox = h->vox; tmp.nx = h->nx; tmp.ny = h->ny; tmp.nz = h->nz; tmp.brick = h->brick; tmp.periodic = h->periodic;
     tmp.mg_plan_levels = h->mg_plan_levels;
@@ -552,8 +556,20 @@ extern "C" int vg_step_explicit(vg_sim *h, int64_t nsteps, double dt, int64_t lo
     hipStream_t s = (hipStream_t)stream;
     const size_t row = (size_t)h->nseg * 6;
     auto logged = [&](int64_t j) { return log_every > 0 && j % log_every == 0; };
-    auto finalize = [&](int64_t j) -> int {
-        return launch_totals_finalize(h, totals_log_d + (size_t)(j / log_every - 1) * row, s);
+    // the partials of up to tot_batch logged passes wait in their slots and
+    // are reduced by one launch (rows first_row ..)
+    int64_t first_row = 0;
+    h->part_slot = 0;
+    auto flush = [&]() -> int {
+        const int rows = h->part_slot;
+        h->part_slot = 0;
+        const int rc2 = launch_totals_finalize(h, totals_log_d + (size_t)first_row * row, rows, s);
+        first_row += rows;
+        return rc2;
+    };
+    auto finalize = [&](int64_t) -> int {
+        if (++h->part_slot < h->tot_batch) return VG_OK;
+        return flush();
     };
     // four fused passes j .. j + 3 with no totals logged run as two band
     // launches when the band kernel applies
@@ -604,6 +620,7 @@ extern "C" int vg_step_explicit(vg_sim *h, int64_t nsteps, double dt, int64_t lo
             if (lg && (rc = finalize(j))) return rc;
         }
     }
+    if ((rc = flush())) return rc;
     return restore_canonical(h, s);
 }
 
@@ -657,8 +674,9 @@ extern "C" int vg_mass_totals(vg_sim *h, double *out_h, void *stream) {
         for (int i = 0; i < h->nseg * 6; i++) out_h[i] = 0.0;
         return VG_OK;
     }
+    h->part_slot = 0;
     if ((rc = launch_pass(h, MODE_NONE, TOT_IN, 1.0, s))) return rc;
-    if ((rc = launch_totals_finalize(h, h->tot_tmp, s))) return rc;
+    if ((rc = launch_totals_finalize(h, h->tot_tmp, 1, s))) return rc;
     if ((rc = hip_status(hipMemcpyAsync(out_h, h->tot_tmp, sizeof(double) * 6 * (size_t)h->nseg, hipMemcpyDeviceToHost, s),
                          "copy totals"))) return rc;
     if ((rc = hip_status(hipStreamSynchronize(s), "synchronise"))) return rc;
@@ -758,6 +776,16 @@ extern "C" int vg_step_record(vg_sim *h, int64_t nsteps, double dt, void *states
     // states[0] = x^k0, states[j] = T(D(states[j-1])) (T alone for j = 1);
     // the fused pass j >= 2 sees x^(k0+j-1) between its halves: row j-2
     if ((rc = launch_record(h, 1, dt, states_d, s))) return rc;
+    int64_t first_row = 0;   // batched totals as in vg_step_explicit
+    h->part_slot = 0;
+    auto flush = [&]() -> int {
+        const int rows = h->part_slot;
+        h->part_slot = 0;
+        const int rc2 = launch_totals_finalize(h, totals_log_d + (size_t)first_row * row, rows, s);
+        first_row += rows;
+        return rc2;
+    };
+    auto logged = [&]() -> int { return ++h->part_slot < h->tot_batch ? VG_OK : flush(); };
     for (int64_t j = 1; j < nsteps; j++) {
         const void *src[VG_NPOOL];
         void *dst[VG_NPOOL];
@@ -767,7 +795,7 @@ extern "C" int vg_step_record(vg_sim *h, int64_t nsteps, double dt, void *states
         }
         if ((rc = launch_pass_bufs(h, j == 1 ? MODE_T : MODE_DT, j == 1 ? TOT_NONE : TOT_MID, dt, src, dst, s)))
             return rc;
-        if (j >= 2 && (rc = launch_totals_finalize(h, totals_log_d + (size_t)(j - 2) * row, s))) return rc;
+        if (j >= 2 && (rc = logged())) return rc;
     }
     // the last two steps into the bound fields (canonical between calls):
     // T(D(states[nsteps-1])) (T alone when nsteps = 1), then D
@@ -780,10 +808,11 @@ extern "C" int vg_step_record(vg_sim *h, int64_t nsteps, double dt, void *states
         }
         const bool one = nsteps == 1;
         if ((rc = launch_pass_bufs(h, one ? MODE_T : MODE_DT, one ? TOT_NONE : TOT_MID, dt, src, dst, s))) return rc;
-        if (!one && (rc = launch_totals_finalize(h, totals_log_d + (size_t)(nsteps - 2) * row, s))) return rc;
+        if (!one && (rc = logged())) return rc;
     }
     if ((rc = launch_pass(h, MODE_D, TOT_OUT, dt, s))) return rc;
-    if ((rc = launch_totals_finalize(h, totals_log_d + (size_t)(nsteps - 1) * row, s))) return rc;
+    if ((rc = logged())) return rc;
+    if ((rc = flush())) return rc;
     return restore_canonical(h, s);
 }
 

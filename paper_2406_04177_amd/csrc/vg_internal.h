@@ -497,7 +497,7 @@ struct vg_sim {
     int32_t max_seg_pieces = 0;  // most pieces in one segment (one-stage totals up to 4096)
     std::vector<int32_t> chunk_first_h, seg_chunk_h;
     int32_t *chunk_first = nullptr, *seg_chunk = nullptr;
-    double *chunk_part = nullptr;   // [nchunks][5]
+    double *chunk_part = nullptr;   // [tot_batch][nchunks][5]
     // rank-index neighbours (single volume)
     const void *rank = nullptr;
     int nx = 0, ny = 0, nz = 0, brick = 0;
@@ -525,7 +525,9 @@ struct vg_sim {
     std::vector<int64_t> piece_lo_h;
     int32_t *piece_first = nullptr, *piece_seg = nullptr, *seg_first = nullptr;
     int64_t *piece_lo = nullptr;
-    double *part = nullptr;      // [npieces][5]
+    double *part = nullptr;      // [tot_batch][npieces][5]: partials of up to tot_batch logged passes
+    int tot_batch = 1;           // logged passes whose totals are reduced by one launch
+    int part_slot = 0;           // the slot the next pass with totals writes
     double *tot_tmp = nullptr;   // [nseg][6]
     // implicit CG (FP64 vectors)
     double *cg_y = nullptr, *cg_r = nullptr, *cg_z = nullptr, *cg_q = nullptr, *cg_m = nullptr;
@@ -585,7 +587,11 @@ int launch_pass(vg_sim *h, int mode, int tot, double dt, hipStream_t s);
 int launch_pass2(vg_sim *h, int mode, int tot, double dt_t, double dt_d, hipStream_t s);
 int launch_pass_bufs(vg_sim *h, int mode, int tot, double dt, const void *const src[VG_NPOOL],
                      void *const dst[VG_NPOOL], hipStream_t s);
-int launch_totals_finalize(vg_sim *h, double *out_rows, hipStream_t s);
+// Reduces the partials of slots 0 .. rows-1 into rows consecutive totals
+// rows out_rows[r][nseg][6].
+int launch_totals_finalize(vg_sim *h, double *out_rows, int rows, hipStream_t s);
+// The partials the next pass with totals writes (slot part_slot).
+inline double *part_of(const vg_sim *h) { return h->part + (size_t)h->part_slot * VG_NPOOL * (size_t)h->npieces; }
 int launch_geometry(vg_sim *h, hipStream_t s);
 bool use_rank(const vg_sim *h);
 bool use_offsets(const vg_sim *h);

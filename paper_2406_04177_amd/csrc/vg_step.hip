@@ -822,12 +822,16 @@ __global__ __launch_bounds__(kBlock) void k_rel_pack(const int32_t *__restrict__
     out[i] = w;
 }
 
-// Totals, stage 1: chunks of up to kChunk pieces of one segment.
+// Totals, stage 1: chunks of up to kChunk pieces of one segment (blockIdx.y:
+// the logged pass; part and chunk_part advance by their row strides).
 __global__ __launch_bounds__(kBlock) void k_tot_chunks(const double *__restrict__ part,
                                                        const int32_t *__restrict__ chunk_first,
-                                                       double *__restrict__ chunk_part) {
+                                                       double *__restrict__ chunk_part, int64_t part_stride,
+                                                       int64_t chunk_stride) {
     __shared__ double lds[kWaves * VG_NPOOL];
     const int c = blockIdx.x;
+    part += blockIdx.y * part_stride;
+    chunk_part += blockIdx.y * chunk_stride;
     const int32_t p = chunk_first[c] + (int32_t)threadIdx.x;
     double v[VG_NPOOL] = {0, 0, 0, 0, 0};
     if (p < chunk_first[c + 1]) {
@@ -845,9 +849,12 @@ __global__ __launch_bounds__(kBlock) void k_tot_chunks(const double *__restrict_
 // then the five pool totals into total carbon.
 __global__ __launch_bounds__(kBlock) void k_tot_segments(const double *__restrict__ chunk_part,
                                                          const int32_t *__restrict__ seg_chunk,
-                                                         double *__restrict__ out) {
+                                                         double *__restrict__ out, int64_t chunk_stride,
+                                                         int64_t out_stride) {
     __shared__ double lds[kWaves * VG_NPOOL];
     const int g = blockIdx.x;
+    chunk_part += blockIdx.y * chunk_stride;
+    out += blockIdx.y * out_stride;
     double v[VG_NPOOL] = {0, 0, 0, 0, 0};
     for (int32_t c = seg_chunk[g] + (int32_t)threadIdx.x; c < seg_chunk[g + 1]; c += kBlock) {
 #pragma unroll
@@ -869,9 +876,12 @@ constexpr int32_t kDirectPieces = 4096;
 
 __global__ __launch_bounds__(kBlock) void k_tot_direct(const double *__restrict__ part,
                                                        const int32_t *__restrict__ seg_first,
-                                                       double *__restrict__ out) {
+                                                       double *__restrict__ out, int64_t part_stride,
+                                                       int64_t out_stride) {
     __shared__ double lds[kWaves * VG_NPOOL];
     const int g = blockIdx.x;
+    part += blockIdx.y * part_stride;
+    out += blockIdx.y * out_stride;
     double v[VG_NPOOL] = {0, 0, 0, 0, 0};
     for (int32_t p = seg_first[g] + (int32_t)threadIdx.x; p < seg_first[g + 1]; p += kBlock) {
 #pragma unroll
@@ -916,45 +926,45 @@ int launch_one(vg_sim *h, const StepBufs<R> &B, const Coef<R> &C, hipStream_t s)
             const unsigned grid = (unsigned)((h->n + kBlock * V2 - 1) / (kBlock * V2));
             if (use_relative(h)) {
                 hipLaunchKernelGGL((k_step_off<R, MODE, MOB, REG, TOT, true, false, V2>), dim3(grid), dim3(kBlock),
-                                   0, s, B, C, pc, h->part);
+                                   0, s, B, C, pc, part_of(h));
                 return launch_status("k_step_off relative");
             }
             if (use_offsets(h)) {
                 hipLaunchKernelGGL((k_step_off<R, MODE, MOB, REG, TOT, false, false, V2>), dim3(grid), dim3(kBlock),
-                                   0, s, B, C, pc, h->part);
+                                   0, s, B, C, pc, part_of(h));
                 return launch_status("k_step_off");
             }
         }
         if (use_relative(h)) {
             if (seq)
                 hipLaunchKernelGGL((k_step_off<R, MODE, MOB, REG, TOT, true, MODE == MODE_DT>),
-                                   dim3((unsigned)h->ntiles), dim3(kBlock), 0, s, B, C, pc, h->part);
+                                   dim3((unsigned)h->ntiles), dim3(kBlock), 0, s, B, C, pc, part_of(h));
             else
                 hipLaunchKernelGGL((k_step_off<R, MODE, MOB, REG, TOT, true, false>), dim3((unsigned)h->ntiles),
-                                   dim3(kBlock), 0, s, B, C, pc, h->part);
+                                   dim3(kBlock), 0, s, B, C, pc, part_of(h));
             return launch_status("k_step_off relative");
         }
         if (use_offsets(h)) {
             if (seq)
                 hipLaunchKernelGGL((k_step_off<R, MODE, MOB, REG, TOT, false, MODE == MODE_DT>),
-                                   dim3((unsigned)h->ntiles), dim3(kBlock), 0, s, B, C, pc, h->part);
+                                   dim3((unsigned)h->ntiles), dim3(kBlock), 0, s, B, C, pc, part_of(h));
             else
                 hipLaunchKernelGGL((k_step_off<R, MODE, MOB, REG, TOT, false, false>), dim3((unsigned)h->ntiles),
-                                   dim3(kBlock), 0, s, B, C, pc, h->part);
+                                   dim3(kBlock), 0, s, B, C, pc, part_of(h));
             return launch_status("k_step_off");
         }
     }
     if (use_rank(h) && MODE != MODE_NONE) {
         if (h->brick == 0)
             hipLaunchKernelGGL((k_step_geo<R, MODE, MOB, REG, TOT, true>), dim3((unsigned)h->ntiles), dim3(kBlock), 0,
-                               s, B, C, make_rgeom(h), h->geo, h->part);
+                               s, B, C, make_rgeom(h), h->geo, part_of(h));
         else
             hipLaunchKernelGGL((k_step_geo<R, MODE, MOB, REG, TOT, false>), dim3((unsigned)h->ntiles), dim3(kBlock), 0,
-                               s, B, C, make_rgeom(h), h->geo, h->part);
+                               s, B, C, make_rgeom(h), h->geo, part_of(h));
         return launch_status("k_step_geo");
     }
     hipLaunchKernelGGL((k_step<R, MODE, MOB, REG, TOT>), dim3((unsigned)h->ntiles), dim3(kBlock), 0, s, B,
-                       C, pc, h->part);
+                       C, pc, part_of(h));
     return launch_status("k_step");
 }
 
@@ -1183,7 +1193,7 @@ __global__ __launch_bounds__(kBlock) void k_band2(StepBufs<R> B, Coef<R> C, Band
 template <int MODE, int MOB, int TOT>
 int launch_c(vg_sim *h, const CompBufs &B, const Coef<double> &C, hipStream_t s) {
     Pieces pc{h->piece_first, h->piece_lo, h->piece_seg, h->npieces};
-    hipLaunchKernelGGL((k_step_c<MODE, MOB, TOT>), dim3((unsigned)h->ntiles), dim3(kBlock), 0, s, B, C, pc, h->part);
+    hipLaunchKernelGGL((k_step_c<MODE, MOB, TOT>), dim3((unsigned)h->ntiles), dim3(kBlock), 0, s, B, C, pc, part_of(h));
     return launch_status("k_step_c");
 }
 
@@ -1515,19 +1525,21 @@ int launch_pass_bufs(vg_sim *h, int mode, int tot, double dt, const void *const 
     return dispatch_bufs<float>(h, mode, tot, dt, dt, B, s);
 }
 
-int launch_totals_finalize(vg_sim *h, double *out_rows, hipStream_t s) {
-    if (h->nseg == 0 || h->n == 0) return VG_OK;
+int launch_totals_finalize(vg_sim *h, double *out_rows, int rows, hipStream_t s) {
+    if (h->nseg == 0 || h->n == 0 || rows <= 0) return VG_OK;
+    const int64_t part_stride = (int64_t)VG_NPOOL * h->npieces, out_stride = (int64_t)h->nseg * 6;
+    const int64_t chunk_stride = (int64_t)VG_NPOOL * h->nchunks;
     if (h->max_seg_pieces <= kDirectPieces) {
-        hipLaunchKernelGGL(k_tot_direct, dim3((unsigned)h->nseg), dim3(kBlock), 0, s, h->part, h->seg_first,
-                           out_rows);
+        hipLaunchKernelGGL(k_tot_direct, dim3((unsigned)h->nseg, (unsigned)rows), dim3(kBlock), 0, s, h->part,
+                           h->seg_first, out_rows, part_stride, out_stride);
         return launch_status("k_tot_direct");
     }
-    hipLaunchKernelGGL(k_tot_chunks, dim3((unsigned)h->nchunks), dim3(kBlock), 0, s, h->part, h->chunk_first,
-                       h->chunk_part);
+    hipLaunchKernelGGL(k_tot_chunks, dim3((unsigned)h->nchunks, (unsigned)rows), dim3(kBlock), 0, s, h->part,
+                       h->chunk_first, h->chunk_part, part_stride, chunk_stride);
     int rc = launch_status("k_tot_chunks");
     if (rc) return rc;
-    hipLaunchKernelGGL(k_tot_segments, dim3((unsigned)h->nseg), dim3(kBlock), 0, s, h->chunk_part, h->seg_chunk,
-                       out_rows);
+    hipLaunchKernelGGL(k_tot_segments, dim3((unsigned)h->nseg, (unsigned)rows), dim3(kBlock), 0, s, h->chunk_part,
+                       h->seg_chunk, out_rows, chunk_stride, out_stride);
     return launch_status("k_tot_segments");
 }
 
