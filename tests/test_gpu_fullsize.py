@@ -111,6 +111,40 @@ def test_implicit_step_512(full):
     assert err <= 1e-11, err
 
 
+def test_multigrid_implicit_step_512(full):
+    """The implicit step with the multigrid preconditioner in the benchmark's
+    configuration: the transformation half bit for bit, the true residual by
+    the oracle's matrix within 2 rtol, at most a third of Jacobi's
+    iterations, and agreement with the Jacobi solve within kappa * rtol."""
+    from paper_2406_04177_amd.sim import Simulation
+    mask, spec, g, og = full
+    p = inputs.ModelParams()
+    dt = 20 * inputs.explicit_dt(p, 1.0)
+    a = p.D[1] * dt / p.h ** 2
+    rtol = 1e-10
+    x0 = orc.fields_from_spec(og, spec)
+    xt = orc.transform(p, dt, x0)
+    sim = Simulation(g, p, precision="f64", implicit=True, multigrid=True)
+    print("levels", sim.mg_levels(), flush=True)
+    out = {}
+    for pc in ("jacobi", "mg"):
+        sim.set_preconditioner(pc)
+        sim.set_fields(g.fields_from_specs(spec, torch.float64))
+        its, rel, rc = sim.implicit_step(dt, rtol=rtol)
+        assert rc == 0 and rel[1] <= rtol
+        out[pc] = (its[1], sim.fields.cpu().numpy())
+    its_mg, got = out["mg"]
+    for s in (0, 2, 3, 4):
+        np.testing.assert_array_equal(got[s], xt[s])
+    b = xt[1]
+    true_res = np.linalg.norm(b - orc.apply_B(a, og, got[1])) / np.linalg.norm(b)
+    assert true_res <= 2 * rtol, true_res
+    assert 3 * its_mg <= out["jacobi"][0], (its_mg, out["jacobi"][0])
+    kappa = 1 + 12 * a
+    err = np.abs(got[1] - out["jacobi"][1][1]).max() / np.abs(got[1]).max()
+    assert err <= 2 * kappa * rtol, err
+
+
 def test_band_kernel_fp64_bitwise_512(full):
     """The band kernel (two fused passes per launch) in FP64 against the
     oracle bit for bit: 9 steps = a transformation pass, two runs of four

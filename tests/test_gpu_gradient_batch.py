@@ -146,3 +146,30 @@ def test_gradient_200_steps_against_oracle(work):
         del sim
     assert not compare(res["f64"], g_or, 1e-6, list(range(20))), compare(res["f64"], g_or, 1e-6, list(range(20)))
     assert not compare(res["f32"], g_or, 1e-3, CHECKED), compare(res["f32"], g_or, 1e-3, CHECKED)
+
+
+def test_recorded_forward_bitwise_at_full_size(work):
+    """On the whole batch (FP32, 400 steps, checkpoints every 100): every
+    segment recorded by the forward, none, and the last two give the same
+    gradient, adjoint of x0 and totals bit for bit."""
+    from paper_2406_04177_amd.autograd import co2_mse, simulate_totals
+    masks, specs, g, p, dt = work
+    steps, K = 400, 100
+    theta, tgt_theta = theta_parts()
+    sim = make_sim(g, p, "f32")
+    x0 = g.fields_from_specs(specs, torch.float32)
+    with torch.no_grad():
+        target = simulate_totals(sim, tgt_theta, x0, steps, dt, K)[:, :, 4].clone()
+    per_seg = K * 5 * g.n * 4
+    out = []
+    for tape in (0, 4 * per_seg, 2 * per_seg):
+        th = theta.clone().requires_grad_(True)
+        xg = x0.clone().requires_grad_(True)
+        tot = simulate_totals(sim, th, xg, steps, dt, K, tape_bytes=tape)
+        co2_mse(tot, target).backward()
+        out.append((th.grad.clone(), xg.grad.clone(), tot.detach().clone(), sim.last_taped_segments))
+    assert [o[3] for o in out] == [0, 4, 2]
+    for gr, lam, tot, _ in out[1:]:
+        assert torch.equal(gr, out[0][0])
+        assert torch.equal(lam, out[0][1])
+        assert torch.equal(tot, out[0][2])
