@@ -254,7 +254,36 @@ def step_1024(steps=101):
     res["brick_order"] = br
     log("1024^3 brick order: %.3f ms/step rank index, %.3f ms/step table (AUTO %s)"
         % (br["ms_per_step_rank"], br["ms_per_step_table"], br["auto_kernel"]))
-    del sim, x0, gb
+    del sim, x0
+    torch.cuda.empty_cache()
+    # the gradient at this size: the first 200 steps, checkpoints every 20,
+    # region weights, CO2 totals every step, static pools' D gradients skipped
+    from paper_2406_04177_amd.autograd import co2_mse, simulate_totals, theta_of
+    gb.make_region_codes()
+    sima = Simulation(gb, p, precision="f32", implicit=False, adjoint=True, regions=[1.0] * 8)
+    sima.set_adjoint_options(skip_static_d=True)
+    dta = inputs.explicit_dt(p, 0.8)
+    xa = gb.fields_from_specs(spec_full, torch.float32)
+    theta = theta_of(p, [1.0] * 8)
+    gsteps, gk = 200, 20
+    target = torch.zeros((gsteps + 1, gb.nseg), dtype=torch.float64, device="cuda")
+    with torch.no_grad():
+        simulate_totals(sima, theta, xa, gsteps, dta, gk)
+    ms_f, _ = timed(lambda: simulate_totals(sima, theta, xa, gsteps, dta, gk))
+
+    def grad1024():
+        th = theta.clone().requires_grad_(True)
+        co2_mse(simulate_totals(sima, th, xa, gsteps, dta, gk), target).backward()
+    grad1024()
+    ms_g, _ = timed(grad1024)
+    br["gradient_200_steps"] = {
+        "workload": "first 200 FP32 steps, checkpoints every 20, region weights, CO2 totals every step, "
+                    "static pools' D gradients skipped (table neighbours: brick order)",
+        "forward_ms": ms_f, "gradient_ms": ms_g, "gradient_forward_ratio": ms_g / ms_f,
+        "taped_segments": "%d of %d" % (sima.last_taped_segments, gsteps // gk)}
+    log("1024^3 brick order, gradient of 200 steps: forward %.0f ms, gradient %.0f ms (ratio %.2f, %s segments "
+        "recorded in the forward)" % (ms_f, ms_g, ms_g / ms_f, br["gradient_200_steps"]["taped_segments"]))
+    del sima, xa, gb
     torch.cuda.empty_cache()
     # one GPU's share of the 1024^3 volume split into 8 z-slabs: its first 128
     # planes as a volume of their own (closed faces: no halo exchange)
