@@ -396,6 +396,54 @@ def accuracy_runs(N, steps, label):
     return res
 
 
+def implicit_run(mask, nsteps, every=5):
+    """The 512^3 workload's implicit run: nsteps implicit steps at 20x the
+    explicit bound (1.92 s; 4500 of them cover the 8640 s of the explicit
+    run's 10^5 steps of 0.0864 s), FP64 fields, multigrid-preconditioned CG
+    at rtol 1e-10, totals every `every` steps; against the explicit FP64 run
+    over the same simulated time: final totals per pool and carbon drift."""
+    import numpy as np
+    import torch
+    from paper_2406_04177_amd import inputs
+    from paper_2406_04177_amd.graph import Graph
+    from paper_2406_04177_amd.sim import Simulation
+    g = Graph.from_masks(mask)
+    spec = inputs.init_uniform(mask, seed=0)
+    p = inputs.ModelParams()
+    dti, dte = 20.0 * inputs.explicit_dt(p, 1.0), inputs.explicit_dt(p, 0.9)
+    x0 = g.fields_from_specs(spec, torch.float64)
+    sim = Simulation(g, p, precision="f64", implicit=True, multigrid=True)
+    sim.set_preconditioner("mg")
+    sim.set_fields(x0)
+    c0 = float(sim.totals()[:, 5].sum())
+    its, drift = [], 0.0
+    t0 = time.perf_counter()
+    for k in range(1, nsteps + 1):
+        its.append(sim.implicit_step(dti, rtol=1e-10)[0][1])
+        if k % every == 0 or k == nsteps:
+            drift = max(drift, abs(float(sim.totals()[:, 5].sum()) / c0 - 1))
+    sec_i = time.perf_counter() - t0
+    tot_i = sim.totals()[0]
+    del sim
+    torch.cuda.empty_cache()
+    ne = int(round(nsteps * dti / dte))
+    sim = Simulation(g, p, precision="f64", implicit=False)
+    sim.set_fields(x0)
+    ms_e, _ = timed(lambda: sim.step(ne, dte, log_every=100, totals_out=torch.empty(
+        (ne // 100, g.nseg, 6), dtype=torch.float64, device="cuda")))
+    tot_e = sim.totals()[0]
+    rel = np.abs(tot_i[:5] - tot_e[:5]) / np.maximum(np.abs(tot_e[:5]), 1e-300)
+    res = {"workload": "512^3, %d implicit steps of %.3f s (FP64 fields, multigrid CG, rtol 1e-10, totals every %d) "
+                       "vs %d explicit FP64 steps of %.4f s" % (nsteps, dti, every, ne, dte),
+           "simulated_s": nsteps * dti, "implicit_s": sec_i, "cg_iterations": int(sum(its)),
+           "cg_iterations_per_step": float(np.mean(its)), "explicit_s": ms_e / 1e3,
+           "carbon_drift_implicit": drift,
+           "final_totals_rel_diff_vs_explicit": dict(zip(("MB", "DOM", "SOM", "P4", "CO2"), map(float, rel)))}
+    log("implicit run: %d steps in %.1f s (%.1f CG iterations per step), explicit %d steps in %.1f s; final totals "
+        "differ by %s" % (nsteps, sec_i, np.mean(its), ne, ms_e / 1e3, " ".join("%.1e" % v for v in rel)))
+    return res
+
+
 def gradient_batch(steps, K=100):
     """The gradient workload: 16 x 128^3 volumes (porosities U(0.12, 0.25)),
     FP32 fields, CO2 totals every step, loss = MSE against the curve of the
@@ -709,6 +757,9 @@ def main(argv=None):
     ap.add_argument("--zlayer", type=int, default=1, help="run the 512^3 z-layer diffusion comparison (0: skip)")
     ap.add_argument("--pngm", type=int, default=1, help="run the 512^3 pore-network fitting row (0: skip)")
     ap.add_argument("--big", type=int, default=1, help="run the 1024^3 explicit-step row (0: skip)")
+    ap.add_argument("--implicit-run", type=int, default=0,
+                    help="implicit steps of the 512^3 implicit run (4500 cover the explicit run's 8640 s; "
+                         "0: skip; about 2.5 min for 4500)")
     ap.add_argument("--kernel", choices=("auto", "table", "rank", "offset", "relative", "band"), default="auto",
                     help="neighbour source of the explicit-step kernel")
     ap.add_argument("--precision", choices=("f32", "f32c", "f64"), default="f32",
@@ -817,7 +868,8 @@ def main(argv=None):
     def want(name):
         return (selected is None and not args.quick) or (selected is not None and name in selected)
 
-    if selected is not None or not args.quick:
+    have_rows = selected is not None or not args.quick or args.implicit_run > 0
+    if have_rows:
         rows = {}
         rows["a1_graph_build_ms"] = ms_graph
     sim32 = sim
@@ -947,12 +999,14 @@ def main(argv=None):
         out["adjoint_forward_ratio"] = rows["a6_gradient_16x128"]["gradient_forward_ratio_all_d"]
     if want("fit") and args.fit_epochs > 0:
         rows["f1_fit_16x128"] = fit_batch(args.fit_epochs, steps=args.grad_steps)
-    if selected is not None or not args.quick:
+    if have_rows:
         out["rows"] = rows
         # FP32 and compensated FP32 fields (FP64 totals) against the plain
         # FP64 step: the 256^3 workload at its length (10^4 steps) and the
         # 512^3 one at its (10^5 steps), totals every 100, error per species
         # (fields, relative to each pool's max) and per totals curve
+    if args.implicit_run > 0:
+        rows["implicit_run_512"] = implicit_run(mask, args.implicit_run)
     if want("precision"):
         rows["precision_256"] = accuracy_runs(256, args.acc_steps, "FP32 vs FP64 workload")
         if args.long_steps > 0:
