@@ -164,6 +164,9 @@ def test_calls_out_of_sequence():
     assert L.vg_mass_totals(h, out.ctypes.data, None) == _lib.VG_ESTATE
     assert L.vg_solve_implicit_step(h, 1.0, 1e-10, 10, None, None, None) == _lib.VG_ESTATE
     assert L.vg_record(h, 1, 1.0, None, None) == _lib.VG_ESTATE
+    assert L.vg_step_record(h, 1, 1.0, None, None, 0, None) == _lib.VG_ESTATE
+    assert L.vg_step_record(None, 1, 1.0, None, None, 0, None) == _lib.VG_EINVAL
+    assert L.vg_precondition(h, 1.0, None, None, None) == _lib.VG_ESTATE
     ws = ctypes.c_size_t(0)
     assert L.vg_workspace_bytes(h, ctypes.byref(ws)) == 0 and ws.value > 0
     assert L.vg_init_state(h, 0x1000, 0x1000, 0x1000, 0, None) == _lib.VG_EINVAL   # workspace too small
