@@ -153,6 +153,14 @@ __device__ __forceinline__ constexpr bool mobile(int s) {
     return MOB == 2 || (MOB == 1 && s == 1);
 }
 
+// Pools whose adjoint differences a reverse step takes: the diffusing ones,
+// and with DALL the others too (for dL/dD_s only); never a uniform CO2
+// adjoint (its differences are all zero).
+template <int MOB, bool DALL, bool CO2U>
+__device__ __forceinline__ constexpr bool adj_differenced(int s) {
+    return (DALL || mobile<MOB>(s)) && !(CO2U && s == 4);
+}
+
 // Neighbour sources of the adjoint kernel (the forward's): the 6-slot table
 // with 64-bit indexing, or a packed source with 32-bit indexing.
 enum { NS_TABLE = 0, NS_REL = 1, NS_OFF = 2 };
@@ -181,6 +189,51 @@ __device__ __forceinline__ T &elem(T *b, uint32_t i) {
 template <typename T>
 __device__ __forceinline__ T &elem(T *b, int64_t i) {
     return b[i];
+}
+
+// What a reverse step reads of the voxel itself: its stored state, lambda^(k+1)
+// (CO2's only when it is not uniform), its neighbour words (the table's six
+// indices, or the packed words) and its region code.
+template <typename R, int NS>
+struct AdjOwn {
+    R x[VG_NPOOL], li[VG_NPOOL];
+    int32_t jt[NS == NS_TABLE ? 6 : 1];
+    PackedWords W;
+    uint32_t code;
+};
+
+// A load whose address is the same in every lane, through the constant
+// address space: it becomes a scalar load even where the kernel's stores
+// keep the compiler from proving that the word is read-only.
+template <typename T>
+__device__ __forceinline__ T uload(const T *p) {
+    return *(const __attribute__((address_space(4))) T *)p;
+}
+
+// Loads o for voxel i (a valid index: the loads are not guarded, so that a
+// wave issues the same memory instructions on every path).
+template <typename R, int MOB, bool REG, int NS, bool DALL, bool CO2U>
+__device__ __forceinline__ void adj_load_own(const AdjBufs<R> &A, const R *const *st, const R *const *lin,
+                                             typename AdjIndex<NS>::T i, AdjOwn<R, NS> &o) {
+    o.W = PackedWords{0, 0};
+    o.code = 0;
+    o.x[4] = o.li[4] = R(0);
+    if constexpr (NS == NS_TABLE) {
+#pragma unroll
+        for (int k = 0; k < 6; k++) o.jt[k] = A.nbr[(int64_t)k * A.n + i];
+    } else {
+        o.jt[0] = -1;
+        o.W = packed_words<NS == NS_REL>(A.pk, (uint32_t)i);
+    }
+#pragma unroll
+    for (int s = 0; s < VG_NPOOL - 1; s++) o.x[s] = elem(st[s], i);
+    // the CO2 state enters only dL/dD_CO2 (the transformation's derivative
+    // does not depend on it): not read when that term is not computed
+    if (!(MOB == 1 && (CO2U || !DALL))) o.x[4] = elem(st[4], i);
+#pragma unroll
+    for (int s = 0; s < VG_NPOOL - 1; s++) o.li[s] = elem(lin[s], i);
+    if (!CO2U) o.li[4] = elem(lin[4], i);
+    if (REG) o.code = elem(A.rcode, i);
 }
 
 // DALL: dL/da_s also for the pools that do not diffuse (their adjoints'
@@ -222,56 +275,67 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces 
         lout[s] = A.lout + (int64_t)s * n;
     }
 
-    for (int64_t it = 0;; it++) {
-    const int64_t t = xcd_stride_tile(blockIdx.x, gridDim.x, it, A.ntiles);
-    if (t >= A.ntiles) break;
-    // seeds of this step's totals: uniform when the tile lies in one volume
-    const int32_t pf = pc.piece_first[t], pl = pc.piece_first[t + 1];
-    const int32_t seg_tile = pl - pf == 1 ? pc.piece_seg[pf] : -1;
-    for (int v = 0; v < kVPT; v++) {
-        const int64_t i64 = t * kTile + v * kBlock + threadIdx.x;
-        if (i64 >= n) continue;
-        const I i = (I)i64;
+    // the seeds of this step's totals and the uniform CO2 adjoint of voxel
+    // i64's volume, taken piece by piece over the pieces that overlap its
+    // tile (uniform loads): the last piece that starts at or before the
+    // voxel holds it
+    auto volume_terms = [&](int64_t t, int64_t i64, double (&sd)[VG_NPOOL], R &lco2) {
+#pragma unroll
+        for (int s = 0; s < VG_NPOOL; s++) sd[s] = 0.0;
+        lco2 = R(0);
+        const int32_t pf = uload(pc.piece_first + t), pl = uload(pc.piece_first + t + 1);
+        for (int32_t p = pf; p < pl; p++) {
+            const int32_t sg = uload(pc.piece_seg + p);
+            const bool in = p == pf || i64 >= uload(pc.piece_lo + p);
+            const double *sp = A.seed + (int64_t)sg * VG_NPOOL;
+#pragma unroll
+            for (int s = 0; s < VG_NPOOL; s++) sd[s] = in ? uload(sp + s) : sd[s];
+            if (CO2U) lco2 = in ? uload(A.co2 + sg) : lco2;
+        }
+    };
+    // neighbour values of voxel i: the stored state of the diffusing pools
+    // (to recompute D) and lambda^(k+1) of the pools whose differences are
+    // taken
+    auto gather = [&](const AdjOwn<R, NS> &o, I i, R (&zj)[VG_NPOOL][6], R (&lj)[VG_NPOOL][6]) {
         // neighbour indices (an absent neighbour is the voxel itself: every
         // difference of an absent slot is exactly +0)
         I j[6];
         if constexpr (NS == NS_TABLE) {
 #pragma unroll
-            for (int k = 0; k < 6; k++) {
-                const int32_t jk = A.nbr[(int64_t)k * n + i];
-                j[k] = jk >= 0 ? (I)jk : i;
-            }
-        }
-        PackedWords W{0, 0};
-        if constexpr (NS != NS_TABLE) W = packed_words<NS == NS_REL>(A.pk, (uint32_t)i);
-        // forward state of this step and lambda^(k+1) of the voxel
-        R x[VG_NPOOL], li[VG_NPOOL];
-#pragma unroll
-        for (int s = 0; s < VG_NPOOL - 1; s++) x[s] = elem(st[s], i);
-        // the CO2 state enters only dL/dD_CO2 (the transformation's
-        // derivative does not depend on it): not read when that term is not
-        // computed
-        x[4] = (MOB == 1 && (CO2U || !DALL)) ? R(0) : elem(st[4], i);
-        // the volume of the voxel (seeds, uniform CO2 adjoint)
-        int32_t seg = seg_tile;
-        if (seg < 0) {
-            int32_t p = pf;
-            while (p + 1 < pl && i64 >= pc.piece_lo[p + 1]) p++;
-            seg = pc.piece_seg[p];
-        }
-#pragma unroll
-        for (int s = 0; s < VG_NPOOL - 1; s++) li[s] = elem(lin[s], i);
-        li[4] = CO2U ? A.co2[seg] : elem(lin[4], i);
-        if constexpr (NS != NS_TABLE) {
+            for (int k = 0; k < 6; k++) j[k] = o.jt[k] >= 0 ? (I)o.jt[k] : i;
+        } else {
             uint32_t jp[6];
-            packed_decode<NS == NS_REL>(A.pk, (uint32_t)i, W, jp);
+            packed_decode<NS == NS_REL>(A.pk, (uint32_t)i, o.W, jp);
 #pragma unroll
             for (int k = 0; k < 6; k++) j[k] = (I)jp[k];
         }
+#pragma unroll
+        for (int s = 0; s < VG_NPOOL; s++) {
+            if (!FROM_X && mobile<MOB>(s)) {
+#pragma unroll
+                for (int k = 0; k < 6; k++) zj[s][k] = elem(st[s], j[k]);
+            }
+            if (adj_differenced<MOB, DALL, CO2U>(s)) {
+#pragma unroll
+                for (int k = 0; k < 6; k++) lj[s][k] = elem(lin[s], j[k]);
+            }
+        }
+    };
+    // the reverse step at voxel i from its own words and neighbour values
+    auto work = [&](const AdjOwn<R, NS> &o, I i, const double (&sd)[VG_NPOOL], R lco2,
+                    const R (&zj)[VG_NPOOL][6], const R (&lj)[VG_NPOOL][6]) {
+        // forward state of this step and lambda^(k+1) of the voxel
+        R x[VG_NPOOL], li[VG_NPOOL];
+#pragma unroll
+        for (int s = 0; s < VG_NPOOL; s++) {
+            x[s] = o.x[s];
+            li[s] = o.li[s];
+        }
+        if (CO2U) li[4] = lco2;
         R w[6];
         uint32_t code = 0, own = 0;
         if (REG) {
-            code = elem(A.rcode, i);
+            code = o.code;
             own = code & 7u;
 #pragma unroll
             for (int k = 0; k < 6; k++) {
@@ -291,7 +355,7 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces 
                 R d[6];
 #pragma unroll
                 for (int k = 0; k < 6; k++) {
-                    const R diff = elem(st[s], j[k]) - xi;
+                    const R diff = zj[s][k] - xi;
                     d[k] = REG ? w[k] * diff : diff;
                 }
                 x[s] = xi + C.a[s] * (((d[0] + d[1]) + (d[2] + d[3])) + (d[4] + d[5]));
@@ -305,21 +369,18 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces 
         double own_c = 0.0, cross_c[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int s = 0; s < VG_NPOOL; s++) {
-            if ((!DALL && !mobile<MOB>(s)) || (CO2U && s == 4)) {
+            if (!adj_differenced<MOB, DALL, CO2U>(s)) {
                 // (a uniform CO2 adjoint has no neighbour differences: its dL/dD term is 0)
                 bar[s] = li[s];
                 continue;
             }
-            R lj[6];
-#pragma unroll
-            for (int k = 0; k < 6; k++) lj[k] = elem(lin[s], j[k]);
             R sum = R(0);
-            // the voxel's terms of dw/dc (half of each cross-octant edge
-            // to each side), summed in the field type
+            // the voxel's terms of dw/dc (half of each cross-octant edge to
+            // each side), summed in the field type
             R creg_own = R(0), creg_x[3] = {R(0), R(0), R(0)};
 #pragma unroll
             for (int k = 0; k < 6; k++) {
-                const R dl = lj[k] - li[s];
+                const R dl = lj[s][k] - li[s];
                 sum += w[k] * dl;
                 if (REG && mobile<MOB>(s)) {
                     if ((code >> (3 + k)) & 1u) {
@@ -343,19 +404,62 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces 
         if (REG) {
             // four region slots of this thread (the octant and its three
             // neighbours across the mid-planes); private, in a fixed order
-            const unsigned t = threadIdx.x;
-            creg[own][t] += own_c;
-            creg[own ^ 1u][t] += cross_c[0];
-            creg[own ^ 2u][t] += cross_c[1];
-            creg[own ^ 4u][t] += cross_c[2];
+            const unsigned tid = threadIdx.x;
+            creg[own][tid] += own_c;
+            creg[own ^ 1u][tid] += cross_c[0];
+            creg[own ^ 2u][tid] += cross_c[1];
+            creg[own ^ 4u][tid] += cross_c[2];
         }
         // adjoint of the transformation half
         transform_rev(C, x, bar, &g[5]);
-        const double *sd = A.seed + (int64_t)seg * VG_NPOOL;
 #pragma unroll
         for (int s = 0; s < VG_NPOOL - 1; s++) elem(lout[s], i) = (R)((double)bar[s] + sd[s]);
         if (!CO2U) elem(lout[4], i) = (R)((double)bar[4] + sd[4]);
+    };
+
+    // Full tiles run software-pipelined: a tile's own words (state,
+    // lambda^(k+1), neighbour words, region code) are loaded in the previous
+    // iteration, right after that iteration's neighbour gathers, so that a
+    // tile waits for one dependent round trip (its gathers) instead of two.
+    // No memory access in this loop is guarded (every lane of a full tile
+    // holds a voxel; the look-ahead past the last full tile reads voxel 0),
+    // so every path issues the same memory instructions.  A ragged last tile
+    // is the last tile of its block (each block's tiles ascend) and runs
+    // after the loop.
+    static_assert(kVPT == 1, "one voxel per thread and tile");
+    const int64_t nfull = n / kTile;
+    auto own_index = [&](int64_t tt) -> I { return (I)(tt < nfull ? tt * kTile + threadIdx.x : 0); };
+    int64_t t = xcd_stride_tile(blockIdx.x, gridDim.x, 0, A.ntiles);
+    AdjOwn<R, NS> cur;
+    if (t < nfull) adj_load_own<R, MOB, REG, NS, DALL, CO2U>(A, st, lin, own_index(t), cur);
+    for (int64_t it = 1; t < nfull; it++) {
+        const int64_t tn = xcd_stride_tile(blockIdx.x, gridDim.x, it, A.ntiles);
+        const int64_t i64 = t * kTile + threadIdx.x;
+        const I i = (I)i64;
+        double sd[VG_NPOOL];
+        R lco2;
+        volume_terms(t, i64, sd, lco2);
+        R zj[VG_NPOOL][6], lj[VG_NPOOL][6];
+        gather(cur, i, zj, lj);
+        AdjOwn<R, NS> nxt;
+        adj_load_own<R, MOB, REG, NS, DALL, CO2U>(A, st, lin, own_index(tn), nxt);
+        work(cur, i, sd, lco2, zj, lj);
+        cur = nxt;
+        t = tn;
     }
+    if (t < A.ntiles) {
+        // the ragged last tile
+        const int64_t i64 = t * kTile + threadIdx.x;
+        double sd[VG_NPOOL];
+        R lco2;
+        volume_terms(t, i64, sd, lco2);
+        if (i64 < n) {
+            const I i = (I)i64;
+            adj_load_own<R, MOB, REG, NS, DALL, CO2U>(A, st, lin, i, cur);
+            R zj[VG_NPOOL][6], lj[VG_NPOOL][6];
+            gather(cur, i, zj, lj);
+            work(cur, i, sd, lco2, zj, lj);
+        }
     }
     if (REG) {
 #pragma unroll
