@@ -33,24 +33,23 @@ namespace {
 
 constexpr int kG = VG_NGRAD;
 
+// The clamps of both directions are written as selects between values that
+// are all computed (no branches): the selected values are the ones the
+// branches would produce, so the results are the same, and a wave does not
+// split on the voxels' clamp cases.
 template <typename R>
 __device__ __forceinline__ void transform_fwd(const Coef<R> &C, R &m1, R &m2, R &m3, R &m4, R &m5) {
     R uptake = C.v_dom * m2 / (C.k_dom + m2) * m1 * C.dt;
-    if (uptake > m2) uptake = m2;
-    R resp = C.rho * m1 * C.dt;
-    R morta = C.mu * m1 * C.dt;
-    if (resp + morta > m1) {
-        if (morta > m1) {
-            morta = m1;
-            resp = R(0);
-        } else {
-            resp = m1 - morta;
-        }
-    }
+    uptake = uptake > m2 ? m2 : uptake;
+    const R resp0 = C.rho * m1 * C.dt, morta0 = C.mu * m1 * C.dt;
+    const bool over = resp0 + morta0 > m1;   // respiration and mortality would take more than there is
+    const bool all = over && morta0 > m1;    // mortality alone would
+    const R morta = all ? m1 : morta0;
+    const R resp = all ? R(0) : (over ? m1 - morta0 : resp0);
     R turn_p4 = C.v_p4 * m4 * C.dt;
-    if (turn_p4 > m4) turn_p4 = m4;
+    turn_p4 = turn_p4 > m4 ? m4 : turn_p4;
     R turn_som = C.v_som * m3 * C.dt;
-    if (turn_som > m3) turn_som = m3;
+    turn_som = turn_som > m3 ? m3 : turn_som;
     const R n1 = m1 + (uptake - morta - resp);
     R n2, n3, n4;
     if (C.route == 0) {
@@ -65,11 +64,11 @@ __device__ __forceinline__ void transform_fwd(const Coef<R> &C, R &m1, R &m2, R 
     m1 = n1; m2 = n2; m3 = n3; m4 = n4; m5 = m5 + resp;
 }
 
-// Reverse of the transformation at pre-step masses x (branches re-taken from
-// x).  In: ybar = adjoint of T's outputs.  Out: adjoint of its inputs.  The
-// rate derivatives accumulate into g[0..6] = v_DOM, K_DOM, rho, mu, beta,
+// Reverse of the transformation at pre-step masses x (clamp cases re-taken
+// from x).  In: ybar = adjoint of T's outputs.  Out: adjoint of its inputs.
+// The rate derivatives accumulate into g[0..6] = v_DOM, K_DOM, rho, mu, beta,
 // v_SOM, v_P4 (FP64 sums of the voxel's terms, each formed in the field
-// type).
+// type; a clamped case adds +0).
 template <typename R>
 __device__ __forceinline__ void transform_rev(const Coef<R> &C, const R (&x)[VG_NPOOL], R (&bar)[VG_NPOOL],
                                               double *g) {
@@ -79,12 +78,10 @@ __device__ __forceinline__ void transform_rev(const Coef<R> &C, const R (&x)[VG_
     const R up_raw = C.v_dom * m2 / den * m1 * dt;
     const bool up_clamp = up_raw > m2;
     const R resp0 = C.rho * m1 * dt, morta0 = C.mu * m1 * dt;
-    int rm = 0;   // 0 free, 1 all biomass dies, 2 respiration takes the rest
-    R morta = morta0;
-    if (resp0 + morta0 > m1) {
-        if (morta0 > m1) { rm = 1; morta = m1; }
-        else rm = 2;
-    }
+    // 0 free, 1 all biomass dies, 2 respiration takes the rest
+    const bool over = resp0 + morta0 > m1;
+    const bool rm1 = over && morta0 > m1, rm2 = over && !rm1;
+    const R morta = rm1 ? m1 : morta0;
     const bool p4_clamp = C.v_p4 * m4 * dt > m4;
     const bool som_clamp = C.v_som * m3 * dt > m3;
 
@@ -102,34 +99,32 @@ __device__ __forceinline__ void transform_rev(const Coef<R> &C, const R (&x)[VG_
     const R respb = -y1 + y5;
     const R p4b = y2 - y4;
     const R somb = y2 - y3;
-    if (up_clamp) {
-        b2 += upb;
-    } else {
-        // one division: d(uptake)/d(m2) = v m1 dt K / den^2 and
-        // d(uptake)/dK = -v m1 dt m2 / den^2 from 1/den
+    // uptake: one division; d(uptake)/d(m2) = v m1 dt K / den^2 and
+    // d(uptake)/dK = -v m1 dt m2 / den^2 from 1/den
+    {
         const R inv = R(1) / den;
         const R gm = m2 * inv;
         const R vmd = C.v_dom * m1 * dt * inv;
-        b1 += upb * C.v_dom * gm * dt;
-        b2 += upb * vmd * (C.k_dom * inv);
-        g[0] += (double)(upb * (gm * m1 * dt));
-        g[1] -= (double)(upb * (vmd * gm));
+        const R t1 = upb * C.v_dom * gm * dt;
+        const R t2 = upb * vmd * (C.k_dom * inv);
+        b1 += up_clamp ? R(0) : t1;
+        b2 += up_clamp ? upb : t2;
+        g[0] += up_clamp ? 0.0 : (double)(upb * (gm * m1 * dt));
+        g[1] -= up_clamp ? 0.0 : (double)(upb * (vmd * gm));
     }
-    if (rm == 0) {
-        b1 += respb * C.rho * dt + mortb * C.mu * dt;
-        g[2] += (double)(respb * (m1 * dt));
-        g[3] += (double)(mortb * (m1 * dt));
-    } else if (rm == 1) {
-        b1 += mortb;
-    } else {
+    {
         const R mt = mortb - respb;
-        b1 += respb + mt * C.mu * dt;
-        g[3] += (double)(mt * (m1 * dt));
+        const R f0 = respb * C.rho * dt + mortb * C.mu * dt;
+        const R f2 = respb + mt * C.mu * dt;
+        b1 += rm1 ? mortb : (rm2 ? f2 : f0);
+        const bool free = !over;
+        g[2] += free ? (double)(respb * (m1 * dt)) : 0.0;
+        g[3] += rm1 ? 0.0 : (double)((rm2 ? mt : mortb) * (m1 * dt));
     }
-    if (som_clamp) b3 += somb;
-    else { b3 += somb * C.v_som * dt; g[5] += (double)(somb * (m3 * dt)); }
-    if (p4_clamp) b4 += p4b;
-    else { b4 += p4b * C.v_p4 * dt; g[6] += (double)(p4b * (m4 * dt)); }
+    b3 += som_clamp ? somb : somb * C.v_som * dt;
+    g[5] += som_clamp ? 0.0 : (double)(somb * (m3 * dt));
+    b4 += p4_clamp ? p4b : p4b * C.v_p4 * dt;
+    g[6] += p4_clamp ? 0.0 : (double)(p4b * (m4 * dt));
     bar[0] = b1; bar[1] = b2; bar[2] = b3; bar[3] = b4; bar[4] = b5;
 }
 
