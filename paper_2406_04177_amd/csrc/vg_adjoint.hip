@@ -117,8 +117,8 @@ __device__ __forceinline__ void transform_rev(const Coef<R> &C, const R (&x)[VG_
         const R f0 = respb * C.rho * dt + mortb * C.mu * dt;
         const R f2 = respb + mt * C.mu * dt;
         b1 += rm1 ? mortb : (rm2 ? f2 : f0);
-        const bool free = !over;
-        g[2] += free ? (double)(respb * (m1 * dt)) : 0.0;
+        const bool neither = !over;   // neither respiration nor mortality clamped
+        g[2] += neither ? (double)(respb * (m1 * dt)) : 0.0;
         g[3] += rm1 ? 0.0 : (double)((rm2 ? mt : mortb) * (m1 * dt));
     }
     b3 += som_clamp ? somb : somb * C.v_som * dt;
