@@ -479,8 +479,21 @@ int vg_seed_lambda(vg_sim *h, const double *seed_d, void *lambda_d, int zero, vo
  * the pools that do not diffuse in this handle (every pool but DOM unless
  * mobile_all) and grad_d[s] is set to NaN for them; this saves the six
  * neighbour gathers of each of their adjoints per voxel and step.  The other
- * gradients and lambda are unchanged.  Default: every dL/dD_s computed. */
+ * gradients and lambda are unchanged.  Default: every dL/dD_s computed.
+ * VG_ADJ_TAPE_DOM (ignored with mobile_all): vg_record and vg_step_record
+ * keep, for every recorded state states[j] with j >= 1, the DOM after the
+ * diffusion half of the step that follows it (the x^(k0+j) of the paper's
+ * order) in the CO2 row of states[j], in place of CO2 (4 more bytes written
+ * per voxel and recorded step); vg_adjoint then reads each step's x^k
+ * directly instead of gathering the stored DOM at six neighbours to form it
+ * (Sec. II.B.3a Scheme 1 applied in the forward, not again in the reverse).
+ * lambda and the gradient are bit-identical to the recording without it.
+ * The flag must be the same for the recording and its vg_adjoint; such
+ * states hold no CO2, so vg_adjoint returns VG_EINVAL for them when dL/dD_CO2
+ * is asked for (no VG_ADJ_SKIP_STATIC_D) with a CO2 adjoint that varies
+ * within a volume. */
 #define VG_ADJ_SKIP_STATIC_D 1u
+#define VG_ADJ_TAPE_DOM      2u
 int vg_set_adjoint_options(vg_sim *h, unsigned flags);
 
 #ifdef __cplusplus

@@ -23,7 +23,7 @@ VG_PRECOND_JACOBI, VG_PRECOND_MG = 0, 1
 VG_MG_MAX_LEVELS = 12
 VG_NPOOL, VG_NREG, VG_NGRAD = 5, 8, 20
 VG_KERNEL_AUTO, VG_KERNEL_TABLE, VG_KERNEL_RANK, VG_KERNEL_OFFSET, VG_KERNEL_RELATIVE, VG_KERNEL_BAND = 0, 1, 2, 3, 4, 5
-VG_ADJ_SKIP_STATIC_D = 1
+VG_ADJ_SKIP_STATIC_D, VG_ADJ_TAPE_DOM = 1, 2
 VG_PNGM_NOALLOC_MAX_Q = 65536
 VG_LAUNCH_GRAPHS_AUTO, VG_LAUNCH_GRAPHS_ON, VG_LAUNCH_GRAPHS_OFF = 0, 1, 2
 

@@ -15,7 +15,11 @@ Segments whose recorded states fit ``tape_bytes`` (default: half the free
 device memory at the forward; 0 turns it off) are recorded by the forward
 itself (``vg_step_record``: the same kernels, bit-identical states and
 totals), so the backward sweeps them without running them again; the last
-segments are the ones kept, and each is freed once swept.
+segments are the ones kept, and each is freed once swept.  When only DOM
+diffuses, the recordings keep each step's diffused DOM (the adjoint option
+``tape_dom``: the totals' CO2 adjoint is uniform over each volume, which it
+needs), so the reverse steps need not diffuse again; the gradient is
+bit-identical either way.
 """
 from __future__ import annotations
 
@@ -47,6 +51,18 @@ def params_of(theta, base: ModelParams) -> tuple:
 class _TotalsFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, theta, x0, sim, nsteps, dt, K, tape_bytes):
+        # recordings and their sweeps take the same option; the caller's is
+        # restored afterwards
+        ctx.tape_dom = not sim.mobile_all
+        prev_tape_dom = sim.adjoint_options["tape_dom"]
+        sim.set_adjoint_options(tape_dom=ctx.tape_dom)
+        try:
+            return _TotalsFn._forward(ctx, theta, x0, sim, nsteps, dt, K, tape_bytes)
+        finally:
+            sim.set_adjoint_options(tape_dom=prev_tape_dom)
+
+    @staticmethod
+    def _forward(ctx, theta, x0, sim, nsteps, dt, K, tape_bytes):
         p, c = params_of(theta, sim.params)
         sim.set_params(p)
         sim.set_regions(c)
@@ -86,6 +102,16 @@ class _TotalsFn(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, gout):
+        sim = ctx.sim
+        prev_tape_dom = sim.adjoint_options["tape_dom"]
+        sim.set_adjoint_options(tape_dom=ctx.tape_dom)
+        try:
+            return _TotalsFn._backward(ctx, gout)
+        finally:
+            sim.set_adjoint_options(tape_dom=prev_tape_dom)
+
+    @staticmethod
+    def _backward(ctx, gout):
         sim, dt = ctx.sim, ctx.dt
         # another forward on the same simulation may have changed its
         # parameters since: re-record at this forward's, restore afterwards

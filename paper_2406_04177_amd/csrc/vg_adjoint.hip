@@ -134,6 +134,7 @@ struct AdjBufs {
     const uint16_t *rcode = nullptr;
     PackedNbr pk;                // packed neighbour sources (when built)
     const R *st = nullptr;       // stored state of this step, pool s at st + s*n
+    int dom_row = 1;             // the row read as DOM (4: the diffused DOM kept in the CO2 row)
     const R *lin = nullptr;      // lambda^(k+1)
     R *lout = nullptr;           // lambda^k
     const double *seed = nullptr;   // [nseg][5] for this step
@@ -265,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces 
     R *lout[VG_NPOOL];
 #pragma unroll
     for (int s = 0; s < VG_NPOOL; s++) {
-        st[s] = A.st + (int64_t)s * n;
+        st[s] = A.st + (int64_t)(s == 1 ? A.dom_row : s) * n;
         lin[s] = A.lin + (int64_t)s * n;
         lout[s] = A.lout + (int64_t)s * n;
     }
@@ -592,6 +593,16 @@ int launch_adj_step(vg_sim *h, bool from_x, const AdjBufs<R> &A, const Coef<R> &
     return launch_adj_ns<R, MOB, REG, NS_TABLE>(h, from_x, A, C, s);
 }
 
+}  // namespace
+
+// The recording keeps each step's diffused DOM (VG_ADJ_TAPE_DOM; only DOM
+// diffusing).
+bool tape_keeps_dom(const vg_sim *h) {
+    return (h->adj_flags & VG_ADJ_TAPE_DOM) && !h->mobile_all;
+}
+
+namespace {
+
 template <typename R>
 int adjoint_sweep(vg_sim *h, int64_t nsteps, double dt, const void *states, const double *seeds, void *lambda,
                   double *grad, hipStream_t s) {
@@ -629,6 +640,15 @@ int adjoint_sweep(vg_sim *h, int64_t nsteps, double dt, const void *states, cons
             if ((rc = launch_status("k_co2_init"))) return rc;
         }
     }
+    // recorded with the diffused DOM kept (see record): every step reads its
+    // x^k directly; those states hold no CO2, which only dL/dD_CO2 with a
+    // CO2 adjoint that varies within a volume would need
+    const bool xd = tape_keeps_dom(h);
+    if (xd && !co2u && !(h->adj_flags & VG_ADJ_SKIP_STATIC_D)) {
+        set_error("states recorded with VG_ADJ_TAPE_DOM hold no CO2: dL/dD_CO2 needs a CO2 adjoint uniform over "
+                  "each volume, or VG_ADJ_SKIP_STATIC_D");
+        return VG_EINVAL;
+    }
     for (int64_t jstep = nsteps - 1; jstep >= 0; jstep--) {
         AdjBufs<R> A;
         A.nbr = h->nbr;
@@ -644,7 +664,8 @@ int adjoint_sweep(vg_sim *h, int64_t nsteps, double dt, const void *states, cons
         A.nseg = h->nseg;
         A.n = n;
         A.ntiles = h->ntiles;
-        const bool fx = jstep == 0;
+        const bool fx = jstep == 0 || xd;
+        A.dom_row = xd && jstep > 0 ? 4 : 1;
         if (h->mobile_all) rc = reg ? launch_adj_step<R, 2, true>(h, fx, A, C, s) : launch_adj_step<R, 2, false>(h, fx, A, C, s);
         else rc = reg ? launch_adj_step<R, 1, true>(h, fx, A, C, s) : launch_adj_step<R, 1, false>(h, fx, A, C, s);
         if (rc) return rc;
@@ -677,6 +698,7 @@ int record(vg_sim *h, int64_t nsteps, double dt, void *states, hipStream_t s) {
     // states[0] = x^k0 (the bound fields)
     if ((rc = hip_status(hipMemcpyAsync(st, h->fields, sizeof(R) * VG_NPOOL * (size_t)n, hipMemcpyDeviceToDevice, s),
                          "record copy"))) return rc;
+    const bool xd = tape_keeps_dom(h);
     for (int64_t jstep = 1; jstep < nsteps; jstep++) {
         const void *src[VG_NPOOL];
         void *dst[VG_NPOOL];
@@ -684,9 +706,24 @@ int record(vg_sim *h, int64_t nsteps, double dt, void *states, hipStream_t s) {
             src[p] = st + ((jstep - 1) * VG_NPOOL + p) * n;
             dst[p] = st + (jstep * VG_NPOOL + p) * n;
         }
-        // states[1] = T(x^k0); states[j] = T(D(states[j-1])) afterwards
-        rc = launch_pass_bufs(h, jstep == 1 ? MODE_T : MODE_DT, TOT_NONE, dt, src, dst, s);
+        // states[1] = T(x^k0); states[j] = T(D(states[j-1])) afterwards; with
+        // the diffused DOM kept, D(states[j-1])'s DOM goes into the CO2 row
+        // of states[j-1] (j >= 2: read there before it is overwritten)
+        void *xdom = xd && jstep >= 2 ? st + ((jstep - 1) * VG_NPOOL + 4) * n : nullptr;
+        rc = launch_pass_bufs(h, jstep == 1 ? MODE_T : MODE_DT, TOT_NONE, dt, src, dst, s, xdom);
         if (rc) return rc;
+    }
+    if (xd && nsteps >= 2) {
+        // the last state's diffused DOM: a diffusion pass whose DOM output is
+        // that state's CO2 row
+        const void *src[VG_NPOOL];
+        void *dst[VG_NPOOL];
+        for (int p = 0; p < VG_NPOOL; p++) {
+            src[p] = st + ((nsteps - 1) * VG_NPOOL + p) * n;
+            dst[p] = (void *)src[p];
+        }
+        dst[1] = st + ((nsteps - 1) * VG_NPOOL + 4) * n;
+        if ((rc = launch_pass_bufs(h, MODE_D, TOT_NONE, dt, src, dst, s))) return rc;
     }
     return VG_OK;
 }

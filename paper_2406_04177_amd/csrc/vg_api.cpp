@@ -435,7 +435,7 @@ extern "C" int vg_set_kernel(vg_sim *h, int variant) {
 
 extern "C" int vg_set_adjoint_options(vg_sim *h, unsigned flags) {
     if (!h) { set_error("handle is NULL"); return VG_EINVAL; }
-    if (flags & ~VG_ADJ_SKIP_STATIC_D) { set_error("unknown adjoint options"); return VG_EINVAL; }
+    if (flags & ~(VG_ADJ_SKIP_STATIC_D | VG_ADJ_TAPE_DOM)) { set_error("unknown adjoint options"); return VG_EINVAL; }
     h->adj_flags = flags;
     return VG_OK;
 }
@@ -786,6 +786,9 @@ extern "C" int vg_step_record(vg_sim *h, int64_t nsteps, double dt, void *states
         return rc2;
     };
     auto logged = [&]() -> int { return ++h->part_slot < h->tot_batch ? VG_OK : flush(); };
+    // with the diffused DOM kept, each fused pass writes D(states[j-1])'s DOM
+    // into the CO2 row of states[j-1] (as vg_record does)
+    const bool xd = tape_keeps_dom(h);
     for (int64_t j = 1; j < nsteps; j++) {
         const void *src[VG_NPOOL];
         void *dst[VG_NPOOL];
@@ -793,7 +796,8 @@ extern "C" int vg_step_record(vg_sim *h, int64_t nsteps, double dt, void *states
             src[p] = state(j - 1, p);
             dst[p] = state(j, p);
         }
-        if ((rc = launch_pass_bufs(h, j == 1 ? MODE_T : MODE_DT, j == 1 ? TOT_NONE : TOT_MID, dt, src, dst, s)))
+        if ((rc = launch_pass_bufs(h, j == 1 ? MODE_T : MODE_DT, j == 1 ? TOT_NONE : TOT_MID, dt, src, dst, s,
+                                   xd && j >= 2 ? state(j - 1, 4) : nullptr)))
             return rc;
         if (j >= 2 && (rc = logged())) return rc;
     }
@@ -807,7 +811,9 @@ extern "C" int vg_step_record(vg_sim *h, int64_t nsteps, double dt, void *states
             dst[p] = h->fields + (size_t)p * n * esz;
         }
         const bool one = nsteps == 1;
-        if ((rc = launch_pass_bufs(h, one ? MODE_T : MODE_DT, one ? TOT_NONE : TOT_MID, dt, src, dst, s))) return rc;
+        if ((rc = launch_pass_bufs(h, one ? MODE_T : MODE_DT, one ? TOT_NONE : TOT_MID, dt, src, dst, s,
+                                   xd && !one ? state(nsteps - 1, 4) : nullptr)))
+            return rc;
         if (!one && (rc = logged())) return rc;
     }
     if ((rc = launch_pass(h, MODE_D, TOT_OUT, dt, s))) return rc;

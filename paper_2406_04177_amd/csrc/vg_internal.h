@@ -586,7 +586,7 @@ enum { TOT_NONE = 0, TOT_IN = 1, TOT_MID = 2, TOT_OUT = 3 };
 int launch_pass(vg_sim *h, int mode, int tot, double dt, hipStream_t s);
 int launch_pass2(vg_sim *h, int mode, int tot, double dt_t, double dt_d, hipStream_t s);
 int launch_pass_bufs(vg_sim *h, int mode, int tot, double dt, const void *const src[VG_NPOOL],
-                     void *const dst[VG_NPOOL], hipStream_t s);
+                     void *const dst[VG_NPOOL], hipStream_t s, void *xdom = nullptr);
 // Reduces the partials of slots 0 .. rows-1 into rows consecutive totals
 // rows out_rows[r][nseg][6].
 int launch_totals_finalize(vg_sim *h, double *out_rows, int rows, hipStream_t s);
@@ -598,6 +598,7 @@ bool use_offsets(const vg_sim *h);
 bool use_relative(const vg_sim *h);
 bool band_geometry(const vg_sim *h);   // the graph and features allow the band kernel
 bool use_band(const vg_sim *h);        // the next pass pairs run on the band kernel
+bool tape_keeps_dom(const vg_sim *h);  // recordings keep each state's diffused DOM in its CO2 row
 int build_band(vg_sim *h, hipStream_t s);
 int launch_band_quad(vg_sim *h, double dt, hipStream_t s);
 PackedNbr packed_of(const vg_sim *h);

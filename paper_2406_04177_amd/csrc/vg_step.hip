@@ -160,6 +160,10 @@ struct StepBufs {
     PackedNbr pk;                       // packed neighbour sources (when built)
     const R *src[VG_NPOOL] = {};
     R *dst[VG_NPOOL] = {};
+    // when set (a recording pass of the adjoint that keeps the diffused
+    // DOM): a fused pass also writes each voxel's DOM after the diffusion
+    // half, before the transformation, here
+    R *xdom = nullptr;
     int64_t n = 0;
 };
 
@@ -281,6 +285,11 @@ __device__ __forceinline__ void finish(const StepBufs<R> &B, const Coef<R> &C, c
 #pragma unroll
             for (int v = 0; v < kVPT; v++) diffuse_voxel<R, MOB, REG>(B, C, ic[v], j[v], w[v], x[v]);
         }
+    }
+    if (MODE == MODE_DT && MOB == 1 && B.xdom) {
+#pragma unroll
+        for (int v = 0; v < kVPT; v++)
+            if (act[v]) B.xdom[ic[v]] = x[v][1];
     }
 #pragma unroll
     for (int v = 0; v < kVPT; v++) {
@@ -447,6 +456,11 @@ __global__ __launch_bounds__(kBlock) void k_step_off(StepBufs<R> B, Coef<R> C, P
             const R sum = ((d[0] + d[1]) + (d[2] + d[3])) + (d[4] + d[5]);
             x[v][s] = xi + C.a[s] * sum;
         }
+    if (MODE == MODE_DT && MOB == 1 && B.xdom) {
+#pragma unroll
+        for (int v = 0; v < V; v++)
+            if (act[v]) at(B.xdom, ic[v]) = x[v][1];
+    }
 #pragma unroll
     for (int v = 0; v < V; v++) {
         if (TOT == TOT_MID && act[v]) {
@@ -1511,17 +1525,21 @@ int launch_pass(vg_sim *h, int mode, int tot, double dt, hipStream_t s) {
 }
 
 // A pass between explicit buffers (pool s read from src[s], written to
-// dst[s]); used by the adjoint's forward recording.
+// dst[s]); used by the adjoint's forward recording.  xdom: see StepBufs
+// (fused passes, only DOM diffusing; it may be src[4], read before it is
+// written by the same thread).
 int launch_pass_bufs(vg_sim *h, int mode, int tot, double dt, const void *const src[VG_NPOOL],
-                     void *const dst[VG_NPOOL], hipStream_t s) {
+                     void *const dst[VG_NPOOL], hipStream_t s, void *xdom) {
     if (h->n == 0) return VG_OK;
     if (h->prec == VG_F64) {
         StepBufs<double> B = graph_bufs<double>(h);
         for (int p = 0; p < VG_NPOOL; p++) { B.src[p] = (const double *)src[p]; B.dst[p] = (double *)dst[p]; }
+        B.xdom = (double *)xdom;
         return dispatch_bufs<double>(h, mode, tot, dt, dt, B, s);
     }
     StepBufs<float> B = graph_bufs<float>(h);
     for (int p = 0; p < VG_NPOOL; p++) { B.src[p] = (const float *)src[p]; B.dst[p] = (float *)dst[p]; }
+    B.xdom = (float *)xdom;
     return dispatch_bufs<float>(h, mode, tot, dt, dt, B, s);
 }
 

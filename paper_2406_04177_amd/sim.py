@@ -48,6 +48,8 @@ class Simulation:
         self.stream = stream
         if mobile_all is None:
             mobile_all = any(float(d) != 0.0 for s, d in enumerate(params.D) if s != 1)
+        self.mobile_all = bool(mobile_all)
+        self._adj_skip = self._adj_tape_dom = False
         features = ((_lib.VG_FEAT_CG if implicit else 0) | (_lib.VG_FEAT_ADJ if adjoint else 0)
                     | (_lib.VG_FEAT_BAND if band else 0) | (_lib.VG_FEAT_MG if multigrid else 0))
         # segments of the totals (and of the adjoint's seeds): the volumes, or
@@ -237,11 +239,24 @@ class Simulation:
         _lib.check(self.L.vg_adjoint(self.h, int(nsteps), float(dt), states.data_ptr(), seeds.data_ptr(),
                                      lam.data_ptr(), grad.data_ptr(), self._sp()), "vg_adjoint")
 
-    def set_adjoint_options(self, skip_static_d: bool = False):
+    def set_adjoint_options(self, skip_static_d=None, tape_dom=None):
         """skip_static_d: do not compute dL/dD_s for the pools that do not
-        diffuse (their gradient entries come back NaN); faster reverse sweep."""
-        _lib.check(self.L.vg_set_adjoint_options(self.h, _lib.VG_ADJ_SKIP_STATIC_D if skip_static_d else 0),
-                   "vg_set_adjoint_options")
+        diffuse (their gradient entries come back NaN); faster reverse sweep.
+        tape_dom: recordings keep each state's diffused DOM in its CO2 row
+        and the reverse sweep reads it there (bit-identical results; such
+        recorded states hold no CO2).  An option given as None keeps its
+        current value."""
+        if skip_static_d is not None:
+            self._adj_skip = bool(skip_static_d)
+        if tape_dom is not None:
+            self._adj_tape_dom = bool(tape_dom)
+        flags = ((_lib.VG_ADJ_SKIP_STATIC_D if self._adj_skip else 0)
+                 | (_lib.VG_ADJ_TAPE_DOM if self._adj_tape_dom else 0))
+        _lib.check(self.L.vg_set_adjoint_options(self.h, flags), "vg_set_adjoint_options")
+
+    @property
+    def adjoint_options(self) -> dict:
+        return {"skip_static_d": self._adj_skip, "tape_dom": self._adj_tape_dom}
 
     def seed_lambda(self, seed: torch.Tensor, lam: torch.Tensor, zero: bool):
         _lib.check(self.L.vg_seed_lambda(self.h, seed.data_ptr(), lam.data_ptr(), 1 if zero else 0, self._sp()),
