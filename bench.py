@@ -69,12 +69,12 @@ KERNEL_SOURCES = ("paper_2406_04177_amd/csrc/vg_step.hip", "paper_2406_04177_amd
                   "paper_2406_04177_amd/build.py")
 MEASURED_TRAFFIC = {
     # (kernel, size): (bytes per launch, sha256 of KERNEL_SOURCES); from
-    # profiles/k_band2_f32_512cube.md: FETCH_SIZE 592952.6 KiB x 2 +
-    # WRITE_SIZE 412403.7 KiB x 1 per launch (two fused passes), and
-    # profiles/k_step_c_f32c_512cube.md: FETCH_SIZE 479812.9 KiB x 2 +
-    # WRITE_SIZE 614041.8 KiB per launch (one pass, compensated FP32)
-    ("band", 512): (592952.6 * 1024 * 2 + 412403.7 * 1024, "e632f6749dceb549be6f2f9662342610d6a8cce5254b5921a0acbfe5252fee78"),
-    ("relative_f32c", 512): (479812.9 * 1024 * 2 + 614041.8 * 1024, "e632f6749dceb549be6f2f9662342610d6a8cce5254b5921a0acbfe5252fee78"),
+    # profiles/k_band2_f32_512cube.md: FETCH_SIZE 592738.6 KiB x 2 +
+    # WRITE_SIZE 412403.8 KiB x 1 per launch (two fused passes), and
+    # profiles/k_step_c_f32c_512cube.md: FETCH_SIZE 479812.7 KiB x 2 +
+    # WRITE_SIZE 614084.6 KiB per launch (one pass, compensated FP32)
+    ("band", 512): (592738.6 * 1024 * 2 + 412403.8 * 1024, "cf83a8f561ad50763b3988f36c3398c10d920eaaa4f68229a0e4a581e963b794"),
+    ("relative_f32c", 512): (479812.7 * 1024 * 2 + 614084.6 * 1024, "cf83a8f561ad50763b3988f36c3398c10d920eaaa4f68229a0e4a581e963b794"),
 }
 
 
