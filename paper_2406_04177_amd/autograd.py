@@ -11,8 +11,9 @@ values) and of the initial fields ``x0``.  The backward pass is the library's
 hand-written discrete adjoint (``vg_adjoint``) with checkpointed recomputation:
 the forward keeps the state at the start of every ``checkpoint_every`` steps;
 the backward re-records each segment (``vg_record``) and sweeps it in reverse.
-Segments whose recorded states fit ``tape_bytes`` (default: half the free
-device memory at the forward; 0 turns it off) are recorded by the forward
+Segments whose recorded states fit ``tape_bytes`` (default:
+``default_tape_bytes`` of the free device memory at the forward; 0 turns it
+off) are recorded by the forward
 itself (``vg_step_record``: the same kernels, bit-identical states and
 totals), so the backward sweeps them without running them again; the last
 segments are the ones kept, and each is freed once swept.  When only DOM
@@ -48,6 +49,18 @@ def params_of(theta, base: ModelParams) -> tuple:
     return p, t[12:20]
 
 
+def default_tape_bytes(free: int, seg_bytes: int, total_bytes: int, field_bytes: int, nseg: int) -> int:
+    """The forward's recording budget: every segment when all of them fit
+    with a tenth of the free memory and the backward's two adjoint field sets
+    to spare; else what fits beside those, the checkpoints of the segments
+    not recorded (at most nseg field sets) and the one segment's states that
+    the backward records again."""
+    spare = free // 10 + 2 * field_bytes
+    if total_bytes + spare <= free:
+        return total_bytes
+    return max(0, free - spare - seg_bytes - nseg * field_bytes)
+
+
 class _TotalsFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, theta, x0, sim, nsteps, dt, K, tape_bytes):
@@ -77,7 +90,8 @@ class _TotalsFn(torch.autograd.Function):
         # the last segments whose states fit the budget are recorded on the way
         per_step = 5 * sim.graph.n * torch.empty((), dtype=sim.dtype).element_size()
         if tape_bytes is None:
-            tape_bytes = torch.cuda.mem_get_info(dev)[0] // 2 if dev.type == "cuda" else 0
+            tape_bytes = 0 if dev.type != "cuda" else default_tape_bytes(
+                torch.cuda.mem_get_info(dev)[0], min(K, nsteps) * per_step, nsteps * per_step, per_step, len(segs))
         taped, budget = set(), int(tape_bytes) if keep else 0
         for k0, k in reversed(segs):
             if k * per_step > budget:

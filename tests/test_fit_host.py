@@ -50,3 +50,16 @@ def test_gauss_newton_iteration_on_an_exponential_fit():
         d, _ = lstsq_step(torch.as_tensor(J), torch.as_tensor(f - y))
         la, lb = la + float(d[0]), lb + float(d[1])
     assert abs(np.exp(la) / a - 1) < 1e-12 and abs(np.exp(lb) / b - 1) < 1e-12
+
+
+def test_default_tape_budget():
+    """Every segment when all fit with a tenth of the free memory and two
+    adjoint field sets to spare; else room is left for the checkpoints and
+    the one segment recorded again in the backward; never negative."""
+    from paper_2406_04177_amd.autograd import default_tape_bytes
+    G = 1 << 30
+    # 20 segments of 10 GiB, field set 1 GiB
+    assert default_tape_bytes(300 * G, 10 * G, 200 * G, G, 20) == 200 * G
+    # 250 GiB free: 25 + 2 spare, 10 for the re-recorded segment, 40 checkpoints
+    assert default_tape_bytes(250 * G, 10 * G, 400 * G, G, 40) == 250 * G - 27 * G - 10 * G - 40 * G
+    assert default_tape_bytes(20 * G, 10 * G, 400 * G, G, 40) == 0
