@@ -90,8 +90,11 @@ class _TotalsFn(torch.autograd.Function):
         # the last segments whose states fit the budget are recorded on the way
         per_step = 5 * sim.graph.n * torch.empty((), dtype=sim.dtype).element_size()
         if tape_bytes is None:
-            tape_bytes = 0 if dev.type != "cuda" else default_tape_bytes(
-                torch.cuda.mem_get_info(dev)[0], min(K, nsteps) * per_step, nsteps * per_step, per_step, len(segs))
+            # free device memory, and what torch's allocator holds unused
+            # (e.g. the states buffer of an earlier backward)
+            free = 0 if dev.type != "cuda" else (torch.cuda.mem_get_info(dev)[0] + torch.cuda.memory_reserved(dev)
+                                                 - torch.cuda.memory_allocated(dev))
+            tape_bytes = default_tape_bytes(free, min(K, nsteps) * per_step, nsteps * per_step, per_step, len(segs))
         taped, budget = set(), int(tape_bytes) if keep else 0
         for k0, k in reversed(segs):
             if k * per_step > budget:
