@@ -192,3 +192,35 @@ def test_unknown_option_rejected():
     for flags in range(4):
         assert sim.L.vg_set_adjoint_options(sim.h, flags) == _lib.VG_OK
     assert sim.L.vg_set_adjoint_options(sim.h, 4) == _lib.VG_EINVAL
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+@pytest.mark.parametrize("brick", [0, 4], ids=["raster", "brick4"])
+def test_rank_index_recording_bit_identical(brick, precision):
+    """A single volume recorded through the rank-index pass (raster and brick
+    order, region weights): the same bit-identity with and without the kept
+    DOM, for vg_record and vg_step_record."""
+    from paper_2406_04177_amd.graph import Graph
+    mask = inputs.synthetic_volume((16, 16, 16), porosity=0.22, seed=81)
+    spec = inputs.init_random_all(mask, 81)
+    g = Graph.from_masks(mask, brick=brick, regions=True)
+    dtype = torch.float64 if precision == "f64" else torch.float32
+    x0 = g.fields_from_specs(spec, dtype)
+    dt = inputs.explicit_dt(rates(), 0.8)
+    nsteps = 7
+    lam_end = final_adjoint(g.seg_off, g.n, 13, True)
+    seeds = np.random.default_rng(14).standard_normal((nsteps, 1, 5))
+    out = []
+    for tape_dom in (False, True):
+        sim = make_sim(g, precision, _lib.VG_KERNEL_RANK, True, False, tape_dom)
+        states, lam, grad = sweep(sim, g, x0, dt, nsteps, lam_end, seeds)
+        sim.set_fields(x0)
+        taped = torch.empty_like(states)
+        tot = torch.empty((nsteps, 1, 6), dtype=torch.float64, device="cuda")
+        sim.step_record(nsteps, dt, taped, tot)
+        torch.cuda.synchronize()
+        assert torch.equal(taped, states)
+        out.append((lam, grad, states[:, :4].clone(), tot, sim.fields.clone()))
+        del sim
+    for a, b in zip(out[0], out[1]):
+        assert torch.equal(a, b)
