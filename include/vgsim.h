@@ -445,7 +445,9 @@ int vg_store_state(vg_sim *h, void *x_d, int x_precision, void *stream);
  * the reverse sweep needs to states_d ([nsteps][5][n], field type):
  * states[0] = x^k0 and states[j] = T(x^(k0+j-1)) for j >= 1 (the state
  * after the transformation half of step k0+j-1).  The bound fields are left
- * at x^k0 (the call only reads them).
+ * at x^k0 (the call only reads them).  With the adjoint option
+ * VG_ADJ_TAPE_DOM (vg_set_adjoint_options) the CO2 row of states[j], j >= 1,
+ * holds the DOM of x^(k0+j) instead of CO2.
  *
  * vg_adjoint runs the reverse sweep over those nsteps steps.
  *   lambda_d [5][n] (field type): in dL/dx^(k0+nsteps), out dL/dx^k0.

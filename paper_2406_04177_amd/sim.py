@@ -246,13 +246,11 @@ class Simulation:
         and the reverse sweep reads it there (bit-identical results; such
         recorded states hold no CO2).  An option given as None keeps its
         current value."""
-        if skip_static_d is not None:
-            self._adj_skip = bool(skip_static_d)
-        if tape_dom is not None:
-            self._adj_tape_dom = bool(tape_dom)
-        flags = ((_lib.VG_ADJ_SKIP_STATIC_D if self._adj_skip else 0)
-                 | (_lib.VG_ADJ_TAPE_DOM if self._adj_tape_dom else 0))
+        skip = self._adj_skip if skip_static_d is None else bool(skip_static_d)
+        tape = self._adj_tape_dom if tape_dom is None else bool(tape_dom)
+        flags = (_lib.VG_ADJ_SKIP_STATIC_D if skip else 0) | (_lib.VG_ADJ_TAPE_DOM if tape else 0)
         _lib.check(self.L.vg_set_adjoint_options(self.h, flags), "vg_set_adjoint_options")
+        self._adj_skip, self._adj_tape_dom = skip, tape
 
     @property
     def adjoint_options(self) -> dict:
