@@ -991,7 +991,7 @@ def main(argv=None):
         sima.set_adjoint_options(tape_dom=True)
         sima.set_fields(x0)
         KA = 20
-        states = torch.empty((KA, 5, n), dtype=torch.float32, device="cuda")
+        states = torch.empty((KA, sima.tape_rows, n), dtype=torch.float32, device="cuda")
         seeds = torch.zeros((KA, g.nseg, 5), dtype=torch.float64, device="cuda")
         seeds[:, :, 4] = 1.0
         lam = torch.zeros((5, n), dtype=torch.float32, device="cuda")

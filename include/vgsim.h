@@ -442,12 +442,14 @@ int vg_store_state(vg_sim *h, void *x_d, int x_precision, void *stream);
 
 /* ---- discrete adjoint of the explicit loop (paper order only) -----------
  * vg_record advances nsteps steps from the bound state x^k0 and writes what
- * the reverse sweep needs to states_d ([nsteps][5][n], field type):
- * states[0] = x^k0 and states[j] = T(x^(k0+j-1)) for j >= 1 (the state
- * after the transformation half of step k0+j-1).  The bound fields are left
- * at x^k0 (the call only reads them).  With the adjoint option
- * VG_ADJ_TAPE_DOM (vg_set_adjoint_options) the CO2 row of states[j], j >= 1,
- * holds the DOM of x^(k0+j) instead of CO2.
+ * the reverse sweep needs to states_d ([nsteps][rows][n], field type, rows =
+ * vg_tape_rows(h)).  Five rows: states[0] = x^k0 and states[j] = T(x^(k0+j-1))
+ * for j >= 1 (the state after the transformation half of step k0+j-1).
+ * Four rows (the adjoint option VG_ADJ_TAPE_DOM): MB, DOM, SOM, P4 of those
+ * states, except that the DOM row of states[j], j >= 1, holds the DOM of
+ * x^(k0+j) (after the diffusion half), and no CO2.  The bound fields are left
+ * at x^k0 (the call only reads them); the adjoint's own second lambda buffer
+ * is overwritten.
  *
  * vg_adjoint runs the reverse sweep over those nsteps steps.
  *   lambda_d [5][n] (field type): in dL/dx^(k0+nsteps), out dL/dx^k0.
@@ -461,6 +463,10 @@ int vg_store_state(vg_sim *h, void *x_d, int x_precision, void *stream);
  * VG_EINVAL for params.sequential = 1 (the reverse sweep differentiates
  * Algorithm 1) and for the diffuse-first step order. */
 int vg_record(vg_sim *h, int64_t nsteps, double dt, void *states_d, void *stream);
+/* Rows per recorded state of vg_record, vg_step_record and vg_adjoint under
+ * the handle's current adjoint options: 5, or 4 with VG_ADJ_TAPE_DOM (when
+ * not every pool diffuses); VG_EINVAL for a NULL handle. */
+int vg_tape_rows(const vg_sim *h);
 /* The forward run and its record in one: advances the bound state nsteps
  * steps, writes to states_d what vg_record writes for the same start, and
  * logs the totals after every step to totals_log_d[nsteps][nseg][6] (as
@@ -483,17 +489,18 @@ int vg_seed_lambda(vg_sim *h, const double *seed_d, void *lambda_d, int zero, vo
  * neighbour gathers of each of their adjoints per voxel and step.  The other
  * gradients and lambda are unchanged.  Default: every dL/dD_s computed.
  * VG_ADJ_TAPE_DOM (ignored with mobile_all): vg_record and vg_step_record
- * keep, for every recorded state states[j] with j >= 1, the DOM after the
- * diffusion half of the step that follows it (the x^(k0+j) of the paper's
- * order) in the CO2 row of states[j], in place of CO2 (4 more bytes written
- * per voxel and recorded step); vg_adjoint then reads each step's x^k
- * directly instead of gathering the stored DOM at six neighbours to form it
- * (Sec. II.B.3a Scheme 1 applied in the forward, not again in the reverse).
- * lambda and the gradient are bit-identical to the recording without it.
- * The flag must be the same for the recording and its vg_adjoint; such
- * states hold no CO2, so vg_adjoint returns VG_EINVAL for them when dL/dD_CO2
- * is asked for (no VG_ADJ_SKIP_STATIC_D) with a CO2 adjoint that varies
- * within a volume. */
+ * write four rows per recorded state (see vg_record): MB, SOM and P4 of the
+ * state and, for j >= 1, the DOM after the diffusion half of the step that
+ * follows it (the x^(k0+j) of the paper's order), which the recording pass
+ * has at hand; the transformed DOM and CO2 that the recording needs to go on
+ * stay in the adjoint's second lambda buffer.  16 B per FP32 voxel and step
+ * instead of 20, and vg_adjoint reads each step's x^k directly instead of
+ * gathering the stored DOM at six neighbours to form it (Sec. II.B.3a
+ * Scheme 1 applied in the forward, not again in the reverse).  lambda and
+ * the gradient are bit-identical to the five-row recording.  The flag must
+ * be the same for the recording and its vg_adjoint; such states hold no CO2,
+ * so vg_adjoint returns VG_EINVAL for them when dL/dD_CO2 is asked for (no
+ * VG_ADJ_SKIP_STATIC_D) with a CO2 adjoint that varies within a volume. */
 #define VG_ADJ_SKIP_STATIC_D 1u
 #define VG_ADJ_TAPE_DOM      2u
 int vg_set_adjoint_options(vg_sim *h, unsigned flags);

@@ -34,7 +34,7 @@ EXPORTS = ("vg_strerror", "vg_last_error", "vg_version", "vg_rank_bytes", "vg_co
            "vg_set_kernel", "vg_get_kernel", "vg_set_launch_options", "vg_set_adjoint_options", "vg_set_params", "vg_set_regions", "vg_alt_elems", "vg_workspace_bytes", "vg_init_state",
            "vg_step_explicit", "vg_step_subcycled", "vg_solve_implicit_step", "vg_set_preconditioner",
            "vg_mg_levels", "vg_precondition", "vg_mass_totals", "vg_record", "vg_adjoint",
-           "vg_seed_lambda", "vg_load_state", "vg_store_state", "vg_step_record")
+           "vg_seed_lambda", "vg_load_state", "vg_store_state", "vg_step_record", "vg_tape_rows")
 
 
 class VgError(RuntimeError):
@@ -113,6 +113,7 @@ def load():
             "vg_mass_totals": (I, [P, P, P]),
             "vg_record": (I, [P, I64, D, P, P]),
             "vg_step_record": (I, [P, I64, D, P, P, U, P]),
+            "vg_tape_rows": (I, [P]),
             "vg_adjoint": (I, [P, I64, D, P, P, P, P, P]),
             "vg_seed_lambda": (I, [P, P, P, I, P]),
             "vg_load_state": (I, [P, P, I, P]),

@@ -32,6 +32,7 @@ import torch
 from .inputs import ModelParams
 
 NTHETA = 20
+VG_POOLS = 5
 THETA_NAMES = ("D_MB", "D_DOM", "D_SOM", "D_P4", "D_CO2", "v_dom", "k_dom", "rho", "mu", "beta",
                "v_som", "v_p4") + tuple("c%d" % r for r in range(8))
 
@@ -88,13 +89,15 @@ class _TotalsFn(torch.autograd.Function):
         keep = any(ctx.needs_input_grad[:2])      # no checkpoints when no gradient is wanted
         segs = [(k0, min(K, nsteps - k0)) for k0 in range(0, nsteps, K)]
         # the last segments whose states fit the budget are recorded on the way
-        per_step = 5 * sim.graph.n * torch.empty((), dtype=sim.dtype).element_size()
+        rows = sim.tape_rows
+        per_step = rows * sim.graph.n * torch.empty((), dtype=sim.dtype).element_size()
         if tape_bytes is None:
             # free device memory, and what torch's allocator holds unused
             # (e.g. the states buffer of an earlier backward)
             free = 0 if dev.type != "cuda" else (torch.cuda.mem_get_info(dev)[0] + torch.cuda.memory_reserved(dev)
                                                  - torch.cuda.memory_allocated(dev))
-            tape_bytes = default_tape_bytes(free, min(K, nsteps) * per_step, nsteps * per_step, per_step, len(segs))
+            field = VG_POOLS * sim.graph.n * torch.empty((), dtype=sim.dtype).element_size()
+            tape_bytes = default_tape_bytes(free, min(K, nsteps) * per_step, nsteps * per_step, field, len(segs))
         taped, budget = set(), int(tape_bytes) if keep else 0
         for k0, k in reversed(segs):
             if k * per_step > budget:
@@ -103,7 +106,7 @@ class _TotalsFn(torch.autograd.Function):
             taped.add(k0)
         for k0, k in segs:
             if k0 in taped:
-                tape = torch.empty((k, 5, sim.graph.n), dtype=sim.dtype, device=dev)
+                tape = torch.empty((k, rows, sim.graph.n), dtype=sim.dtype, device=dev)
                 sim.step_record(k, dt, tape, tot[k0 + 1:k0 + 1 + k])
                 ckpts.append((k0, k, tape))
             else:
@@ -142,7 +145,7 @@ class _TotalsFn(torch.autograd.Function):
         sim.seed_lambda(seeds[ctx.nsteps], lam, zero=True)
         grad = torch.zeros(NTHETA, dtype=torch.float64, device=dev)
         kmax = max((k for k0, k, _ in ctx.ckpts if k0 not in ctx.taped), default=0)
-        states = torch.empty((kmax, 5, n), dtype=sim.dtype, device=dev) if kmax else None
+        states = torch.empty((kmax, sim.tape_rows, n), dtype=sim.dtype, device=dev) if kmax else None
         for idx in range(len(ctx.ckpts) - 1, -1, -1):
             k0, k, ck = ctx.ckpts[idx]
             if k0 in ctx.taped:

@@ -134,7 +134,7 @@ struct AdjBufs {
     const uint16_t *rcode = nullptr;
     PackedNbr pk;                // packed neighbour sources (when built)
     const R *st = nullptr;       // stored state of this step, pool s at st + s*n
-    int dom_row = 1;             // the row read as DOM (4: the diffused DOM kept in the CO2 row)
+    int co2_row = 4;             // the row of CO2 (a kept-DOM recording has none: never read then)
     const R *lin = nullptr;      // lambda^(k+1)
     R *lout = nullptr;           // lambda^k
     const double *seed = nullptr;   // [nseg][5] for this step
@@ -266,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_adj(AdjBufs<R> A, Coef<R> C, Pieces 
     R *lout[VG_NPOOL];
 #pragma unroll
     for (int s = 0; s < VG_NPOOL; s++) {
-        st[s] = A.st + (int64_t)(s == 1 ? A.dom_row : s) * n;
+        st[s] = A.st + (int64_t)(s == 4 ? A.co2_row : s) * n;
         lin[s] = A.lin + (int64_t)s * n;
         lout[s] = A.lout + (int64_t)s * n;
     }
@@ -601,6 +601,42 @@ bool tape_keeps_dom(const vg_sim *h) {
     return (h->adj_flags & VG_ADJ_TAPE_DOM) && !h->mobile_all;
 }
 
+int tape_rows(const vg_sim *h) {
+    return tape_keeps_dom(h) ? 4 : VG_NPOOL;
+}
+
+// A kept-DOM recording holds per state MB, DOM, SOM and P4 (state 0: x^k0's;
+// state j >= 1: T(x^(k0+j-1))'s MB, SOM, P4 and x^(k0+j)'s DOM).  The
+// transformed DOM and the CO2 of the state a recording pass works on live
+// in two ping-pong row pairs of the adjoint's second lambda buffer (idle
+// while recording), state j's in pair j & 1; state 0's CO2 is the bound
+// fields'.
+void tape_pass_bufs(const vg_sim *h, void *states, int64_t j, const void *src[VG_NPOOL], void *dst[VG_NPOOL],
+                    void **xdom) {
+    const int64_t n = h->n;
+    const size_t esz = h->elem();
+    char *st = (char *)states;
+    const int rows = tape_rows(h);
+    auto at_row = [&](int64_t jj, int r) { return (void *)(st + ((size_t)jj * rows + r) * n * esz); };
+    for (int p = 0; p < VG_NPOOL; p++) {
+        src[p] = p < rows ? at_row(j, p) : nullptr;
+        dst[p] = p < rows ? at_row(j + 1, p) : nullptr;
+    }
+    *xdom = nullptr;
+    if (rows == VG_NPOOL) return;
+    char *side = (char *)h->lam_alt;
+    auto side_row = [&](int64_t jj, int r) { return (void *)(side + ((size_t)(jj & 1) * 2 + r) * n * esz); };
+    if (j > 0) {
+        src[1] = side_row(j, 0);
+        src[4] = side_row(j, 1);
+        *xdom = at_row(j, 1);
+    } else {
+        src[4] = h->fields + 4 * n * esz;
+    }
+    dst[1] = side_row(j + 1, 0);
+    dst[4] = side_row(j + 1, 1);
+}
+
 namespace {
 
 template <typename R>
@@ -649,12 +685,14 @@ int adjoint_sweep(vg_sim *h, int64_t nsteps, double dt, const void *states, cons
                   "each volume, or VG_ADJ_SKIP_STATIC_D");
         return VG_EINVAL;
     }
+    const int rows = tape_rows(h);
     for (int64_t jstep = nsteps - 1; jstep >= 0; jstep--) {
         AdjBufs<R> A;
         A.nbr = h->nbr;
         A.rcode = h->rcode;
         A.pk = packed_of(h);
-        A.st = (const R *)states + jstep * VG_NPOOL * n;
+        A.st = (const R *)states + jstep * rows * n;
+        A.co2_row = rows == VG_NPOOL ? 4 : 3;
         A.lin = bufs[cur];
         A.lout = bufs[cur ^ 1];
         A.seed = seeds + jstep * (int64_t)h->nseg * VG_NPOOL;
@@ -665,7 +703,6 @@ int adjoint_sweep(vg_sim *h, int64_t nsteps, double dt, const void *states, cons
         A.n = n;
         A.ntiles = h->ntiles;
         const bool fx = jstep == 0 || xd;
-        A.dom_row = xd && jstep > 0 ? 4 : 1;
         if (h->mobile_all) rc = reg ? launch_adj_step<R, 2, true>(h, fx, A, C, s) : launch_adj_step<R, 2, false>(h, fx, A, C, s);
         else rc = reg ? launch_adj_step<R, 1, true>(h, fx, A, C, s) : launch_adj_step<R, 1, false>(h, fx, A, C, s);
         if (rc) return rc;
@@ -693,36 +730,25 @@ int adjoint_sweep(vg_sim *h, int64_t nsteps, double dt, const void *states, cons
 template <typename R>
 int record(vg_sim *h, int64_t nsteps, double dt, void *states, hipStream_t s) {
     const int64_t n = h->n;
-    R *st = (R *)states;
     int rc;
-    // states[0] = x^k0 (the bound fields)
-    if ((rc = hip_status(hipMemcpyAsync(st, h->fields, sizeof(R) * VG_NPOOL * (size_t)n, hipMemcpyDeviceToDevice, s),
-                         "record copy"))) return rc;
-    const bool xd = tape_keeps_dom(h);
+    // states[0] = x^k0 (the bound fields; a kept-DOM recording takes their
+    // first four rows)
+    if ((rc = hip_status(hipMemcpyAsync(states, h->fields, sizeof(R) * tape_rows(h) * (size_t)n,
+                                        hipMemcpyDeviceToDevice, s), "record copy"))) return rc;
+    const void *src[VG_NPOOL];
+    void *dst[VG_NPOOL];
+    void *xdom;
     for (int64_t jstep = 1; jstep < nsteps; jstep++) {
-        const void *src[VG_NPOOL];
-        void *dst[VG_NPOOL];
-        for (int p = 0; p < VG_NPOOL; p++) {
-            src[p] = st + ((jstep - 1) * VG_NPOOL + p) * n;
-            dst[p] = st + (jstep * VG_NPOOL + p) * n;
-        }
-        // states[1] = T(x^k0); states[j] = T(D(states[j-1])) afterwards; with
-        // the diffused DOM kept, D(states[j-1])'s DOM goes into the CO2 row
-        // of states[j-1] (j >= 2: read there before it is overwritten)
-        void *xdom = xd && jstep >= 2 ? st + ((jstep - 1) * VG_NPOOL + 4) * n : nullptr;
-        rc = launch_pass_bufs(h, jstep == 1 ? MODE_T : MODE_DT, TOT_NONE, dt, src, dst, s, xdom);
-        if (rc) return rc;
+        // states[1] = T(x^k0); states[j] = T(D(states[j-1])) afterwards; a
+        // kept-DOM recording writes D(states[j-1])'s DOM into states[j-1]
+        tape_pass_bufs(h, states, jstep - 1, src, dst, &xdom);
+        if ((rc = launch_pass_bufs(h, jstep == 1 ? MODE_T : MODE_DT, TOT_NONE, dt, src, dst, s, xdom))) return rc;
     }
-    if (xd && nsteps >= 2) {
-        // the last state's diffused DOM: a diffusion pass whose DOM output is
-        // that state's CO2 row
-        const void *src[VG_NPOOL];
-        void *dst[VG_NPOOL];
-        for (int p = 0; p < VG_NPOOL; p++) {
-            src[p] = st + ((nsteps - 1) * VG_NPOOL + p) * n;
-            dst[p] = (void *)src[p];
-        }
-        dst[1] = st + ((nsteps - 1) * VG_NPOOL + 4) * n;
+    if (tape_keeps_dom(h) && nsteps >= 2) {
+        // the last state's diffused DOM: a diffusion pass (it writes DOM only)
+        tape_pass_bufs(h, states, nsteps - 1, src, dst, &xdom);
+        for (int p = 0; p < VG_NPOOL; p++) dst[p] = (void *)src[p];
+        dst[1] = xdom;
         if ((rc = launch_pass_bufs(h, MODE_D, TOT_NONE, dt, src, dst, s))) return rc;
     }
     return VG_OK;

@@ -752,6 +752,11 @@ extern "C" int vg_record(vg_sim *h, int64_t nsteps, double dt, void *states_d, v
     return launch_record(h, nsteps, dt, states_d, (hipStream_t)stream);
 }
 
+extern "C" int vg_tape_rows(const vg_sim *h) {
+    if (!h) { set_error("handle is NULL"); return VG_EINVAL; }
+    return tape_rows(h);
+}
+
 extern "C" int vg_step_record(vg_sim *h, int64_t nsteps, double dt, void *states_d, double *totals_log_d,
                               unsigned flags, void *stream) {
     int rc = need_bound(h);
@@ -771,8 +776,6 @@ extern "C" int vg_step_record(vg_sim *h, int64_t nsteps, double dt, void *states
     const size_t row = (size_t)h->nseg * 6;
     const int64_t n = h->n;
     const size_t esz = h->elem();
-    char *st = (char *)states_d;
-    auto state = [&](int64_t j, int p) { return (void *)(st + ((size_t)j * VG_NPOOL + p) * n * esz); };
     // states[0] = x^k0, states[j] = T(D(states[j-1])) (T alone for j = 1);
     // the fused pass j >= 2 sees x^(k0+j-1) between its halves: row j-2
     if ((rc = launch_record(h, 1, dt, states_d, s))) return rc;
@@ -786,33 +789,24 @@ extern "C" int vg_step_record(vg_sim *h, int64_t nsteps, double dt, void *states
         return rc2;
     };
     auto logged = [&]() -> int { return ++h->part_slot < h->tot_batch ? VG_OK : flush(); };
-    // with the diffused DOM kept, each fused pass writes D(states[j-1])'s DOM
-    // into the CO2 row of states[j-1] (as vg_record does)
-    const bool xd = tape_keeps_dom(h);
+    // the passes of vg_record (with the diffused DOM kept, each fused pass
+    // writes D(states[j-1])'s DOM into states[j-1])
+    const void *src[VG_NPOOL];
+    void *dst[VG_NPOOL];
+    void *xdom;
     for (int64_t j = 1; j < nsteps; j++) {
-        const void *src[VG_NPOOL];
-        void *dst[VG_NPOOL];
-        for (int p = 0; p < VG_NPOOL; p++) {
-            src[p] = state(j - 1, p);
-            dst[p] = state(j, p);
-        }
-        if ((rc = launch_pass_bufs(h, j == 1 ? MODE_T : MODE_DT, j == 1 ? TOT_NONE : TOT_MID, dt, src, dst, s,
-                                   xd && j >= 2 ? state(j - 1, 4) : nullptr)))
+        tape_pass_bufs(h, states_d, j - 1, src, dst, &xdom);
+        if ((rc = launch_pass_bufs(h, j == 1 ? MODE_T : MODE_DT, j == 1 ? TOT_NONE : TOT_MID, dt, src, dst, s, xdom)))
             return rc;
         if (j >= 2 && (rc = logged())) return rc;
     }
     // the last two steps into the bound fields (canonical between calls):
     // T(D(states[nsteps-1])) (T alone when nsteps = 1), then D
     {
-        const void *src[VG_NPOOL];
-        void *dst[VG_NPOOL];
-        for (int p = 0; p < VG_NPOOL; p++) {
-            src[p] = state(nsteps - 1, p);
-            dst[p] = h->fields + (size_t)p * n * esz;
-        }
+        tape_pass_bufs(h, states_d, nsteps - 1, src, dst, &xdom);
+        for (int p = 0; p < VG_NPOOL; p++) dst[p] = h->fields + (size_t)p * n * esz;
         const bool one = nsteps == 1;
-        if ((rc = launch_pass_bufs(h, one ? MODE_T : MODE_DT, one ? TOT_NONE : TOT_MID, dt, src, dst, s,
-                                   xd && !one ? state(nsteps - 1, 4) : nullptr)))
+        if ((rc = launch_pass_bufs(h, one ? MODE_T : MODE_DT, one ? TOT_NONE : TOT_MID, dt, src, dst, s, xdom)))
             return rc;
         if (!one && (rc = logged())) return rc;
     }

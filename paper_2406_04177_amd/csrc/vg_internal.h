@@ -598,7 +598,13 @@ bool use_offsets(const vg_sim *h);
 bool use_relative(const vg_sim *h);
 bool band_geometry(const vg_sim *h);   // the graph and features allow the band kernel
 bool use_band(const vg_sim *h);        // the next pass pairs run on the band kernel
-bool tape_keeps_dom(const vg_sim *h);  // recordings keep each state's diffused DOM in its CO2 row
+bool tape_keeps_dom(const vg_sim *h);  // recordings keep each state's diffused DOM (VG_ADJ_TAPE_DOM)
+int tape_rows(const vg_sim *h);        // rows per recorded state: 4 with the kept DOM, else 5
+// The source pools of a recording pass from recorded state j, the
+// destination pools of state j + 1, and where state j's diffused DOM goes
+// (null without the kept DOM or for j = 0).
+void tape_pass_bufs(const vg_sim *h, void *states, int64_t j, const void *src[VG_NPOOL], void *dst[VG_NPOOL],
+                    void **xdom);
 int build_band(vg_sim *h, hipStream_t s);
 int launch_band_quad(vg_sim *h, double dt, hipStream_t s);
 PackedNbr packed_of(const vg_sim *h);

@@ -218,34 +218,48 @@ class Simulation:
         return out
 
     # ------------------------------------------------------------------ adjoint
+    @property
+    def tape_rows(self) -> int:
+        """Rows per recorded state (5, or 4 with the kept DOM)."""
+        return _lib.check(self.L.vg_tape_rows(self.h), "vg_tape_rows")
+
+    def _check_states(self, nsteps: int, states: torch.Tensor):
+        rows = self.tape_rows
+        if states.dtype != self.dtype or not states.is_contiguous() or \
+                states.numel() < int(nsteps) * rows * self.graph.n:
+            raise ValueError("states must be a contiguous [nsteps, %d, n] tensor of the field type" % rows)
+
     def record(self, nsteps: int, dt: float, states: torch.Tensor):
+        """Record nsteps steps from the bound fields into states
+        ([nsteps, tape_rows, n], field type) for adjoint()."""
+        self._check_states(nsteps, states)
         _lib.check(self.L.vg_record(self.h, int(nsteps), float(dt), states.data_ptr(), self._sp()), "vg_record")
 
     def step_record(self, nsteps: int, dt: float, states: torch.Tensor, totals_out: torch.Tensor,
                     force: bool = False):
-        """Advance nsteps steps, recording the adjoint's states ([nsteps, 5, n]
-        field type, as record()) and the totals after every step into
-        totals_out ([nsteps, nseg, 6] FP64 on the device)."""
+        """Advance nsteps steps, recording the adjoint's states ([nsteps,
+        tape_rows, n] field type, as record()) and the totals after every
+        step into totals_out ([nsteps, nseg, 6] FP64 on the device)."""
         if totals_out.dtype != torch.float64 or not totals_out.is_contiguous() or \
                 totals_out.numel() < nsteps * self.nseg * 6:
             raise ValueError("totals_out must be a contiguous float64 tensor of nsteps * nseg * 6 entries")
-        if states.dtype != self.dtype or not states.is_contiguous() or states.numel() < nsteps * 5 * self.graph.n:
-            raise ValueError("states must be a contiguous [nsteps, 5, n] tensor of the field type")
+        self._check_states(nsteps, states)
         _lib.check(self.L.vg_step_record(self.h, int(nsteps), float(dt), states.data_ptr(), totals_out.data_ptr(),
                                          _lib.VG_FORCE if force else 0, self._sp()), "vg_step_record")
 
     def adjoint(self, nsteps: int, dt: float, states: torch.Tensor, seeds: torch.Tensor, lam: torch.Tensor,
                 grad: torch.Tensor):
+        self._check_states(nsteps, states)
         _lib.check(self.L.vg_adjoint(self.h, int(nsteps), float(dt), states.data_ptr(), seeds.data_ptr(),
                                      lam.data_ptr(), grad.data_ptr(), self._sp()), "vg_adjoint")
 
     def set_adjoint_options(self, skip_static_d=None, tape_dom=None):
         """skip_static_d: do not compute dL/dD_s for the pools that do not
         diffuse (their gradient entries come back NaN); faster reverse sweep.
-        tape_dom: recordings keep each state's diffused DOM in its CO2 row
-        and the reverse sweep reads it there (bit-identical results; such
-        recorded states hold no CO2).  An option given as None keeps its
-        current value."""
+        tape_dom: recordings keep each state's diffused DOM, four rows per
+        state instead of five (see tape_rows), and the reverse sweep reads it
+        (bit-identical results; such recorded states hold no CO2).  An option
+        given as None keeps its current value."""
         skip = self._adj_skip if skip_static_d is None else bool(skip_static_d)
         tape = self._adj_tape_dom if tape_dom is None else bool(tape_dom)
         flags = (_lib.VG_ADJ_SKIP_STATIC_D if skip else 0) | (_lib.VG_ADJ_TAPE_DOM if tape else 0)

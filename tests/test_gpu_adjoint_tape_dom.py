@@ -1,10 +1,11 @@
-"""Recordings that keep each step's diffused DOM (adjoint option tape_dom):
-the reverse sweep reads x^k directly instead of diffusing the stored state
-again.  Lambda, the gradient, the totals and the stepped fields must be
-bit-identical to the recording without it, for every neighbour source, both
+"""Recordings that keep each step's diffused DOM (adjoint option tape_dom:
+four rows per state, MB, DOM, SOM, P4, with the DOM of x^k after the first
+state): the reverse sweep reads x^k directly instead of diffusing the stored
+state again.  Lambda, the gradient, the totals and the stepped fields must be
+bit-identical to the five-row recording, for every neighbour source, both
 field types, with and without region weights, both dL/dD options, one to
-several steps, vg_record and vg_step_record; the kept DOM itself is checked
-against the oracle's states."""
+several steps, vg_record and vg_step_record; the kept rows themselves are
+checked against the oracle's states."""
 import numpy as np
 import pytest
 import torch
@@ -15,6 +16,7 @@ from paper_2406_04177_amd import _lib, inputs
 pytestmark = pytest.mark.gpu
 
 KERNELS = [_lib.VG_KERNEL_TABLE, _lib.VG_KERNEL_OFFSET, _lib.VG_KERNEL_RELATIVE]
+STATIC = [0, 2, 3]   # MB, SOM, P4: the rows both recordings hold alike
 KERNEL_IDS = ["table", "offset", "relative"]
 
 
@@ -48,7 +50,7 @@ def make_sim(g, precision, kernel, regions, skip, tape_dom, mobile_all=None):
 def sweep(sim, g, x0, dt, nsteps, lam_end, seeds):
     """vg_record then vg_adjoint from x0; returns (states, lambda^0, grad)."""
     sim.set_fields(x0)
-    states = torch.empty((nsteps, 5, g.n), dtype=x0.dtype, device="cuda")
+    states = torch.empty((nsteps, sim.tape_rows, g.n), dtype=x0.dtype, device="cuda")
     sim.record(nsteps, dt, states)
     lam = torch.as_tensor(lam_end, device="cuda").to(x0.dtype).contiguous()
     grad = torch.zeros(20, dtype=torch.float64, device="cuda")
@@ -77,11 +79,13 @@ def test_sweep_bit_identical(kernel, precision, regions, skip, nsteps):
         out.append(sweep(sim, g, x0, dt, nsteps, lam_end, seeds))
         del sim
     (s0, l0, g0), (s1, l1, g1) = out
+    assert s0.shape[1] == 5 and s1.shape[1] == 4
     assert torch.equal(l1, l0)
     assert torch.equal(torch.nan_to_num(g1, nan=7.0), torch.nan_to_num(g0, nan=7.0))
-    # every row but the CO2 row of the states after the first is unchanged
-    assert torch.equal(s1[:, :4], s0[:, :4])
-    assert torch.equal(s1[0], s0[0])
+    # MB, SOM and P4 of every state and the first state's DOM as recorded
+    # without the kept DOM
+    assert torch.equal(s1[:, STATIC], s0[:, STATIC])
+    assert torch.equal(s1[0, 1], s0[0, 1])
 
 
 @pytest.mark.parametrize("precision", ["f32", "f64"])
@@ -109,8 +113,9 @@ def test_varying_co2_adjoint(precision):
 
 
 def test_kept_dom_equals_oracle_states():
-    """FP64: the CO2 row of recorded state j >= 1 holds x^j's DOM (the
-    oracle's state after j steps), the other rows T(x^(j-1))."""
+    """FP64: the DOM row of recorded state j >= 1 holds x^j's DOM (the
+    oracle's state after j steps), the MB, SOM and P4 rows T(x^(j-1))'s;
+    state 0 is x^0 without CO2."""
     from paper_2406_04177_amd.graph import Graph
     masks, specs = batch(seed=41)
     p = rates()
@@ -120,15 +125,17 @@ def test_kept_dom_equals_oracle_states():
     og = orc.build_batch(masks)
     sim = make_sim(g, "f64", _lib.VG_KERNEL_AUTO, False, False, True)
     sim.set_fields(g.fields_from_specs(specs, torch.float64))
-    states = torch.empty((nsteps, 5, g.n), dtype=torch.float64, device="cuda")
+    assert sim.tape_rows == 4
+    states = torch.empty((nsteps, 4, g.n), dtype=torch.float64, device="cuda")
     sim.record(nsteps, dt, states)
     st = states.cpu().numpy()
     ref = orc.run_states(p, dt, og, orc.fields_from_spec(og, specs), nsteps)
+    np.testing.assert_array_equal(st[0], ref[0][:4])
     for j in range(1, nsteps):
         dom = ref[j][1]
-        np.testing.assert_allclose(st[j][4], dom, rtol=1e-12, atol=1e-14 * np.abs(dom).max())
+        np.testing.assert_allclose(st[j][1], dom, rtol=1e-12, atol=1e-14 * np.abs(dom).max())
         tj = orc.transform(p, dt, ref[j - 1])
-        np.testing.assert_allclose(st[j][:4], tj[:4], rtol=1e-12, atol=1e-14 * np.abs(tj).max())
+        np.testing.assert_allclose(st[j][STATIC], tj[STATIC], rtol=1e-12, atol=1e-14 * np.abs(tj).max())
 
 
 @pytest.mark.parametrize("k", [1, 2, 7])
@@ -151,7 +158,7 @@ def test_step_record_bit_identical(precision, k):
         sim.set_fields(x0)
         sim.step(3, dt)
         start = sim.fields.clone()
-        rec = torch.empty((k, 5, g.n), dtype=dtype, device="cuda")
+        rec = torch.empty((k, sim.tape_rows, g.n), dtype=dtype, device="cuda")
         sim.record(k, dt, rec)
         states = torch.empty_like(rec)
         tot = torch.empty((k, g.nseg, 6), dtype=torch.float64, device="cuda")
@@ -220,7 +227,25 @@ def test_rank_index_recording_bit_identical(brick, precision):
         sim.step_record(nsteps, dt, taped, tot)
         torch.cuda.synchronize()
         assert torch.equal(taped, states)
-        out.append((lam, grad, states[:, :4].clone(), tot, sim.fields.clone()))
+        out.append((lam, grad, states[:, STATIC].clone(), tot, sim.fields.clone()))
         del sim
     for a, b in zip(out[0], out[1]):
         assert torch.equal(a, b)
+
+
+def test_states_shape_checked():
+    """A states tensor with fewer rows per step than the recording writes is
+    refused before any launch; the kept-DOM recording takes four."""
+    from paper_2406_04177_amd.graph import Graph
+    masks, specs = batch(seed=91)
+    g = Graph.from_masks(masks)
+    sim = make_sim(g, "f32", _lib.VG_KERNEL_AUTO, False, False, False)
+    sim.set_fields(g.fields_from_specs(specs, torch.float32))
+    small = torch.empty((3, 4, g.n), dtype=torch.float32, device="cuda")
+    assert sim.tape_rows == 5
+    with pytest.raises(ValueError):
+        sim.record(3, inputs.explicit_dt(rates(), 0.8), small)
+    sim.set_adjoint_options(tape_dom=True)
+    assert sim.tape_rows == 4
+    sim.record(3, inputs.explicit_dt(rates(), 0.8), small)
+    torch.cuda.synchronize()
