@@ -409,3 +409,23 @@ def test_multigrid_feature_validation_and_workspace():
     assert L.vg_precondition(h1, 1.0, 0x1000, 0x2000, None) == _lib.VG_ESTATE   # nothing bound yet
     for h in (h0, h1):
         L.vg_destroy(h)
+
+
+def test_adjoint_options_and_tape_rows():
+    """Adjoint options: the two flags and their combination accepted, any
+    other bit refused; a kept-DOM recording has four rows per state, five
+    otherwise and whenever every pool diffuses (host side only)."""
+    L = _lib.load()
+    assert L.vg_tape_rows(None) == _lib.VG_EINVAL
+    assert L.vg_set_adjoint_options(None, 0) == _lib.VG_EINVAL
+    rc, h, _ = make_handle()
+    rc2, h2, _ = make_handle(mobile_all=1)
+    for flags in range(4):
+        assert L.vg_set_adjoint_options(h, flags) == 0
+        assert L.vg_tape_rows(h) == (4 if flags & _lib.VG_ADJ_TAPE_DOM else 5)
+        assert L.vg_set_adjoint_options(h2, flags) == 0
+        assert L.vg_tape_rows(h2) == 5
+    assert L.vg_set_adjoint_options(h, 4) == _lib.VG_EINVAL
+    assert L.vg_set_adjoint_options(h, 0x80000000) == _lib.VG_EINVAL
+    L.vg_destroy(h)
+    L.vg_destroy(h2)
