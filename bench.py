@@ -69,12 +69,12 @@ KERNEL_SOURCES = ("paper_2406_04177_amd/csrc/vg_step.hip", "paper_2406_04177_amd
                   "paper_2406_04177_amd/build.py")
 MEASURED_TRAFFIC = {
     # (kernel, size): (bytes per launch, sha256 of KERNEL_SOURCES); from
-    # profiles/k_band2_f32_512cube.md: FETCH_SIZE 592529.8 KiB x 2 +
-    # WRITE_SIZE 412405.8 KiB x 1 per launch (two fused passes), and
-    # profiles/k_step_c_f32c_512cube.md: FETCH_SIZE 479810.9 KiB x 2 +
-    # WRITE_SIZE 613851.4 KiB per launch (one pass, compensated FP32)
-    ("band", 512): (592529.8 * 1024 * 2 + 412405.8 * 1024, "c2a35f4d4b47ca3c0717fba316276412ced64a4b3c742dcb09853518a831dd3d"),
-    ("relative_f32c", 512): (479810.9 * 1024 * 2 + 613851.4 * 1024, "c2a35f4d4b47ca3c0717fba316276412ced64a4b3c742dcb09853518a831dd3d"),
+    # profiles/k_band2_f32_512cube.md: FETCH_SIZE 593521.3 KiB x 2 +
+    # WRITE_SIZE 412398.7 KiB x 1 per launch (two fused passes), and
+    # profiles/k_step_c_f32c_512cube.md: FETCH_SIZE 479815.7 KiB x 2 +
+    # WRITE_SIZE 614750.5 KiB per launch (one pass, compensated FP32)
+    ("band", 512): (593521.3 * 1024 * 2 + 412398.7 * 1024, "558eed4efc66093b68430acef6ff29365d48ed4de7e6e064e33e3305186388bf"),
+    ("relative_f32c", 512): (479815.7 * 1024 * 2 + 614750.5 * 1024, "558eed4efc66093b68430acef6ff29365d48ed4de7e6e064e33e3305186388bf"),
 }
 
 

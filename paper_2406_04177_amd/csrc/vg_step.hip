@@ -483,8 +483,14 @@ __global__ __launch_bounds__(kBlock) void k_step_off(StepBufs<R> B, Coef<R> C, P
         }
     }
     if constexpr (TOT != TOT_NONE) {
-        static_assert(V == kVPT, "totals are per tile of kTile voxels");
-        tile_totals(pc, tile, acc, part, lds);
+        // totals per reduction tile of kTile voxels: the thread's voxel v
+        // lies in tile tile * V + v (uniform over the block)
+        static_assert(kVPT == 1, "one voxel per thread and reduction tile");
+#pragma unroll
+        for (int v = 0; v < V; v++) {
+            const int64_t tv = tile * V + v;
+            if (tv * kTile < (int64_t)n) tile_totals(pc, tv, reinterpret_cast<const double(&)[1][VG_NPOOL]>(acc[v]), part, lds);
+        }
     }
 }
 
@@ -932,8 +938,8 @@ int launch_one(vg_sim *h, const StepBufs<R> &B, const Coef<R> &C, hipStream_t s)
         // the algorithm is a template argument of the packed-source pass
         // (Algorithm 2 instances only where a transformation runs)
         const bool seq = MODE == MODE_DT && C.seq;
-        if constexpr (MODE == MODE_D && TOT == TOT_NONE) {
-            // diffusion-only passes without totals move 12.5 B per voxel:
+        if constexpr (MODE == MODE_D) {
+            // diffusion-only passes move 12.5 B per voxel (28.5 with totals):
             // two voxels per thread keep more loads in flight (measured 6.5 %
             // faster sub-cycled runs; the fused pass is faster with one)
             constexpr int V2 = 2;
