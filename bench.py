@@ -73,8 +73,8 @@ MEASURED_TRAFFIC = {
     # WRITE_SIZE 412398.7 KiB x 1 per launch (two fused passes), and
     # profiles/k_step_c_f32c_512cube.md: FETCH_SIZE 479815.7 KiB x 2 +
     # WRITE_SIZE 614750.5 KiB per launch (one pass, compensated FP32)
-    ("band", 512): (593521.3 * 1024 * 2 + 412398.7 * 1024, "558eed4efc66093b68430acef6ff29365d48ed4de7e6e064e33e3305186388bf"),
-    ("relative_f32c", 512): (479815.7 * 1024 * 2 + 614750.5 * 1024, "558eed4efc66093b68430acef6ff29365d48ed4de7e6e064e33e3305186388bf"),
+    ("band", 512): (593521.3 * 1024 * 2 + 412398.7 * 1024, "69b7e38df9ad0daa574489029c012a67ae0251ed2b47373b68c9c967b88515e5"),
+    ("relative_f32c", 512): (479815.7 * 1024 * 2 + 614750.5 * 1024, "69b7e38df9ad0daa574489029c012a67ae0251ed2b47373b68c9c967b88515e5"),
 }
 
 

@@ -1532,8 +1532,7 @@ int launch_pass(vg_sim *h, int mode, int tot, double dt, hipStream_t s) {
 
 // A pass between explicit buffers (pool s read from src[s], written to
 // dst[s]); used by the adjoint's forward recording.  xdom: see StepBufs
-// (fused passes, only DOM diffusing; it may be src[4], read before it is
-// written by the same thread).
+// (fused passes, only DOM diffusing; a row the pass does not read).
 int launch_pass_bufs(vg_sim *h, int mode, int tot, double dt, const void *const src[VG_NPOOL],
                      void *const dst[VG_NPOOL], hipStream_t s, void *xdom) {
     if (h->n == 0) return VG_OK;
