@@ -226,8 +226,10 @@ class Simulation:
     def _check_states(self, nsteps: int, states: torch.Tensor):
         rows = self.tape_rows
         if states.dtype != self.dtype or not states.is_contiguous() or \
-                states.numel() < int(nsteps) * rows * self.graph.n:
-            raise ValueError("states must be a contiguous [nsteps, %d, n] tensor of the field type" % rows)
+                states.numel() < int(nsteps) * rows * self.graph.n or \
+                (states.dim() == 3 and states.shape[1:] != (rows, self.graph.n)):
+            raise ValueError("states must be a contiguous [nsteps, %d, n] tensor of the field type (the row count "
+                             "follows the adjoint option tape_dom)" % rows)
 
     def record(self, nsteps: int, dt: float, states: torch.Tensor):
         """Record nsteps steps from the bound fields into states

@@ -249,3 +249,7 @@ def test_states_shape_checked():
     assert sim.tape_rows == 4
     sim.record(3, inputs.explicit_dt(rates(), 0.8), small)
     torch.cuda.synchronize()
+    # a five-row recording swept under the four-row option (or the reverse)
+    five = torch.empty((3, 5, g.n), dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        sim.record(3, inputs.explicit_dt(rates(), 0.8), five)
